@@ -1,0 +1,178 @@
+"""FP64 CPU oracle for Frobenius inversion (arXiv 2208.01239).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never links, loads or calls it, and shares no code with it.
+
+Thin ctypes wrapper over ``liboracle.so`` (plain C, see ``frob_oracle.c``).
+Every routine takes real numpy arrays (the real and imaginary parts of the
+complex input) and returns new arrays; ``info`` follows the C return codes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+STAGE_A = 1000000
+STAGE_C = 2000000
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    src = os.path.join(_HERE, "frob_oracle.c")
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i, d = ctypes.c_int, ctypes.c_double
+    lib.orc_cinv_lu.argtypes = [i, _dp, _dp, _dp, _dp, _ip, _dp]
+    lib.orc_cinv_gj.argtypes = [i, _dp, _dp, _dp, _dp]
+    lib.orc_frob_lu.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_frob_shift.argtypes = [i, _dp, _dp, d, _dp, _dp, _dp]
+    lib.orc_frob_chol.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_cinv_chol.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_frob_solve.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_adjoint.argtypes = [i, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_adjoint.restype = None
+    lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_cmatmul.restype = None
+    lib.orc_num_threads.argtypes = []
+    for name in ("orc_cinv_lu", "orc_cinv_gj", "orc_frob_lu", "orc_frob_shift", "orc_frob_chol",
+                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _c(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _out(*shape):
+    a = np.zeros(shape, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def cinv_lu(Mr, Mi):
+    """Algorithm 4 in complex arithmetic.  Returns (Xr, Xi, info, piv, flops)."""
+    lib = _load()
+    n = Mr.shape[0]
+    (Mr, pr), (Mi, pi) = _c(Mr), _c(Mi)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    piv = np.zeros(n, dtype=np.int32)
+    fl = ctypes.c_double(0)
+    info = lib.orc_cinv_lu(n, pr, pi, xr, xi, piv.ctypes.data_as(_ip), ctypes.byref(fl))
+    return Xr, Xi, info, piv, fl.value
+
+
+def cinv_gj(Mr, Mi):
+    """Gauss-Jordan on [M | I].  Returns (Xr, Xi, info)."""
+    lib = _load()
+    n = Mr.shape[0]
+    (Mr, pr), (Mi, pi) = _c(Mr), _c(Mi)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    info = lib.orc_cinv_gj(n, pr, pi, xr, xi)
+    return Xr, Xi, info
+
+
+def frob_lu(A, B):
+    """Algorithm 5.  Returns (Xr, Xi, info, flops)."""
+    lib = _load()
+    n = A.shape[0]
+    (A, pa), (B, pb) = _c(A), _c(B)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    fl = ctypes.c_double(0)
+    info = lib.orc_frob_lu(n, pa, pb, xr, xi, ctypes.byref(fl))
+    return Xr, Xi, info, fl.value
+
+
+def frob_shift(A, B, mu):
+    """Algorithm 6 with the given shift mu.  Returns (Xr, Xi, info, flops)."""
+    lib = _load()
+    n = A.shape[0]
+    (A, pa), (B, pb) = _c(A), _c(B)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    fl = ctypes.c_double(0)
+    info = lib.orc_frob_shift(n, pa, pb, float(mu), xr, xi, ctypes.byref(fl))
+    return Xr, Xi, info, fl.value
+
+
+def frob_chol(A, B):
+    """Algorithm 7 (HPD input).  Returns (Xr, Xi, info, flops)."""
+    lib = _load()
+    n = A.shape[0]
+    (A, pa), (B, pb) = _c(A), _c(B)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    fl = ctypes.c_double(0)
+    info = lib.orc_frob_chol(n, pa, pb, xr, xi, ctypes.byref(fl))
+    return Xr, Xi, info, fl.value
+
+
+def cinv_chol(Mr, Mi):
+    """Algorithm 8 in complex arithmetic.  Returns (Xr, Xi, info, flops)."""
+    lib = _load()
+    n = Mr.shape[0]
+    (Mr, pr), (Mi, pi) = _c(Mr), _c(Mi)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    fl = ctypes.c_double(0)
+    info = lib.orc_cinv_chol(n, pr, pi, xr, xi, ctypes.byref(fl))
+    return Xr, Xi, info, fl.value
+
+
+def frob_solve(A, B, c, d):
+    """Algorithm 3 (sign of step 7 corrected) for n x p right-hand sides.
+    Returns (x, y, info, flops)."""
+    lib = _load()
+    n = A.shape[0]
+    c = np.asarray(c, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    squeeze = c.ndim == 1
+    if squeeze:
+        c, d = c[:, None], d[:, None]
+    p = c.shape[1]
+    (A, pa), (B, pb), (c, pc), (d, pd) = _c(A), _c(B), _c(c), _c(d)
+    (x, px), (y, py) = _out(n, p), _out(n, p)
+    fl = ctypes.c_double(0)
+    info = lib.orc_frob_solve(n, p, pa, pb, pc, pd, px, py, ctypes.byref(fl))
+    if squeeze:
+        x, y = x[:, 0], y[:, 0]
+    return x, y, info, fl.value
+
+
+def adjoint(Xr, Xi, Gr, Gi):
+    """dM = -X^H G X^H.  Returns (dMr, dMi)."""
+    lib = _load()
+    n = Xr.shape[0]
+    (Xr, a), (Xi, b), (Gr, c), (Gi, d) = _c(Xr), _c(Xi), _c(Gr), _c(Gi)
+    (R, pr), (I, pi) = _out(n, n), _out(n, n)
+    lib.orc_adjoint(n, a, b, c, d, pr, pi)
+    return R, I
+
+
+def cmatmul(Xr, Xi, Yr, Yi):
+    """Plain complex product (X Y).  Returns (Zr, Zi)."""
+    lib = _load()
+    n, k = Xr.shape
+    k2, m = Yr.shape
+    assert k == k2
+    (Xr, a), (Xi, b), (Yr, c), (Yi, d) = _c(Xr), _c(Xi), _c(Yr), _c(Yi)
+    (Zr, pr), (Zi, pi) = _out(n, m), _out(n, m)
+    lib.orc_cmatmul(n, k, m, a, b, c, d, pr, pi)
+    return Zr, Zi

@@ -1,0 +1,90 @@
+/*
+ * frob_oracle.h -- plain, slow FP64 CPU oracle for Frobenius inversion of a
+ * complex matrix M = A + iB (Dai, Lim, Ye, "Complex matrix inversion via real
+ * matrix inversions", arXiv 2208.01239).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  The product path
+ * (libfrobinv) shares no code, header, helper or table with it.
+ *
+ * Conventions (all functions):
+ *   - matrices are dense, row-major, n x n (or n x p for right-hand sides),
+ *     leading dimension equal to the column count, FP64;
+ *   - a complex matrix is passed as two real arrays (real part, imaginary part);
+ *   - every input is read-only; outputs are caller-allocated;
+ *   - `flops` (may be NULL) receives the real-flop count of the run: a complex
+ *     multiply counts 6, a complex add/subtract 2, a complex divide 11, a real
+ *     operation 1 (the paper's accounting in the proof of Theorem 4.1);
+ *   - return value: 0 on success; otherwise a positive code described per
+ *     function.  A zero pivot is detected exactly (pivot == 0.0), following the
+ *     LAPACK convention.
+ */
+#ifndef FROB_ORACLE_H
+#define FROB_ORACLE_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes: info = k+1 of the first zero pivot, offset by the stage. */
+#define ORC_STAGE_A 1000000   /* factorization of the real part (or of A - mu B) failed */
+#define ORC_STAGE_C 2000000   /* factorization of C = A + B A^{-1} B failed (M singular, Lemma 2.3) */
+
+/* Algorithm 4 (inversion with LU decomposition) carried out in complex
+ * arithmetic: GEPP with |z| = hypot(re, im) and the lowest row index on ties,
+ * then U X1 = I by backward substitution, X2 L = X1 by forward substitution,
+ * X = X2 P.  Returns k+1 if the k-th pivot (0-based) is exactly zero.
+ * piv (may be NULL) receives the n row interchanges. */
+int orc_cinv_lu(int n, const double *Mr, const double *Mi, double *Xr, double *Xi,
+                int *piv, double *flops);
+
+/* Gauss-Jordan elimination of [M | I] with partial pivoting (complex).  An
+ * independent route to the same inverse, used only to cross-check orc_cinv_lu. */
+int orc_cinv_gj(int n, const double *Mr, const double *Mi, double *Xr, double *Xi);
+
+/* Algorithm 5 (Frobenius inversion with LU decomposition), real arithmetic.
+ * Output X = Xr + i Xi = (A + iB)^{-1}.  Returns ORC_STAGE_A + k + 1 if A has a
+ * zero pivot, ORC_STAGE_C + k + 1 if C = A + B A^{-1} B has one. */
+int orc_frob_lu(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops);
+
+/* Algorithm 6 (almost sure Frobenius inversion) with the shift mu supplied by
+ * the caller: X1 = A - mu B, X2 = mu A + B, Algorithm 5 on X1 + i X2, then
+ * X5 = X3 - mu X4, X6 = mu X3 + X4 where X3 + i X4 = (X1 + i X2)^{-1}. */
+int orc_frob_shift(int n, const double *A, const double *B, double mu,
+                   double *Xr, double *Xi, double *flops);
+
+/* Algorithm 7 (Frobenius inversion with Cholesky decomposition) for Hermitian
+ * positive definite A + iB (A symmetric positive definite, B skew-symmetric;
+ * Lemma 4.5).  Reads the full A and B.  Returns ORC_STAGE_A + k + 1 if the
+ * Cholesky factorization of A meets a non-positive pivot, ORC_STAGE_C + k + 1
+ * if that of C = A - X1^T X1 does. */
+int orc_frob_chol(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops);
+
+/* Algorithm 8 (inversion with Cholesky decomposition) in complex arithmetic:
+ * M = R^H R, R^H X1 = I, R X2 = X1.  Returns k+1 on a non-positive pivot. */
+int orc_cinv_chol(int n, const double *Mr, const double *Mi, double *Xr, double *Xi, double *flops);
+
+/* Algorithm 3 (linear system with Frobenius inversion and LU), for p
+ * right-hand sides: solves (A + iB)(x + iy) = c + id with c, d, x, y of shape
+ * n x p.  Step 7 is taken as x = x1 + x2, y = y1 - y2 (the printed sign of y is
+ * reversed; the corrected sign follows from eq. (Finv)).  Return codes as for
+ * orc_frob_lu. */
+int orc_frob_solve(int n, int p, const double *A, const double *B, const double *c, const double *d,
+                   double *x, double *y, double *flops);
+
+/* Adjoint of inversion: dM = -X^H G X^H (complex triple loops), i.e. the
+ * gradient of L(M) = Re tr(W M^{-1}) when G = W^H, in the convention
+ * dL = Re sum(conj(dM) .* dM_direction). */
+void orc_adjoint(int n, const double *Xr, const double *Xi, const double *Gr, const double *Gi,
+                 double *dMr, double *dMi);
+
+/* Plain complex matrix product Z = X Y (n x k times k x m), for residuals. */
+void orc_cmatmul(int n, int k, int m, const double *Xr, const double *Xi, const double *Yr,
+                 const double *Yi, double *Zr, double *Zi);
+
+/* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

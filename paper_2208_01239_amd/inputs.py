@@ -1,0 +1,145 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module only draws random numbers and assembles test matrices; it holds
+none of the inversion arithmetic.  Every generator is deterministic in its seed
+(numpy ``default_rng``, PCG64).  Shapes and distributions follow the workloads
+of the paper (Section 5) and the synthetic configurations used for measurement:
+
+* ``general``      -- A, B iid N(0, 1) (A invertible with probability 1).
+* ``hpd``          -- M = Z Z^H + n I with Z complex, N(0, 1/2) per part;
+                      A = Re M (SPD), B = Im M (skew), Lemma 4.5.
+* ``paper_accuracy`` -- A = Q Lambda Q^T / ||Lambda||_F with kappa(A) = kappa
+                      (Section 5.1 accuracy experiment), same for B.
+* ``paper_speed``  -- A, B ~ U[0, 1] (Section 5.1 speed experiment).
+* ``paper_hpd_speed`` -- (A + iB)^H (A + iB) + 0.01 I, A, B ~ U[-1, 1]
+                      (Section 5.6).
+* ``ill_conditioned_pair`` -- the construction in the proof of Theorem 3.5:
+                      A = Q R, B = Q N R with N a direct sum of 2x2 blocks
+                      [[0, -t], [t, 0]].
+* ``spectrum``     -- M = U diag(sigma) V^H (or U diag(sigma) U^H) with Haar
+                      U, V and sigma log-spaced to a target condition number.
+* ``batch``        -- uneven batch: n ~ U{16..512}, kinds alternate general/HPD.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def general(n: int, seed: int = 0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    B = rng.standard_normal((n, n))
+    return A, B
+
+
+def hpd(n: int, seed: int = 1):
+    rng = np.random.default_rng(seed)
+    Zr = rng.standard_normal((n, n)) * np.sqrt(0.5)
+    Zi = rng.standard_normal((n, n)) * np.sqrt(0.5)
+    # Z Z^H with Z = Zr + i Zi, real and imaginary parts assembled from real products
+    Mr = Zr @ Zr.T + Zi @ Zi.T
+    Mi = Zi @ Zr.T - Zr @ Zi.T
+    Mr = 0.5 * (Mr + Mr.T) + n * np.eye(n)
+    Mi = 0.5 * (Mi - Mi.T)
+    return np.ascontiguousarray(Mr), np.ascontiguousarray(Mi)
+
+
+def _haar_orthogonal(n: int, rng) -> np.ndarray:
+    Q, R = np.linalg.qr(rng.uniform(-1.0, 1.0, size=(n, n)))
+    return Q * np.sign(np.diag(R))
+
+
+def paper_accuracy(n: int, kappa: float = 10.0, seed: int = 2):
+    rng = np.random.default_rng(seed)
+
+    def one():
+        Q = _haar_orthogonal(n, rng)
+        if n == 1:
+            lam = np.array([rng.choice([-1.0, 1.0])])
+        else:
+            mags = np.concatenate([[kappa], rng.uniform(1.0, kappa, size=n - 2), [1.0]])
+            lam = mags * rng.choice([-1.0, 1.0], size=n)
+        X = (Q * lam) @ Q.T / np.linalg.norm(lam)
+        return 0.5 * (X + X.T)
+
+    return one(), one()
+
+
+def paper_speed(n: int, seed: int = 3):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n, n)), rng.uniform(0.0, 1.0, size=(n, n))
+
+
+def paper_hpd_speed(n: int, seed: int = 6):
+    rng = np.random.default_rng(seed)
+    Ar = rng.uniform(-1.0, 1.0, size=(n, n))
+    Ai = rng.uniform(-1.0, 1.0, size=(n, n))
+    # (Ar + i Ai)^H (Ar + i Ai) = (Ar^T Ar + Ai^T Ai) + i (Ar^T Ai - Ai^T Ar)
+    Mr = Ar.T @ Ar + Ai.T @ Ai + 0.01 * np.eye(n)
+    Mi = Ar.T @ Ai - Ai.T @ Ar
+    return np.ascontiguousarray(0.5 * (Mr + Mr.T)), np.ascontiguousarray(0.5 * (Mi - Mi.T))
+
+
+def ill_conditioned_pair(m: int, t: float, seed: int = 7, identity_a: bool = False):
+    """Theorem 3.5 construction on 2m x 2m matrices.  Returns (A, B, Q, R, N)."""
+    n = 2 * m
+    rng = np.random.default_rng(seed)
+    if identity_a:
+        Q = np.eye(n)
+        R = np.eye(n)
+    else:
+        Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+    N = np.zeros((n, n))
+    for b in range(m):
+        N[2 * b, 2 * b + 1] = -t
+        N[2 * b + 1, 2 * b] = t
+    A = Q @ R
+    B = Q @ N @ R
+    return A, B, Q, R, N
+
+
+def haar_unitary(n: int, rng):
+    G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(G)
+    d = np.diag(R)
+    return Q * (d / np.abs(d))
+
+
+def spectrum(n: int, kappa: float, kind: str = "general", seed: int = 302):
+    """M = U diag(sigma) V^H with sigma_j = kappa^(-j/(n-1)); HPD uses V = U."""
+    rng = np.random.default_rng(seed)
+    U = haar_unitary(n, rng)
+    sig = kappa ** (-np.arange(n) / max(n - 1, 1))
+    if kind == "hpd":
+        M = (U * sig) @ U.conj().T
+        M = 0.5 * (M + M.conj().T)
+    else:
+        V = haar_unitary(n, rng)
+        M = (U * sig) @ V.conj().T
+    return np.ascontiguousarray(M.real), np.ascontiguousarray(M.imag)
+
+
+def batch(count: int = 2048, seed: int = 4, n_lo: int = 16, n_hi: int = 512):
+    """Uneven batch: sizes n ~ U{n_lo..n_hi}; kind_i = i mod 2 (0 general, 1 HPD).
+    Returns (ns, kinds, list of (A, B))."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    kinds = np.arange(count) % 2
+    children = np.random.SeedSequence(seed).spawn(count)
+    mats = []
+    for i in range(count):
+        s = int(children[i].generate_state(1)[0])
+        n = int(ns[i])
+        mats.append(general(n, s) if kinds[i] == 0 else hpd(n, s))
+    return ns.astype(np.int32), kinds.astype(np.int32), mats
+
+
+def adjoint_batch(count: int = 256, n: int = 256, seed: int = 5):
+    """HPD matrices and complex weights W for L = sum_b Re tr(W_b X_b)."""
+    children = np.random.SeedSequence(seed).spawn(2 * count)
+    mats, ws = [], []
+    for b in range(count):
+        mats.append(hpd(n, int(children[b].generate_state(1)[0])))
+        rng = np.random.default_rng(int(children[count + b].generate_state(1)[0]))
+        ws.append((rng.standard_normal((n, n)), rng.standard_normal((n, n))))
+    return mats, ws

@@ -1,0 +1,495 @@
+"""Pins for the FP64 CPU oracle (runs on the CPU, no GPU).
+
+The oracle is checked against what the paper and the mathematics fix, never
+against itself: closed forms (n = 1, adjugates of 2x2 and 3x3), exact
+Gaussian-rational inversion by brute force, unimodular Gaussian-integer
+matrices with integer inverses, the paper's worked examples (diag(1, i),
+diag(0, 1, i)), the block equations in the proof of Lemma 2.4, the structure
+given by Lemma 4.5, shift independence (Proposition 4.4), the exact inverse of
+the Theorem 3.5 construction, Proposition 3.4, the flop counts of
+Propositions 4.2 and 4.6, LAPACK's inverse as a library special case, and
+central finite differences for the adjoint.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_01239_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U = np.finfo(np.float64).eps / 2
+
+
+def relF(Xr, Xi, Rr, Ri):
+    return np.sqrt(np.sum((Xr - Rr) ** 2 + (Xi - Ri) ** 2) / np.sum(Rr ** 2 + Ri ** 2))
+
+
+def cplx(r, i):
+    return np.asarray(r) + 1j * np.asarray(i)
+
+
+def all_inverses(A, B, hpd=False):
+    """Every oracle route that applies to M = A + iB."""
+    out = {}
+    Xr, Xi, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    out["alg4"] = (Xr, Xi)
+    Xr, Xi, info = oracle.cinv_gj(A, B)
+    assert info == 0
+    out["gauss_jordan"] = (Xr, Xi)
+    Xr, Xi, info, _ = oracle.frob_lu(A, B)
+    assert info == 0
+    out["alg5"] = (Xr, Xi)
+    Xr, Xi, info, _ = oracle.frob_shift(A, B, 0.37)
+    assert info == 0
+    out["alg6"] = (Xr, Xi)
+    if hpd:
+        Xr, Xi, info, _ = oracle.frob_chol(A, B)
+        assert info == 0
+        out["alg7"] = (Xr, Xi)
+        Xr, Xi, info, _ = oracle.cinv_chol(A, B)
+        assert info == 0
+        out["alg8"] = (Xr, Xi)
+    return out
+
+
+# --------------------------------------------------------------------------- closed forms
+def test_n1_closed_form():
+    for a, b in [(2.0, 3.0), (-0.5, 1e-3), (1e3, -7.0)]:
+        ref = 1.0 / complex(a, b)
+        # (a + ib)^{-1} = (a - ib) / (a^2 + b^2)
+        assert abs(ref - complex(a, -b) / (a * a + b * b)) < 1e-15 * abs(ref)
+        for name, (Xr, Xi) in all_inverses(np.array([[a]]), np.array([[b]])).items():
+            assert abs(complex(Xr[0, 0], Xi[0, 0]) - ref) <= 4 * U * abs(ref), name
+
+
+def adjugate_inverse(M):
+    n = M.shape[0]
+    if n == 2:
+        a, b, c, d = M[0, 0], M[0, 1], M[1, 0], M[1, 1]
+        return np.array([[d, -b], [-c, a]]) / (a * d - b * c)
+    assert n == 3
+    C = np.zeros((3, 3), dtype=complex)
+    for i in range(3):
+        for j in range(3):
+            minor = np.delete(np.delete(M, i, 0), j, 1)
+            C[i, j] = (-1) ** (i + j) * (minor[0, 0] * minor[1, 1] - minor[0, 1] * minor[1, 0])
+    det = sum(M[0, j] * C[0, j] for j in range(3))
+    return C.T / det
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("seed", range(6))
+def test_small_adjugate_closed_form(n, seed):
+    rng = np.random.default_rng(100 + seed)
+    A = rng.standard_normal((n, n))
+    B = rng.standard_normal((n, n))
+    M = cplx(A, B)
+    if np.linalg.cond(M) > 1e2:
+        pytest.skip("closed-form tolerance stated for kappa <= 1e2")
+    ref = adjugate_inverse(M)
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert relF(Xr, Xi, ref.real, ref.imag) < 1e-13, name
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_small_hpd_adjugate(n):
+    rng = np.random.default_rng(11 + n)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    M = Z @ Z.conj().T + n * np.eye(n)
+    M = 0.5 * (M + M.conj().T)
+    ref = adjugate_inverse(M)
+    for name, (Xr, Xi) in all_inverses(M.real.copy(), M.imag.copy(), hpd=True).items():
+        assert relF(Xr, Xi, ref.real, ref.imag) < 1e-13, name
+
+
+# --------------------------------------------------------------------------- brute force
+def _gauss_rational_inverse(M):
+    """Exact Gauss-Jordan over Q(i); entries are (Fraction re, Fraction im)."""
+    n = len(M)
+
+    def mul(a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    def sub(a, b):
+        return (a[0] - b[0], a[1] - b[1])
+
+    def inv(a):
+        d = a[0] * a[0] + a[1] * a[1]
+        return (a[0] / d, -a[1] / d)
+
+    zero, one = (Fraction(0), Fraction(0)), (Fraction(1), Fraction(0))
+    W = [list(M[i]) + [one if j == i else zero for j in range(n)] for i in range(n)]
+    for k in range(n):
+        p = next(i for i in range(k, n) if W[i][k] != zero)
+        W[k], W[p] = W[p], W[k]
+        r = inv(W[k][k])
+        W[k] = [mul(r, x) for x in W[k]]
+        for i in range(n):
+            if i != k and W[i][k] != zero:
+                f = W[i][k]
+                W[i] = [sub(x, mul(f, y)) for x, y in zip(W[i], W[k])]
+    return [[W[i][n + j] for j in range(n)] for i in range(n)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("seed", range(3))
+def test_exact_rational_brute_force(n, seed):
+    rng = np.random.default_rng(1000 * n + seed)
+    while True:
+        A = rng.integers(-5, 6, size=(n, n)).astype(float)
+        B = rng.integers(-5, 6, size=(n, n)).astype(float)
+        if np.linalg.cond(A) < 1e3 and np.linalg.cond(cplx(A, B)) < 1e3:
+            break
+    exact = _gauss_rational_inverse([[(Fraction(int(A[i, j])), Fraction(int(B[i, j]))) for j in range(n)]
+                                     for i in range(n)])
+    Er = np.array([[float(e[0]) for e in row] for row in exact])
+    Ei = np.array([[float(e[1]) for e in row] for row in exact])
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert relF(Xr, Xi, Er, Ei) < 1e-13, name
+        # X M = I and M X = I on tiny inputs
+        X, M = cplx(Xr, Xi), cplx(A, B)
+        assert np.abs(X @ M - np.eye(n)).max() < 1e-13, name
+        assert np.abs(M @ X - np.eye(n)).max() < 1e-13, name
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_exact_rational_hpd(n):
+    rng = np.random.default_rng(77 + n)
+    Zr = rng.integers(-3, 4, size=(n, n))
+    Zi = rng.integers(-3, 4, size=(n, n))
+    Z = Zr + 1j * Zi
+    M = Z.conj().T @ Z + np.eye(n)          # exact Gaussian-integer HPD matrix
+    A, B = M.real.copy(), M.imag.copy()
+    if n <= 5:
+        exact = _gauss_rational_inverse([[(Fraction(int(A[i, j])), Fraction(int(B[i, j]))) for j in range(n)]
+                                         for i in range(n)])
+        ref = np.array([[float(e[0]) + 1j * float(e[1]) for e in row] for row in exact])
+    else:
+        ref = None
+    kappa = np.linalg.cond(M)
+    for name, (Xr, Xi) in all_inverses(A, B, hpd=True).items():
+        X = cplx(Xr, Xi)
+        assert np.abs(X @ M - np.eye(n)).max() < 1e-15 * kappa * n * 10, name
+        if ref is not None:
+            assert relF(Xr, Xi, ref.real, ref.imag) < 1e-13, name
+
+
+@pytest.mark.parametrize("n", [6, 7, 8])
+def test_unimodular_gaussian_integer_inverse(n):
+    """M = L U with Gaussian-integer unit triangular factors has det 1 and an
+    inverse with Gaussian-integer entries, computed here exactly."""
+    rng = np.random.default_rng(500 + n)
+    L = np.eye(n, dtype=complex)
+    Uu = np.eye(n, dtype=complex)
+    for i in range(n):
+        for j in range(i):
+            L[i, j] = complex(int(rng.integers(-1, 2)), int(rng.integers(-1, 2)))
+            Uu[j, i] = complex(int(rng.integers(-1, 2)), int(rng.integers(-1, 2)))
+    M = L @ Uu
+    # exact inverses of unit triangular integer matrices by integer substitution
+    def unit_lower_inv(T):
+        m = T.shape[0]
+        X = np.zeros((m, m), dtype=object)
+        for c in range(m):
+            for i in range(m):
+                s = (1 if i == c else 0) - sum(complex(T[i, k]) * X[k, c] for k in range(i))
+                X[i, c] = s
+        return X
+
+    Linv = unit_lower_inv(L)
+    Uinv = unit_lower_inv(Uu.T).T
+    exact = np.array((Uinv @ Linv).tolist(), dtype=complex)
+    assert np.all(exact.real == np.round(exact.real)) and np.all(exact.imag == np.round(exact.imag))
+    A, B = M.real.copy(), M.imag.copy()
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert relF(Xr, Xi, exact.real, exact.imag) < 1e-13, name
+        assert np.array_equal(np.round(Xr), exact.real) and np.array_equal(np.round(Xi), exact.imag), name
+
+
+# --------------------------------------------------------------------------- worked examples
+def test_worked_example_diag_1_i_needs_shift():
+    g = json.load(open(os.path.join(GOLD, "diag_1_i.json")))
+    A, B = np.array(g["Mr"]), np.array(g["Mi"])
+    Xr, Xi, info, _ = oracle.frob_lu(A, B)
+    assert info == oracle.STAGE_A + 2           # A = diag(1, 0): zero pivot at step 2
+    for mu in (0.1, 0.5, 0.9, 1.0):
+        Xr, Xi, info, _ = oracle.frob_shift(A, B, mu)
+        assert info == 0
+        assert np.abs(Xr - np.array(g["Xr"])).max() < 4 * U
+        assert np.abs(Xi - np.array(g["Xi"])).max() < 4 * U
+    Xr, Xi, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0 and np.abs(cplx(Xr, Xi) - cplx(g["Xr"], g["Xi"])).max() < 4 * U
+
+
+def test_worked_example_moore_penrose_singular():
+    g = json.load(open(os.path.join(GOLD, "moore_penrose_3x3.json")))
+    A, B = np.array(g["Mr"]), np.array(g["Mi"])
+    assert oracle.cinv_lu(A, B)[2] > 0
+    assert oracle.cinv_gj(A, B)[2] > 0
+    assert oracle.frob_lu(A, B)[2] > 0
+    for mu in (0.1, 0.5, 0.9):
+        assert oracle.frob_shift(A, B, mu)[2] > 0      # A - mu B singular for every mu
+    # the pseudo-inverse version of eq. (Finv) differs from the pseudo-inverse
+    assert not np.allclose(cplx(g["pinv_r"], g["pinv_i"]), cplx(g["frob_with_pinv_r"], g["frob_with_pinv_i"]))
+    # and numpy's pseudo-inverse agrees with the printed X^dagger
+    P = np.linalg.pinv(cplx(A, B))
+    assert np.allclose(P, cplx(g["pinv_r"], g["pinv_i"]))
+
+
+# --------------------------------------------------------------------------- invariants
+@pytest.mark.parametrize("n,seed", [(16, 0), (48, 1), (97, 2)])
+def test_block_equations_and_library_inverse(n, seed):
+    A, B = inputs.general(n, seed)
+    ref = np.linalg.inv(cplx(A, B))
+    kappa = np.linalg.cond(cplx(A, B))
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        # proof of Lemma 2.4 with tau = 1: A C - B D = I and A D + B C = 0
+        assert np.abs(A @ Xr - B @ Xi - np.eye(n)).max() < 1e-10, name
+        assert np.abs(A @ Xi + B @ Xr).max() < 1e-10, name
+        assert relF(Xr, Xi, ref.real, ref.imag) < 1e-13 * max(kappa, 10) * 50, name
+
+
+def test_frobenius_commutation_identity():
+    """A^{-1} B C^{-1} = C^{-1} B A^{-1}: both equal minus the imaginary part of
+    the inverse (eq. (Finv) and the same formula for the transpose)."""
+    A, B = inputs.general(24, 3)
+    Xr, Xi, info, _ = oracle.frob_lu(A, B)
+    assert info == 0
+    Ai = np.linalg.inv(A)
+    C = A + B @ Ai @ B
+    Ci = np.linalg.inv(C)
+    assert np.allclose(Ai @ B @ Ci, Ci @ B @ Ai, atol=1e-10)
+    assert np.allclose(-Xi, Ai @ B @ Ci, atol=1e-10)
+    assert np.allclose(Xr, Ci, atol=1e-10)
+
+
+@pytest.mark.parametrize("n", [8, 33, 64])
+def test_hpd_structure(n):
+    A, B = inputs.hpd(n, 9)
+    assert np.array_equal(A, A.T) and np.array_equal(B, -B.T)
+    routes = all_inverses(A, B, hpd=True)
+    for name, (Xr, Xi) in routes.items():
+        X = cplx(Xr, Xi)
+        assert np.abs(X - X.conj().T).max() < 1e-15 * n * 10, name
+        w = np.linalg.eigvalsh(0.5 * (X + X.conj().T))
+        assert w.min() > 0, name
+    Xr, Xi = routes["alg7"]
+    assert np.abs(Xr - Xr.T).max() < 1e-15 * n * 10 and np.abs(Xi + Xi.T).max() < 1e-15 * n * 10
+    ref = routes["alg4"]
+    for name in ("alg7", "alg8"):
+        assert relF(*routes[name], *ref) < 1e-14 * 50, name
+    # kappa(A) <= kappa(M) and kappa(C) <= kappa(M) for HPD M
+    kM = np.linalg.cond(cplx(A, B))
+    C = A + B @ np.linalg.solve(A, B)
+    assert np.linalg.cond(A) <= kM * (1 + 1e-10) and np.linalg.cond(C) <= kM * (1 + 1e-10)
+
+
+def test_hpd_rejects_indefinite():
+    A = np.diag([1.0, -1.0, 2.0])
+    B = np.zeros((3, 3))
+    assert oracle.frob_chol(A, B)[2] == oracle.STAGE_A + 2
+    assert oracle.cinv_chol(A, B)[2] == 2
+
+
+@pytest.mark.parametrize("n", [12, 40])
+def test_shift_independence(n):
+    """Proposition 4.4: the almost-sure inversion returns the same inverse for
+    every admissible mu."""
+    A, B = inputs.general(n, 21)
+    res = [oracle.frob_shift(A, B, mu)[:2] for mu in (0.1, 0.5, 0.9)]
+    kappa = np.linalg.cond(cplx(A, B))
+    for r in res[1:]:
+        assert relF(*r, *res[0]) < 1e-14 * kappa * 100
+
+
+def test_shift_singular_real_part():
+    """A singular, M invertible: Algorithm 5 fails, Algorithm 6 succeeds."""
+    rng = np.random.default_rng(5)
+    n = 20
+    A = rng.standard_normal((n, n))
+    A[:, 3] = A[:, 0] - 2 * A[:, 7]               # rank-deficient real part
+    A[:, 3] = 0.0
+    B = rng.standard_normal((n, n))
+    assert oracle.frob_lu(A, B)[2] > oracle.STAGE_A
+    Xr, Xi, info, _ = oracle.frob_shift(A, B, 0.42)
+    assert info == 0
+    ref = np.linalg.inv(cplx(A, B))
+    assert relF(Xr, Xi, ref.real, ref.imag) < 1e-11
+
+
+# --------------------------------------------------------------------------- Section 3 constructions
+def test_theorem_3_5_identity_real_part_exact():
+    m, t = 4, 0.5
+    A, B, Q, R, N = inputs.ill_conditioned_pair(m, t, identity_a=True)
+    n = 2 * m
+    # (I + iN)(I - iN) = I + N^2 = (1 - t^2) I, so (I + iN)^{-1} = (I - iN) / (1 - t^2)
+    ref = (np.eye(n) - 1j * N) / (1 - t * t)
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert np.abs(cplx(Xr, Xi) - ref).max() < 4 * U * np.abs(ref).max(), name
+
+
+@pytest.mark.parametrize("gap", [1e-2, 1e-4])
+def test_theorem_3_5_closed_form(gap):
+    m, t = 8, 1.0 - gap
+    A, B, Q, R, N = inputs.ill_conditioned_pair(m, t, seed=8)
+    n = 2 * m
+    Rinv = np.linalg.inv(R)
+    ref = Rinv @ (np.eye(n) - 1j * N) @ Q.T / (1 - t * t)   # M = Q (I + iN) R
+    kR = np.linalg.cond(R)
+    kM = np.linalg.cond(cplx(A, B))
+    assert kM >= 1.0 / (1.0 - t) * (1 - 1e-6)                # Theorem 3.5 bound
+    C = A + B @ np.linalg.solve(A, B)
+    assert np.allclose(C, (1 - t * t) * A, atol=1e-10 * np.abs(A).max())   # C = (1 - t^2) A
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert relF(Xr, Xi, ref.real, ref.imag) < 200 * U * kR / (1 - t), name
+
+
+def test_proposition_3_4_orthogonal():
+    rng = np.random.default_rng(34)
+    n = 16
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A, B = np.eye(n), Q
+    ref = (np.eye(n) - 1j * Q) @ np.linalg.inv(Q @ Q + np.eye(n))
+    k = np.linalg.cond(np.eye(n) + 1j * Q)
+    for name, (Xr, Xi) in all_inverses(A, B).items():
+        assert relF(Xr, Xi, ref.real, ref.imag) < 100 * U * k * n, name
+
+
+# --------------------------------------------------------------------------- flop counts
+def _leading_coefficient(fn, ns=(24, 32, 40, 48)):
+    """The counters are exact polynomials of degree 3 in n; fit and return a3."""
+    y = np.array([fn(n) for n in ns], dtype=float)
+    V = np.vander(np.array(ns, dtype=float), 4)
+    return np.linalg.solve(V, y)[0]
+
+
+def test_flop_counts_match_paper():
+    g = json.load(open(os.path.join(GOLD, "flop_counts.json")))["leading_coefficient"]
+
+    def gen(n):
+        return inputs.general(n, 5)
+
+    def hp(n):
+        return inputs.hpd(n, 5)
+
+    c4 = _leading_coefficient(lambda n: oracle.cinv_lu(*gen(n))[4])
+    c5 = _leading_coefficient(lambda n: oracle.frob_lu(*gen(n))[3])
+    c7 = _leading_coefficient(lambda n: oracle.frob_chol(*hp(n))[3])
+    c8 = _leading_coefficient(lambda n: oracle.cinv_chol(*hp(n))[3])
+    assert abs(c4 - g["alg4_complex_lu"]) < 1e-8
+    assert abs(c5 - g["alg5_frobenius_lu"]) < 1e-8
+    assert abs(c7 - g["alg7_frobenius_cholesky"]) < 1e-8
+    assert abs(c8 - g["alg8_complex_cholesky"]) < 1e-8
+    n = 20
+    A, B = gen(n)
+    extra = oracle.frob_shift(A, B, 0.5)[3] - oracle.frob_lu(A - 0.5 * B, 0.5 * A + B)[3]
+    assert extra == json.load(open(os.path.join(GOLD, "flop_counts.json")))["shift_extra_flops_per_n2"] * n * n
+
+
+# --------------------------------------------------------------------------- solve (Algorithm 3)
+@pytest.mark.parametrize("n,p", [(1, 1), (17, 1), (40, 3)])
+def test_solve_against_embedding(n, p):
+    A, B = inputs.general(n, 31)
+    rng = np.random.default_rng(32)
+    x = rng.uniform(-1, 1, size=(n, p))
+    y = rng.uniform(-1, 1, size=(n, p))
+    c = A @ x - B @ y
+    d = B @ x + A @ y
+    xs, ys, info, _ = oracle.frob_solve(A, B, c, d)
+    assert info == 0
+    # the 2n x 2n real embedding [[A, -B], [B, A]] solved by LAPACK (Section 3)
+    E = np.block([[A, -B], [B, A]])
+    z = np.linalg.solve(E, np.vstack([c, d]))
+    kappa = np.linalg.cond(E)
+    assert np.abs(xs - z[:n]).max() < 1e-14 * kappa * 100
+    assert np.abs(ys - z[n:]).max() < 1e-14 * kappa * 100
+    assert np.abs(cplx(xs, ys) - cplx(x, y)).max() < 1e-14 * kappa * 100
+
+
+def test_solve_printed_sign_is_wrong():
+    """Step 7 as printed (y = y2 - y1) gives -(the imaginary part) + 2 y1 - ...;
+    the oracle's y = y1 - y2 matches the true solution."""
+    n = 10
+    A, B = inputs.general(n, 40)
+    rng = np.random.default_rng(41)
+    x = rng.uniform(-1, 1, size=n)
+    y = rng.uniform(-1, 1, size=n)
+    c, d = A @ x - B @ y, B @ x + A @ y
+    xs, ys, info, _ = oracle.frob_solve(A, B, c, d)
+    assert np.abs(ys - y).max() < 1e-10
+    Xinv = np.linalg.inv(cplx(A, B))
+    Cinv = Xinv.real
+    y1 = Cinv @ d
+    assert np.abs((y1 - ys) - ys).max() > 1e-3 or np.abs(y1).max() < 1e-12
+
+
+# --------------------------------------------------------------------------- adjoint
+def test_adjoint_finite_differences():
+    n = 7
+    A, B = inputs.hpd(n, 51)
+    rng = np.random.default_rng(52)
+    W = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    M = cplx(A, B)
+
+    def loss(Mc):
+        Xr, Xi, info, _, _ = oracle.cinv_lu(Mc.real.copy(), Mc.imag.copy())
+        assert info == 0
+        return np.trace(W @ cplx(Xr, Xi)).real
+
+    Xr, Xi, _, _, _ = oracle.cinv_lu(A, B)
+    G = W.conj().T
+    dMr, dMi = oracle.adjoint(Xr, Xi, G.real.copy(), G.imag.copy())
+    dM = cplx(dMr, dMi)
+    h = 1e-6
+    for k in range(8):
+        E = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        if k % 2:
+            E = 0.5 * (E + E.conj().T)           # Hermitian directions
+        fd = (loss(M + h * E) - loss(M - h * E)) / (2 * h)
+        an = np.sum(np.conj(dM) * E).real
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    # full per-entry finite differences on the real and imaginary parts
+    for i in range(n):
+        for j in range(n):
+            for part in (1.0, 1j):
+                E = np.zeros((n, n), dtype=complex)
+                E[i, j] = part
+                fd = (loss(M + h * E) - loss(M - h * E)) / (2 * h)
+                an = (dM[i, j].real if part == 1.0 else dM[i, j].imag)
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_adjoint_transpose_convention_differs():
+    """The conjugate-free form -X^H W^T X^H differs when W is complex."""
+    n = 5
+    A, B = inputs.hpd(n, 61)
+    rng = np.random.default_rng(62)
+    W = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Xr, Xi, _, _, _ = oracle.cinv_lu(A, B)
+    good = cplx(*oracle.adjoint(Xr, Xi, W.conj().T.real.copy(), W.conj().T.imag.copy()))
+    other = cplx(*oracle.adjoint(Xr, Xi, W.T.real.copy(), W.T.imag.copy()))
+    assert np.abs(good - other).max() > 1e-3
+
+
+def test_cmatmul_and_threads():
+    rng = np.random.default_rng(70)
+    X = rng.standard_normal((5, 4)) + 1j * rng.standard_normal((5, 4))
+    Y = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    Zr, Zi = oracle.cmatmul(X.real, X.imag, Y.real, Y.imag)
+    assert np.allclose(cplx(Zr, Zi), X @ Y, atol=1e-14)
+    assert oracle.num_threads() >= 1
+
+
+def test_paper_accuracy_generator():
+    """Section 5.1 accuracy generator: kappa(A) = kappa(B) = kappa."""
+    A, B = inputs.paper_accuracy(32, 10.0, seed=3)
+    assert abs(np.linalg.cond(A) - 10.0) < 1e-8 and abs(np.linalg.cond(B) - 10.0) < 1e-8
+    routes = all_inverses(A, B)
+    ref = np.linalg.inv(cplx(A, B))
+    for name, (Xr, Xi) in routes.items():
+        assert relF(Xr, Xi, ref.real, ref.imag) < 1e-12, name
