@@ -1,0 +1,147 @@
+/*
+ * frobinv.h -- C ABI of libfrobinv: inversion of a complex matrix M = A + iB
+ * with real operations only ("Frobenius inversion"), on AMD MI355X (gfx950).
+ *
+ * Method: Z. Dai, L.-H. Lim, K. Ye, "Complex matrix inversion via real matrix
+ * inversions" (arXiv 2208.01239).  The inverse is given by eq. (Finv):
+ *     (A + iB)^{-1} = (A + B A^{-1} B)^{-1} - i A^{-1} B (A + B A^{-1} B)^{-1}.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are dense, ROW-MAJOR, FP64, in DEVICE memory of the handle's
+ *    device, with a leading dimension (in elements, >= the column count).
+ *    A complex matrix is passed "planar": its real part and its imaginary part
+ *    are two separate real arrays sharing one leading dimension.
+ *  - Ownership: the caller owns every input and output buffer.  Inputs are
+ *    read-only; outputs must not alias inputs or each other.  The handle owns a
+ *    grow-only device workspace and a pinned host word for status read-back,
+ *    released by frob_destroy.
+ *  - Ordering: all device work is enqueued on the handle's stream (see
+ *    frob_set_stream).  Each call ends with one synchronization of that stream
+ *    to read the factorization status, so outputs are ready on return.
+ *  - Errors are reported only through the returned status; nothing is thrown
+ *    across the ABI.  On any non-OK status the outputs are unspecified.
+ *  - One handle must not be used by two host threads at the same time.
+ *  - Supported orders: 1 <= n <= 16384.
+ */
+#ifndef FROBINV_H
+#define FROBINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct frob_handle *frob_handle_t;
+
+typedef enum {
+  FROB_OK = 0,
+  FROB_SINGULAR = 1,        /* exact zero pivot: M is singular (Lemma 2.3: with A invertible, C = A + B A^{-1} B
+                               is invertible iff M is); with the shift disabled, also a singular real part A */
+  FROB_NOT_HPD = 2,         /* a Cholesky factorization met a non-positive pivot (Lemma 4.5 says A and C are
+                               positive definite whenever M is Hermitian positive definite) */
+  FROB_NO_CONVERGENCE = 3,  /* iterative refinement did not reduce the residual below its tolerance */
+  FROB_E_ARG = -1,          /* invalid argument (null pointer, n out of range, leading dimension too small) */
+  FROB_E_ALLOC = -2,        /* device or pinned-host allocation failed */
+  FROB_E_HIP = -3,          /* a HIP runtime call failed */
+  FROB_E_INTERNAL = -4
+} frob_status_t;
+
+/* What to do about the real part A (Section 4.2, Algorithm 6, "almost sure
+ * Frobenius inversion").  The shift works on (1 + i mu) M, whose real part
+ * A - mu B is singular for at most n values of mu (Lemma 4.3). */
+typedef enum {
+  FROB_SHIFT_OFF = 0,   /* Algorithm 5 only; a singular A is reported as FROB_SINGULAR (stage 1)          */
+  FROB_SHIFT_AUTO = 1,  /* Algorithm 5; if the LU of A meets an exact zero pivot, redo with Algorithm 6    */
+  FROB_SHIFT_ON = 2     /* always Algorithm 6                                                               */
+} frob_shift_t;
+
+typedef struct {
+  int shift;            /* frob_shift_t, default FROB_SHIFT_AUTO                                            */
+  double mu;            /* shift to use when shifting; mu <= 0 draws mu ~ U(0,1) from the handle's generator  */
+  uint64_t seed;        /* 0: keep the handle's generator state; otherwise reseed it first                   */
+  int refine;           /* number of Newton-Schulz steps X <- X + X (I - M X) after the inversion (0 = none)  */
+  int reserved[7];
+} frob_opts_t;
+
+typedef struct {
+  int info;             /* 1-based column of the failing pivot, 0 if none                                   */
+  int stage;            /* 0 none, 1 factorization of the real part, 2 factorization of C = A + B A^{-1} B   */
+  double mu_used;       /* shift actually applied (0 if none)                                               */
+  int shifts_tried;     /* number of shifts drawn (Algorithm 6 re-draws when A - mu B is singular)           */
+  int refine_steps;     /* Newton-Schulz steps applied                                                     */
+  double reserved[4];
+} frob_result_t;
+
+/* Fill *opts with the defaults (FROB_SHIFT_AUTO, mu drawn, no refinement). */
+void frob_default_opts(frob_opts_t *opts);
+
+/* Create a handle on HIP device `device`; its work goes to the device's null
+ * stream until frob_set_stream selects another.  Returns FROB_E_ARG for a bad
+ * device, FROB_E_HIP on runtime failure. */
+frob_status_t frob_create(frob_handle_t *handle, int device);
+frob_status_t frob_destroy(frob_handle_t handle);
+/* Use `stream` (a hipStream_t; NULL is the null stream) for all later work.
+ * The caller keeps ownership of the stream. */
+frob_status_t frob_set_stream(frob_handle_t handle, void *stream);
+/* Bytes of device workspace currently held by the handle. */
+size_t frob_workspace_bytes(frob_handle_t handle);
+
+/* General complex matrix: Algorithm 5 (Frobenius inversion with LU
+ * decomposition), with Algorithm 6 per opts->shift.  Computes
+ *   LU of A (partial pivoting), Y = A^{-1} B, C = A + B Y, C^{-1},
+ *   Re X = C^{-1}, Im X = -Y C^{-1}
+ * so that Xr + i Xi = (A + iB)^{-1}.
+ *   A, B   : n x n, leading dimensions lda, ldb (inputs)
+ *   Xr, Xi : n x n, leading dimension ldx (outputs)
+ *   opts   : may be NULL (defaults); res: may be NULL. */
+frob_status_t frob_inv_general(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
+                               double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
+/* Hermitian positive definite M = A + iB: Algorithm 7 (Frobenius inversion
+ * with Cholesky decomposition).  A must be symmetric positive definite and B
+ * skew-symmetric (Lemma 4.5); only the lower triangle of A and the full B are
+ * read.  Computes A = R1^T R1, R1^T X1 = B, R1 Y = X1, C = A - X1^T X1,
+ * C = R2^T R2, Re X = C^{-1} (symmetric), Im X = -Y C^{-1} (skew).
+ * No shift is needed (A is always invertible); opts->shift is ignored.
+ * Returns FROB_NOT_HPD (stage 1 or 2) if either Cholesky factorization fails. */
+frob_status_t frob_inv_hpd(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
+                           double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
+/* Linear system (A + iB)(x + iy) = c + id for nrhs right-hand sides
+ * (Algorithm 3 with the sign of step 7 taken as y = y1 - y2, which is what
+ * eq. (Finv) gives).  No inverse is formed: LU of A, Y = A^{-1} B,
+ * C = A + B Y, LU of C, [x1 y1] = C^{-1} [c d], [x2 y2] = Y [y1 x1],
+ * x = x1 + x2, y = y1 - y2.
+ *   c, d : n x nrhs inputs (leading dimension ldc)
+ *   x, y : n x nrhs outputs (leading dimension ldxy)
+ * opts->shift as for frob_inv_general (the shifted system is solved for
+ * (1 + i mu) M, and the solution is unchanged). */
+frob_status_t frob_solve(frob_handle_t handle, int n, int nrhs, const double *A, int lda, const double *B, int ldb,
+                         const double *c, const double *d, int ldc, double *x, double *y, int ldxy,
+                         const frob_opts_t *opts, frob_result_t *res);
+
+/* Baseline: inversion with LU decomposition in complex arithmetic
+ * (Algorithm 4), planar storage, four real matrix-core products per complex
+ * tile product.  form 0: as printed (U X1 = I, X2 L = X1, X^{-1} = X2 P);
+ * form 1: LAPACK getri style (U^{-1} by a triangular inverse, then
+ * X L = U^{-1}, then the column permutation). */
+frob_status_t frob_cinv_lu(frob_handle_t handle, int n, const double *Mr, const double *Mi, int ldm, double *Xr,
+                           double *Xi, int ldx, int form, frob_result_t *res);
+
+/* Baseline: inversion with Cholesky decomposition in complex arithmetic
+ * (Algorithm 8) for Hermitian positive definite M (lower triangle read).
+ * form 0: as printed (R^H X1 = I, R X2 = X1); form 1: LAPACK potri style
+ * (W = R^{-H} by a triangular inverse, X = W^H W). */
+frob_status_t frob_cinv_chol(frob_handle_t handle, int n, const double *Mr, const double *Mi, int ldm, double *Xr,
+                             double *Xi, int ldx, int form, frob_result_t *res);
+
+/* Human-readable name of a status code (static string). */
+const char *frob_status_string(frob_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FROBINV_H */

@@ -1,0 +1,180 @@
+"""Frobenius inversion of complex matrices with real operations on AMD MI355X.
+
+Python binding of libfrobinv (C ABI in ``include/frobinv.h``).  The functions
+below carry the names of the C entry points and only marshal arguments: torch
+tensors provide device memory and the current stream; all arithmetic runs in
+the library's HIP kernels.  Importing this package does not load the library;
+the first call does, and raises if it is missing (there is no fallback path).
+
+Tensors: float64, on a ROCm device, row-major with unit column stride (a
+leading dimension ``stride(0) >= n`` is allowed).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNotHPDError,  # noqa: F401
+                   FrobSingularError, frob_opts_t, frob_result_t)
+
+__all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_cinv_lu", "frob_cinv_chol",
+           "FrobError", "FrobSingularError", "FrobNotHPDError", "FROB_SHIFT_OFF", "FROB_SHIFT_AUTO",
+           "FROB_SHIFT_ON", "load_library"]
+
+
+def load_library():
+    return _lib.load()
+
+
+class Handle:
+    """Owns a frob_handle_t on one device (workspace, status words, stream)."""
+
+    def __init__(self, device: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.frob_create(ctypes.byref(h), int(device)), "frob_create")
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def ptr(self):
+        if self._h is None:
+            raise RuntimeError("handle closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().frob_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def workspace_bytes(self) -> int:
+        return int(_lib.load().frob_workspace_bytes(self.ptr))
+
+    def bind_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _lib.check(_lib.load().frob_set_stream(self.ptr, ctypes.c_void_p(s.cuda_stream)), "frob_set_stream")
+
+
+def _mat(t, n_rows, n_cols, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda":
+        raise TypeError(f"{name}: expected a float64 tensor on a ROCm device")
+    if t.dim() != 2 or t.shape[0] != n_rows or t.shape[1] != n_cols:
+        raise ValueError(f"{name}: expected shape ({n_rows}, {n_cols}), got {tuple(t.shape)}")
+    if t.stride(1) != 1 or t.stride(0) < n_cols:
+        raise ValueError(f"{name}: rows must be contiguous with leading dimension >= {n_cols}")
+    return ctypes.c_void_p(t.data_ptr()), int(t.stride(0))
+
+
+def _opts(shift, mu, seed, refine):
+    o = frob_opts_t()
+    _lib.load().frob_default_opts(ctypes.byref(o))
+    o.shift = int(shift)
+    o.mu = float(mu)
+    o.seed = int(seed)
+    o.refine = int(refine)
+    return o
+
+
+def _empty_like_sq(A, n):
+    import torch
+    return torch.empty((n, n), dtype=torch.float64, device=A.device)
+
+
+def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0):
+    """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting)."""
+    n = A.shape[0]
+    Xr = _empty_like_sq(A, n) if Xr is None else Xr
+    Xi = _empty_like_sq(A, n) if Xi is None else Xi
+    pa, lda = _mat(A, n, n, "A")
+    pb, ldb = _mat(B, n, n, "B")
+    pr, ldx = _mat(Xr, n, n, "Xr")
+    pi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldx != ldxi:
+        raise ValueError("Xr and Xi must share a leading dimension")
+    h.bind_stream()
+    o, r = _opts(shift, mu, seed, refine), frob_result_t()
+    st = _lib.load().frob_inv_general(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, "frob_inv_general", r)
+    return Xr, Xi, r.as_dict()
+
+
+def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0):
+    """(A + iB)^{-1} for Hermitian positive definite A + iB (Algorithm 7)."""
+    n = A.shape[0]
+    Xr = _empty_like_sq(A, n) if Xr is None else Xr
+    Xi = _empty_like_sq(A, n) if Xi is None else Xi
+    pa, lda = _mat(A, n, n, "A")
+    pb, ldb = _mat(B, n, n, "B")
+    pr, ldx = _mat(Xr, n, n, "Xr")
+    pi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldx != ldxi:
+        raise ValueError("Xr and Xi must share a leading dimension")
+    h.bind_stream()
+    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine), frob_result_t()
+    st = _lib.load().frob_inv_hpd(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, "frob_inv_hpd", r)
+    return Xr, Xi, r.as_dict()
+
+
+def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0):
+    """Solve (A + iB)(x + iy) = c + id for n x p right-hand sides (Algorithm 3)."""
+    import torch
+    n = A.shape[0]
+    p = c.shape[1]
+    x = torch.empty((n, p), dtype=torch.float64, device=A.device) if x is None else x
+    y = torch.empty((n, p), dtype=torch.float64, device=A.device) if y is None else y
+    pa, lda = _mat(A, n, n, "A")
+    pb, ldb = _mat(B, n, n, "B")
+    pc, ldc = _mat(c, n, p, "c")
+    pd, ldd = _mat(d, n, p, "d")
+    px, ldx = _mat(x, n, p, "x")
+    py, ldy = _mat(y, n, p, "y")
+    if ldc != ldd or ldx != ldy:
+        raise ValueError("c/d and x/y must share leading dimensions")
+    h.bind_stream()
+    o, r = _opts(shift, mu, seed, 0), frob_result_t()
+    st = _lib.load().frob_solve(h.ptr, n, p, pa, lda, pb, ldb, pc, pd, ldc, px, py, ldx, ctypes.byref(o),
+                                ctypes.byref(r))
+    _lib.check(st, "frob_solve", r)
+    return x, y, r.as_dict()
+
+
+def _cinv(fn_name, h, Mr, Mi, Xr, Xi, form):
+    n = Mr.shape[0]
+    Xr = _empty_like_sq(Mr, n) if Xr is None else Xr
+    Xi = _empty_like_sq(Mr, n) if Xi is None else Xi
+    pr, ldm = _mat(Mr, n, n, "Mr")
+    pi, ldmi = _mat(Mi, n, n, "Mi")
+    qr, ldx = _mat(Xr, n, n, "Xr")
+    qi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldm != ldmi or ldx != ldxi:
+        raise ValueError("planar pairs must share a leading dimension")
+    h.bind_stream()
+    r = frob_result_t()
+    st = getattr(_lib.load(), fn_name)(h.ptr, n, pr, pi, ldm, qr, qi, ldx, int(form), ctypes.byref(r))
+    _lib.check(st, fn_name, r)
+    return Xr, Xi, r.as_dict()
+
+
+def frob_cinv_lu(h: Handle, Mr, Mi, Xr=None, Xi=None, *, form=1):
+    """Baseline: complex-arithmetic LU inversion (Algorithm 4; form 0 as printed, 1 getri style)."""
+    return _cinv("frob_cinv_lu", h, Mr, Mi, Xr, Xi, form)
+
+
+def frob_cinv_chol(h: Handle, Mr, Mi, Xr=None, Xi=None, *, form=1):
+    """Baseline: complex-arithmetic Cholesky inversion (Algorithm 8; form 0 as printed, 1 potri style)."""
+    return _cinv("frob_cinv_chol", h, Mr, Mi, Xr, Xi, form)

@@ -1,0 +1,112 @@
+"""ctypes binding of libfrobinv (include/frobinv.h).
+
+Argument marshalling only: every entry point forwards device pointers, sizes
+and leading dimensions to the C ABI, which runs all arithmetic in HIP kernels.
+PyTorch supplies device memory and the stream.  There is no fallback: if the
+shared library is missing or fails to load, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfrobinv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "frobinv.h")
+
+FROB_OK = 0
+FROB_SINGULAR = 1
+FROB_NOT_HPD = 2
+FROB_NO_CONVERGENCE = 3
+FROB_E_ARG = -1
+FROB_E_ALLOC = -2
+FROB_E_HIP = -3
+FROB_E_INTERNAL = -4
+
+FROB_SHIFT_OFF = 0
+FROB_SHIFT_AUTO = 1
+FROB_SHIFT_ON = 2
+
+
+class frob_opts_t(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("refine", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
+class frob_result_t(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int), ("stage", ctypes.c_int), ("mu_used", ctypes.c_double),
+                ("shifts_tried", ctypes.c_int), ("refine_steps", ctypes.c_int),
+                ("reserved", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {"info": self.info, "stage": self.stage, "mu_used": self.mu_used,
+                "shifts_tried": self.shifts_tried, "refine_steps": self.refine_steps}
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_OPTS = ctypes.POINTER(frob_opts_t)
+_RES = ctypes.POINTER(frob_result_t)
+
+# name -> (restype, argtypes); kept in the order of include/frobinv.h
+SIGNATURES = {
+    "frob_default_opts": (None, [_OPTS]),
+    "frob_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "frob_destroy": (_i, [_vp]),
+    "frob_set_stream": (_i, [_vp, _vp]),
+    "frob_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "frob_inv_general": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_inv_hpd": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
+    "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
+    "frob_status_string": (ctypes.c_char_p, [_i]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfrobinv.so and declare the C ABI.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libfrobinv.so not built at {path}; run paper_2208_01239_amd/build.py")
+    # PyTorch ships its own HIP runtime (same SONAME as ROCm's).  Load it first so
+    # the library binds to that single runtime instead of a second copy.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FrobError(RuntimeError):
+    def __init__(self, status: int, where: str, result: frob_result_t | None = None):
+        name = load().frob_status_string(status).decode()
+        super().__init__(f"{where}: {name}" + (f" {result.as_dict()}" if result is not None else ""))
+        self.status = status
+        self.result = result
+
+
+class FrobSingularError(FrobError):
+    pass
+
+
+class FrobNotHPDError(FrobError):
+    pass
+
+
+def check(status: int, where: str, result: frob_result_t | None = None):
+    if status == FROB_OK:
+        return
+    if status == FROB_SINGULAR:
+        raise FrobSingularError(status, where, result)
+    if status == FROB_NOT_HPD:
+        raise FrobNotHPDError(status, where, result)
+    raise FrobError(status, where, result)

@@ -1,0 +1,142 @@
+// elem.hip -- bandwidth-bound elementwise kernels (copies, shifts, column
+// permutations, triangle mirroring).  Each thread handles consecutive columns
+// of one row so that a wave64 reads and writes contiguous 512-byte segments.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace frob {
+
+namespace {
+
+constexpr int EB = 256;
+
+inline dim3 grid2d(int m, int n) { return dim3(ceil_div(n, EB), m); }
+
+__global__ void k_iota(int n, int* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+__global__ void k_fill_i32(int n, int v, int* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_copy(int m, int n, const double* __restrict__ src, int lds, const int* __restrict__ rows,
+                       double* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  const int r = rows ? rows[i] : i;
+  dst[(long long)i * ldd + j] = src[(long long)r * lds + j];
+}
+
+__global__ void k_fill(int m, int n, double v, double* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n) dst[(long long)i * ldd + j] = v;
+}
+
+__global__ void k_identity(int n, double* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n) dst[(long long)i * ldd + j] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_axpby(int m, int n, double a, const double* __restrict__ X, int ldx, double b,
+                        double* __restrict__ Y, int ldy) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  double* y = Y + (long long)i * ldy + j;
+  const double x = X[(long long)i * ldx + j];
+  *y = (b == 0.0) ? a * x : a * x + b * *y;
+}
+
+__global__ void k_rotate(int m, int n, double mu, const double* __restrict__ A, int lda,
+                         const double* __restrict__ B, int ldb, double* X1, int ld1, double* X2, int ld2) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  const double a = A[(long long)i * lda + j], b = B[(long long)i * ldb + j];
+  X1[(long long)i * ld1 + j] = a - mu * b;
+  X2[(long long)i * ld2 + j] = mu * a + b;
+}
+
+__global__ void k_permute_cols(int m, int n, const double* __restrict__ src, int lds, const int* __restrict__ perm,
+                               double* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  dst[(long long)i * ldd + perm[j]] = src[(long long)i * lds + j];
+}
+
+__global__ void k_mirror_lower(int n, double* a, int lda, double sign) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n && j > i) a[(long long)i * lda + j] = sign * a[(long long)j * lda + i];
+}
+
+__global__ void k_zero_upper(int n, double* a, int lda) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n && j > i) a[(long long)i * lda + j] = 0.0;
+}
+
+}  // namespace
+
+void iota_i32(hipStream_t s, int n, int* p) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_iota, dim3(ceil_div(n, EB)), dim3(EB), 0, s, n, p);
+  FROB_LAUNCH_CHECK();
+}
+
+void fill_i32(hipStream_t s, int n, int v, int* p) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(n, EB)), dim3(EB), 0, s, n, v, p);
+  FROB_LAUNCH_CHECK();
+}
+
+void copy_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* rows, double* dst, int ldd) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_copy, grid2d(m, n), dim3(EB), 0, s, m, n, src, lds, rows, dst, ldd);
+  FROB_LAUNCH_CHECK();
+}
+
+void fill_f64(hipStream_t s, int m, int n, double v, double* dst, int ldd) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_fill, grid2d(m, n), dim3(EB), 0, s, m, n, v, dst, ldd);
+  FROB_LAUNCH_CHECK();
+}
+
+void identity_f64(hipStream_t s, int n, double* dst, int ldd) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_identity, grid2d(n, n), dim3(EB), 0, s, n, dst, ldd);
+  FROB_LAUNCH_CHECK();
+}
+
+void axpby_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, double* Y, int ldy) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_axpby, grid2d(m, n), dim3(EB), 0, s, m, n, a, X, ldx, b, Y, ldy);
+  FROB_LAUNCH_CHECK();
+}
+
+void rotate_f64(hipStream_t s, int m, int n, double mu, const double* A, int lda, const double* B, int ldb,
+                double* X1, int ld1, double* X2, int ld2) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_rotate, grid2d(m, n), dim3(EB), 0, s, m, n, mu, A, lda, B, ldb, X1, ld1, X2, ld2);
+  FROB_LAUNCH_CHECK();
+}
+
+void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* perm, double* dst,
+                      int ldd) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_permute_cols, grid2d(m, n), dim3(EB), 0, s, m, n, src, lds, perm, dst, ldd);
+  FROB_LAUNCH_CHECK();
+}
+
+void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mirror_lower, grid2d(n, n), dim3(EB), 0, s, n, a, lda, sign);
+  FROB_LAUNCH_CHECK();
+}
+
+void zero_upper_f64(hipStream_t s, int n, double* a, int lda) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_upper, grid2d(n, n), dim3(EB), 0, s, n, a, lda);
+  FROB_LAUNCH_CHECK();
+}
+
+}  // namespace frob

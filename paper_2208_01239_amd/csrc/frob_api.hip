@@ -1,0 +1,419 @@
+// frob_api.hip -- the C ABI of libfrobinv and the Frobenius inversion drivers.
+//
+// frob_inv_general: Algorithm 5 (Frobenius inversion with LU), with the
+//   almost-sure shift of Algorithm 6 on demand;
+// frob_inv_hpd:     Algorithm 7 (Frobenius inversion with Cholesky);
+// frob_solve:       Algorithm 3 (linear systems, sign of step 7 corrected).
+// The complex-arithmetic baselines (Algorithms 4 and 8) live in cbase.hip.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "../../include/frobinv.h"
+#include "common.hpp"
+#include "handle.hpp"
+#include "internal.hpp"
+
+using namespace frob;
+
+namespace frob {
+
+// ------------------------------------------------------------------ handle
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double draw_mu(frob_handle* h) {
+  for (;;) {
+    const double u = (double)(splitmix64(h->rng) >> 11) * 0x1.0p-53;
+    if (u > 0.0) return u;
+  }
+}
+
+void* ws_reserve(frob_handle* h, size_t bytes) {
+  bytes += 64 * 256;  // alignment slack: sub-carves may start at unaligned offsets
+  if (bytes <= h->ws_cap) return h->ws;
+  FROB_HIP(hipStreamSynchronize(h->stream));
+  if (h->ws) FROB_HIP(hipFree(h->ws));
+  h->ws = nullptr;
+  h->ws_cap = 0;
+  const size_t cap = bytes + (bytes >> 3);
+  if (hipMalloc(&h->ws, cap) != hipSuccess) {
+    h->ws = nullptr;
+    throw std::bad_alloc();
+  }
+  h->ws_cap = cap;
+  return h->ws;
+}
+
+void read_info(frob_handle* h) {
+  FROB_HIP(hipMemcpyAsync(h->hinfo, h->dinfo, sizeof(int) * INFO_SLOTS, hipMemcpyDeviceToHost, h->stream));
+  FROB_HIP(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace frob
+
+namespace {
+
+frob_opts_t opts_or_default(const frob_opts_t* o) {
+  frob_opts_t d;
+  frob_default_opts(&d);
+  return o ? *o : d;
+}
+
+struct Status {
+  frob_status_t st;
+};
+
+template <class F>
+frob_status_t guarded(frob_handle_t h, F&& f) {
+  if (!h) return FROB_E_ARG;
+  try {
+    FROB_HIP(hipSetDevice(h->device));
+    return f();
+  } catch (const std::bad_alloc&) {
+    return FROB_E_ALLOC;
+  } catch (const HipError&) {
+    return FROB_E_HIP;
+  } catch (...) {
+    return FROB_E_INTERNAL;
+  }
+}
+
+bool bad_dims(int n, int lda) { return n < 1 || n > FROB_MAX_N || lda < n; }
+
+// ---------------------------------------------------------------------------
+// One pass of Algorithm 5 on (A, B) -> (Xr, Xi); factorization status in
+// dinfo[0] (LU of A) and dinfo[1] (LU of C).
+// ---------------------------------------------------------------------------
+struct GenWs {
+  double *F, *Y, *C, *W, *tmp;
+  int *p1, *p2;
+  int ld;
+};
+
+size_t gen_ws_bytes(int n) {
+  Carve c(nullptr);
+  const size_t nn = (size_t)n * n;
+  c.take<double>(nn); c.take<double>(nn); c.take<double>(nn); c.take<double>(nn);
+  c.take<double>(tmp_elems(n));
+  c.take<int>(n); c.take<int>(n);
+  return c.off;
+}
+
+GenWs gen_ws_carve(Carve& c, int n) {
+  GenWs w;
+  const size_t nn = (size_t)n * n;
+  w.F = c.take<double>(nn); w.Y = c.take<double>(nn); w.C = c.take<double>(nn); w.W = c.take<double>(nn);
+  w.tmp = c.take<double>(tmp_elems(n));
+  w.p1 = c.take<int>(n); w.p2 = c.take<int>(n);
+  w.ld = n;
+  return w;
+}
+
+// Steps 1-4 of Algorithm 5 (shared with Algorithm 3): LU of A, Y = A^{-1} B,
+// C = A + B Y, LU of C.
+void frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, GenWs& w, int* dinfo) {
+  const int ld = w.ld;
+  // step 1: P1 A = L1 U1
+  copy_f64(s, n, n, A, lda, nullptr, w.F, ld);
+  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0);
+  // step 2: Y = U1^{-1} L1^{-1} P1 B
+  copy_f64(s, n, n, B, ldb, w.p1, w.Y, ld);
+  DOp LU1{w.F, ld, w.p1};
+  DOut Yo{w.Y, ld, nullptr, nullptr};
+  trsm_f64(s, false, TRI_LOWER_UNIT, false, n, n, LU1, Yo);
+  trsm_f64(s, false, TRI_UPPER, false, n, n, LU1, Yo);
+  // step 3: C = A + B Y
+  copy_f64(s, n, n, A, lda, nullptr, w.C, ld);
+  gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
+           DOut{w.C, ld, nullptr, nullptr});
+  // step 4: P2 C = L2 U2   (a zero pivot here means M is singular, Lemma 2.3)
+  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1);
+}
+
+void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, double* Xr, double* Xi,
+                  int ldx, GenWs& w, int* dinfo) {
+  const int ld = w.ld;
+  frob_lu_front(s, n, A, lda, B, ldb, w, dinfo);
+  // step 5, first block row: Re X = C^{-1} = U2^{-1} L2^{-1} P2
+  DOp LU2{w.C, ld, w.p2};
+  trtri_f64(s, TRI_UPPER, false, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp, tmp_ld(n));
+  trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr});
+  permute_cols_f64(s, n, n, w.W, ld, w.p2, Xr, ldx);
+  // step 5, second block row: Im X = -Y C^{-1}
+  gemm_f64(s, false, false, n, n, n, -1.0, DOp{w.Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
+           DOut{Xi, ldx, nullptr, nullptr});
+}
+
+}  // namespace
+
+// =========================================================================== C ABI
+extern "C" {
+
+void frob_default_opts(frob_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->shift = FROB_SHIFT_AUTO;
+  o->mu = 0.0;
+  o->seed = 0;
+  o->refine = 0;
+}
+
+frob_status_t frob_create(frob_handle_t* out, int device) {
+  if (!out) return FROB_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return FROB_E_HIP;
+  if (device < 0 || device >= count) return FROB_E_ARG;
+  frob_handle* h = new (std::nothrow) frob_handle();
+  if (!h) return FROB_E_ALLOC;
+  h->device = device;
+  h->rng = 0x2208012390ull;
+  try {
+    FROB_HIP(hipSetDevice(device));
+    h->stream = nullptr;   // the device's null stream until frob_set_stream says otherwise
+    FROB_HIP(hipMalloc((void**)&h->dinfo, sizeof(int) * INFO_SLOTS));
+    FROB_HIP(hipHostMalloc((void**)&h->hinfo, sizeof(int) * INFO_SLOTS, hipHostMallocDefault));
+  } catch (...) {
+    frob_destroy(h);
+    return FROB_E_HIP;
+  }
+  *out = h;
+  return FROB_OK;
+}
+
+frob_status_t frob_destroy(frob_handle_t h) {
+  if (!h) return FROB_E_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->dinfo) (void)hipFree(h->dinfo);
+  if (h->hinfo) (void)hipHostFree(h->hinfo);
+  delete h;
+  return FROB_OK;
+}
+
+frob_status_t frob_set_stream(frob_handle_t h, void* stream) {
+  if (!h) return FROB_E_ARG;
+  h->stream = (hipStream_t)stream;
+  return FROB_OK;
+}
+
+size_t frob_workspace_bytes(frob_handle_t h) { return h ? h->ws_cap : 0; }
+
+frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                               double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.refine < 0) return FROB_E_ARG;
+  return guarded(h, [&]() -> frob_status_t {
+    if (o.seed) h->rng = o.seed;
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    Carve sz(nullptr);
+    sz.take<char>(gen_ws_bytes(n));
+    sz.take<double>(nn); sz.take<double>(nn);   // shifted A, B
+    sz.take<char>(ns_ws_bytes(n, o.refine));
+    Carve c((char*)ws_reserve(h, sz.off));
+    GenWs w = gen_ws_carve(c, n);
+    double* As = c.take<double>(nn);
+    double* Bs = c.take<double>(nn);
+    frob_result_t r;
+    std::memset(&r, 0, sizeof(r));
+    frob_status_t st = FROB_OK;
+    bool done = false;
+    if (o.shift != FROB_SHIFT_ON) {
+      fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+      frob_lu_pass(s, n, A, lda, B, ldb, Xr, Xi, ldx, w, h->dinfo);
+      read_info(h);
+      if (h->hinfo[0] == 0) {
+        done = true;
+        if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; }
+      } else if (o.shift == FROB_SHIFT_OFF) {
+        done = true;
+        st = FROB_SINGULAR; r.info = h->hinfo[0]; r.stage = 1;
+      }
+    }
+    // Algorithm 6: invert (1 + i mu) M, whose real part A - mu B is singular for
+    // at most n values of mu (Lemma 4.3), then multiply the inverse by (1 + i mu).
+    for (int attempt = 0; !done && attempt < 3; ++attempt) {
+      const double mu = (o.mu > 0.0 && attempt == 0) ? o.mu : draw_mu(h);
+      r.shifts_tried++;
+      rotate_f64(s, n, n, mu, A, lda, B, ldb, As, n, Bs, n);        // X1 = A - mu B, X2 = mu A + B
+      fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+      frob_lu_pass(s, n, As, n, Bs, n, Xr, Xi, ldx, w, h->dinfo);   // X3 + i X4 = (X1 + i X2)^{-1}
+      read_info(h);
+      if (h->hinfo[0] != 0) { r.info = h->hinfo[0]; r.stage = 1; continue; }
+      done = true;
+      r.mu_used = mu;
+      if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; break; }
+      rotate_f64(s, n, n, mu, Xr, ldx, Xi, ldx, Xr, ldx, Xi, ldx);   // X5 = X3 - mu X4, X6 = mu X3 + X4
+      r.info = 0; r.stage = 0;
+    }
+    if (!done) st = FROB_SINGULAR;
+    if (st == FROB_OK && o.refine > 0) {
+      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, c, &r);
+    } else if (st == FROB_OK) {
+      FROB_HIP(hipStreamSynchronize(s));
+    }
+    if (res) *res = r;
+    return st;
+  });
+}
+
+frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                           double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  if (o.refine < 0) return FROB_E_ARG;
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    Carve sz(nullptr);
+    for (int k = 0; k < 4; ++k) sz.take<double>(nn);
+    sz.take<double>(tmp_elems(n));
+    sz.take<char>(ns_ws_bytes(n, o.refine));
+    Carve c((char*)ws_reserve(h, sz.off));
+    double* F = c.take<double>(nn);   // R1^T (lower), later W = R2^{-T}
+    double* X1 = c.take<double>(nn);
+    double* Y = c.take<double>(nn);
+    double* Cm = c.take<double>(nn);  // C, then R2^T
+    double* tmp = c.take<double>(tmp_elems(n));
+    const int ld = n;
+    fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+    // step 1: A = R1^T R1 (stored as the lower factor L1 = R1^T)
+    copy_f64(s, n, n, A, lda, nullptr, F, ld);
+    potrf_f64(s, n, F, ld, h->dinfo + 0);
+    // steps 2-3: R1^T X1 = B (forward), R1 Y = X1 (backward)
+    copy_f64(s, n, n, B, ldb, nullptr, X1, ld);
+    trsm_f64(s, false, TRI_LOWER, false, n, n, DOp{F, ld, nullptr}, DOut{X1, ld, nullptr, nullptr});
+    copy_f64(s, n, n, X1, ld, nullptr, Y, ld);
+    trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr});
+    // steps 4-5: C = A - X1^T X1 (B skew gives B A^{-1} B = -X1^T X1), lower triangle
+    copy_f64(s, n, n, A, lda, nullptr, Cm, ld);
+    gemm_f64(s, true, false, n, n, n, -1.0, DOp{X1, ld, nullptr}, TRI_NONE, DOp{X1, ld, nullptr}, TRI_NONE, 1.0,
+             DOut{Cm, ld, nullptr, nullptr}, true);
+    // step 6: C = R2^T R2
+    potrf_f64(s, n, Cm, ld, h->dinfo + 1);
+    // steps 7-8: Re X = C^{-1} = R2^{-1} R2^{-T} = W^T W with W = (R2^T)^{-1} lower
+    trtri_f64(s, TRI_LOWER, false, n, DOp{Cm, ld, nullptr}, DOut{F, ld, nullptr, nullptr}, tmp, tmp_ld(n));
+    gemm_f64(s, true, false, n, n, n, 1.0, DOp{F, ld, nullptr}, TRI_UPPER, DOp{F, ld, nullptr}, TRI_LOWER, 0.0,
+             DOut{Xr, ldx, nullptr, nullptr}, true);
+    mirror_lower_f64(s, n, Xr, ldx, 1.0);
+    // step 9: Im X = -Y C^{-1}
+    gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
+             DOut{Xi, ldx, nullptr, nullptr});
+    read_info(h);
+    frob_result_t r;
+    std::memset(&r, 0, sizeof(r));
+    frob_status_t st = FROB_OK;
+    if (h->hinfo[0]) { st = FROB_NOT_HPD; r.info = h->hinfo[0]; r.stage = 1; }
+    else if (h->hinfo[1]) { st = FROB_NOT_HPD; r.info = h->hinfo[1]; r.stage = 2; }
+    if (st == FROB_OK && o.refine > 0) st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, c, &r);
+    if (res) *res = r;
+    return st;
+  });
+}
+
+frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int lda, const double* B, int ldb,
+                         const double* cv, const double* dv, int ldc, double* x, double* y, int ldxy,
+                         const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !cv || !dv || !x || !y || bad_dims(n, lda) || ldb < n || nrhs < 1 || ldc < nrhs ||
+      ldxy < nrhs)
+    return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON) return FROB_E_ARG;
+  return guarded(h, [&]() -> frob_status_t {
+    if (o.seed) h->rng = o.seed;
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    const int q = 2 * nrhs;
+    Carve sz(nullptr);
+    sz.take<char>(gen_ws_bytes(n));
+    sz.take<double>(nn); sz.take<double>(nn);
+    sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q);
+    Carve c((char*)ws_reserve(h, sz.off));
+    GenWs w = gen_ws_carve(c, n);
+    double* As = c.take<double>(nn);
+    double* Bs = c.take<double>(nn);
+    double* Z = c.take<double>((size_t)n * q);   // [x1 y1]
+    double* V = c.take<double>((size_t)n * q);   // [y1 x1]
+    double* T = c.take<double>((size_t)n * q);   // [x2 y2]
+    frob_result_t r;
+    std::memset(&r, 0, sizeof(r));
+
+    // (1 + i mu) M (x + iy) = (1 + i mu)(c + id): solve the shifted system with
+    // right-hand side c' = c - mu d, d' = mu c + d; the solution is unchanged.
+    auto pass = [&](const double* Au, int ldA, const double* Bu, int ldB, double mu) {
+      fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+      frob_lu_front(s, n, Au, ldA, Bu, ldB, w, h->dinfo);
+      // step 5: L2 U2 [x1 y1] = P2 [c d]
+      copy_f64(s, n, nrhs, cv, ldc, w.p2, Z, q);
+      copy_f64(s, n, nrhs, dv, ldc, w.p2, Z + nrhs, q);
+      if (mu != 0.0) {
+        // rows were gathered by p2 in both halves; rotate them in place
+        rotate_f64(s, n, nrhs, mu, Z, q, Z + nrhs, q, Z, q, Z + nrhs, q);
+      }
+      DOp LU2{w.C, w.ld, w.p2};
+      trsm_f64(s, false, TRI_LOWER_UNIT, false, n, q, LU2, DOut{Z, q, nullptr, nullptr});
+      trsm_f64(s, false, TRI_UPPER, false, n, q, LU2, DOut{Z, q, nullptr, nullptr});
+      // step 6: [x2 y2] = A^{-1} B [y1 x1] = Y [y1 x1]
+      copy_f64(s, n, nrhs, Z + nrhs, q, nullptr, V, q);
+      copy_f64(s, n, nrhs, Z, q, nullptr, V + nrhs, q);
+      gemm_f64(s, false, false, n, q, n, 1.0, DOp{w.Y, w.ld, nullptr}, TRI_NONE, DOp{V, q, nullptr}, TRI_NONE, 0.0,
+               DOut{T, q, nullptr, nullptr});
+      // step 7: x = x1 + x2, y = y1 - y2
+      copy_f64(s, n, nrhs, Z, q, nullptr, x, ldxy);
+      axpby_f64(s, n, nrhs, 1.0, T, q, 1.0, x, ldxy);
+      copy_f64(s, n, nrhs, Z + nrhs, q, nullptr, y, ldxy);
+      axpby_f64(s, n, nrhs, -1.0, T + nrhs, q, 1.0, y, ldxy);
+      read_info(h);
+    };
+    frob_status_t st = FROB_OK;
+    bool done = false;
+    if (o.shift != FROB_SHIFT_ON) {
+      pass(A, lda, B, ldb, 0.0);
+      if (h->hinfo[0] == 0) {
+        done = true;
+        if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; }
+      } else if (o.shift == FROB_SHIFT_OFF) {
+        done = true;
+        st = FROB_SINGULAR; r.info = h->hinfo[0]; r.stage = 1;
+      }
+    }
+    for (int attempt = 0; !done && attempt < 3; ++attempt) {
+      const double mu = (o.mu > 0.0 && attempt == 0) ? o.mu : draw_mu(h);
+      r.shifts_tried++;
+      rotate_f64(s, n, n, mu, A, lda, B, ldb, As, n, Bs, n);
+      pass(As, n, Bs, n, mu);
+      if (h->hinfo[0] != 0) { r.info = h->hinfo[0]; r.stage = 1; continue; }
+      done = true;
+      r.mu_used = mu;
+      r.info = 0; r.stage = 0;
+      if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; }
+    }
+    if (!done) st = FROB_SINGULAR;
+    if (res) *res = r;
+    return st;
+  });
+}
+
+const char* frob_status_string(frob_status_t s) {
+  switch (s) {
+    case FROB_OK: return "FROB_OK";
+    case FROB_SINGULAR: return "FROB_SINGULAR";
+    case FROB_NOT_HPD: return "FROB_NOT_HPD";
+    case FROB_NO_CONVERGENCE: return "FROB_NO_CONVERGENCE";
+    case FROB_E_ARG: return "FROB_E_ARG";
+    case FROB_E_ALLOC: return "FROB_E_ALLOC";
+    case FROB_E_HIP: return "FROB_E_HIP";
+    case FROB_E_INTERNAL: return "FROB_E_INTERNAL";
+  }
+  return "FROB_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// internal.hpp -- launchers and drivers shared between the translation units of
+// libfrobinv.  Nothing here is part of the public C ABI (include/frobinv.h).
+#pragma once
+
+#include "common.hpp"
+
+namespace frob {
+
+// ----------------------------------------------------------------- GEMM (FP64)
+enum { GEMM_CFG_128x128 = 0, GEMM_CFG_64x64 = 1, GEMM_CFG_128x32 = 2, GEMM_CFG_32x128 = 3 };
+// GEMM_NEED_FULL_M: one block row must cover all of M (in-place left products);
+// GEMM_NEED_FULL_N: one block column must cover all of N (in-place right products).
+enum { GEMM_NEED_ANY = 0, GEMM_NEED_FULL_M = 1, GEMM_NEED_FULL_N = 2 };
+int gemm_pick_cfg(int M, int N, int need);
+
+// C = alpha op(A) op(B) + beta C, see gemm_f64.hip.
+void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
+              int triB, double beta, DOut C, bool lowerOnly = false, int batch = 1, long long sA = 0,
+              long long sB = 0, long long sC = 0, int need = GEMM_NEED_ANY);
+
+// Planar complex GEMM, C = alpha op(A) op(B) + beta C with real alpha/beta and
+// op in {N, T, C (conjugate transpose)}; four real MFMA products per tile.
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+void gemm_z64(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha, ZOp A, int triA, ZOp B,
+              int triB, double beta, ZOut C, bool lowerOnly = false, int need = GEMM_NEED_ANY);
+
+// ------------------------------------------------------- small triangular solves
+// In-place solve with a triangle of order nt <= 64 (one LDS-resident block):
+//   left:  op(T) X = B   (B is nt x nr),   right: X op(T) = B  (B is nr x nt).
+// `tri` describes op(T) (lower/upper, unit/non-unit) in logical coordinates;
+// `trans` selects op(T) = T^T.  If `identity` is set the right-hand side is the
+// identity (B is then output only, nr = nt).
+void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, bool identity);
+void trsm_small_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B, bool identity);
+
+// --------------------------------------------------- blocked triangular drivers
+// Recursive triangular solve (left or right) built from the small solves and
+// GEMM updates.  Arguments as for trsm_small_*, any order nt.
+void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B);
+void trsm_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B);
+// W = op(T)^{-1} for a triangle of order n into a separate dense buffer W
+// (only W's triangle is meaningful).  tmp must hold n*n/4 (+slack) entries.
+void trtri_f64(hipStream_t s, int tri, bool trans, int n, DOp T, DOut W, double* tmp, int ldtmp);
+void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, ZOut W, double* tmp_re, double* tmp_im, int ldtmp);
+
+// ------------------------------------------------------------- factorizations
+// LU with partial pivoting of the n x n matrix a (row-major, lda), in place,
+// pivoting through the index array perm (initialised to the identity here):
+// logical row i of P A = L U lives in physical row perm[i].  *info (device)
+// receives the 1-based column of the first exactly-zero pivot or stays 0.
+void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info);
+void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info);
+// Cholesky A = L L^T (lower, in place in the lower triangle of a; the strict
+// upper triangle is not referenced).  *info receives the 1-based index of the
+// first non-positive pivot.
+void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info);
+void potrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* info);
+
+// ------------------------------------------------------------ elementwise ops
+void iota_i32(hipStream_t s, int n, int* p);
+void fill_i32(hipStream_t s, int n, int v, int* p);
+void copy_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* src_rows, double* dst, int ldd);
+void fill_f64(hipStream_t s, int m, int n, double v, double* dst, int ldd);
+void identity_f64(hipStream_t s, int n, double* dst, int ldd);
+// Y = a X + b Y  (m x n)
+void axpby_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, double* Y, int ldy);
+// (X1, X2) = (A - mu B, mu A + B): shift in; used in-place-safe on distinct buffers
+void rotate_f64(hipStream_t s, int m, int n, double mu, const double* A, int lda, const double* B, int ldb,
+                double* X1, int ld1, double* X2, int ld2);
+// dst[:, perm[k]] = src[:, k]
+void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* perm, double* dst,
+                      int ldd);
+// Mirror the strict lower triangle into the upper one: a[j][i] = sign * a[i][j]
+void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign);
+// Zero the strict upper triangle
+void zero_upper_f64(hipStream_t s, int n, double* a, int lda);
+
+}  // namespace frob

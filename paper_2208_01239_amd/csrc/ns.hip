@@ -1,0 +1,68 @@
+// ns.hip -- Newton-Schulz refinement of a computed inverse in FP64.
+//
+//   R = I - M X,   X <- X + X R,     so that I - M X_new = (I - M X)^2.
+//
+// Both complex products are formed from three real matrix-core GEMMs with
+// Gauss's scheme (Proposition 2.2 with tau = 1):
+//   (P + iQ)(S + iT):  M1 = (P - Q)(S + T), M2 = P T, M3 = Q S,
+//                      real = M1 - M2 + M3, imag = M2 + M3.
+#include "common.hpp"
+#include "handle.hpp"
+#include "internal.hpp"
+
+namespace frob {
+
+size_t ns_ws_bytes(int n, int steps) {
+  if (steps <= 0) return 0;
+  Carve c(nullptr);
+  for (int k = 0; k < 6; ++k) c.take<double>((size_t)n * n);
+  return c.off;
+}
+
+// (Zr, Zi) = (Pr + i Pi)(Sr + i Si) via three GEMMs; T1, T2 scratch n x n.
+static void gauss3m(hipStream_t s, int n, const double* Pr, int ldp, const double* Pi, const double* Sr, int lds,
+                    const double* Si, double* Zr, double* Zi, int ldz, double* T1, double* T2) {
+  const int ld = n;
+  // T1 = P_r - P_i, T2 = S_r + S_i
+  copy_f64(s, n, n, Pr, ldp, nullptr, T1, ld);
+  axpby_f64(s, n, n, -1.0, Pi, ldp, 1.0, T1, ld);
+  copy_f64(s, n, n, Sr, lds, nullptr, T2, ld);
+  axpby_f64(s, n, n, 1.0, Si, lds, 1.0, T2, ld);
+  // Zi = M2 = P_r S_i ; Zr = M3 = P_i S_r
+  gemm_f64(s, false, false, n, n, n, 1.0, DOp{Pr, ldp, nullptr}, TRI_NONE, DOp{Si, lds, nullptr}, TRI_NONE, 0.0,
+           DOut{Zi, ldz, nullptr, nullptr});
+  gemm_f64(s, false, false, n, n, n, 1.0, DOp{Pi, ldp, nullptr}, TRI_NONE, DOp{Sr, lds, nullptr}, TRI_NONE, 0.0,
+           DOut{Zr, ldz, nullptr, nullptr});
+  // (Zr, Zi) <- (M3 - M2, M3 + M2), elementwise from the old values
+  rotate_f64(s, n, n, 1.0, Zr, ldz, Zi, ldz, Zr, ldz, Zi, ldz);
+  gemm_f64(s, false, false, n, n, n, 1.0, DOp{T1, ld, nullptr}, TRI_NONE, DOp{T2, ld, nullptr}, TRI_NONE, 1.0,
+           DOut{Zr, ldz, nullptr, nullptr});                        // Zr += M1
+}
+
+frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                        double* Xi, int ldx, int steps, Carve& c, frob_result_t* r) {
+  hipStream_t s = h->stream;
+  const size_t nn = (size_t)n * n;
+  double* Rr = c.take<double>(nn);
+  double* Ri = c.take<double>(nn);
+  double* Ur = c.take<double>(nn);
+  double* Ui = c.take<double>(nn);
+  double* T1 = c.take<double>(nn);
+  double* T2 = c.take<double>(nn);
+  for (int k = 0; k < steps; ++k) {
+    // (Rr, Ri) = M X ; then R = I - M X
+    gauss3m(s, n, A, lda, B, Xr, ldx, Xi, Rr, Ri, n, T1, T2);
+    identity_f64(s, n, Ur, n);
+    axpby_f64(s, n, n, 1.0, Ur, n, -1.0, Rr, n);                   // Rr = I - Re(M X)
+    axpby_f64(s, n, n, 0.0, Ur, n, -1.0, Ri, n);                   // Ri = -Im(M X)
+    // (Ur, Ui) = X R ; X += X R
+    gauss3m(s, n, Xr, ldx, Xi, Rr, n, Ri, Ur, Ui, n, T1, T2);
+    axpby_f64(s, n, n, 1.0, Ur, n, 1.0, Xr, ldx);
+    axpby_f64(s, n, n, 1.0, Ui, n, 1.0, Xi, ldx);
+  }
+  FROB_HIP(hipStreamSynchronize(s));
+  r->refine_steps = steps;
+  return FROB_OK;
+}
+
+}  // namespace frob
