@@ -138,6 +138,17 @@ frob_status_t frob_cinv_lu(frob_handle_t handle, int n, const double *Mr, const 
 frob_status_t frob_cinv_chol(frob_handle_t handle, int n, const double *Mr, const double *Mi, int ldm, double *Xr,
                              double *Xi, int ldx, int form, frob_result_t *res);
 
+/* Kernel timing with HIP events (for measurement).  When enabled, the library
+ * records an event pair on the handle's stream around every launch of a
+ * kernel class and accumulates, per class, the number of launches, their
+ * summed duration in milliseconds and their algorithmic FP64 flop count.
+ * Class 0: the n x n x n matrix-core GEMMs of the inversion paths (B Y and
+ * -Y C^{-1}).  Enabling resets the counters.  Reading is valid after a call
+ * returned (its final synchronization resolves the events). */
+frob_status_t frob_profile_enable(frob_handle_t handle, int on);
+frob_status_t frob_profile_read(frob_handle_t handle, int kernel_class, long long *launches, double *total_ms,
+                                double *flops);
+
 /* Human-readable name of a status code (static string). */
 const char *frob_status_string(frob_status_t status);
 

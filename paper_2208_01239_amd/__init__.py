@@ -62,6 +62,17 @@ class Handle:
     def workspace_bytes(self) -> int:
         return int(_lib.load().frob_workspace_bytes(self.ptr))
 
+    def profile(self, on: bool = True):
+        """Enable (and reset) or disable HIP-event timing of kernel classes."""
+        _lib.check(_lib.load().frob_profile_enable(self.ptr, 1 if on else 0), "frob_profile_enable")
+
+    def profile_read(self, kernel_class: int = 0):
+        """(launches, total_ms, flops) accumulated for a kernel class."""
+        n, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().frob_profile_read(self.ptr, int(kernel_class), ctypes.byref(n), ctypes.byref(ms),
+                                                 ctypes.byref(fl)), "frob_profile_read")
+        return int(n.value), float(ms.value), float(fl.value)
+
     def bind_stream(self, stream=None):
         import torch
         s = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -61,6 +61,9 @@ SIGNATURES = {
     "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
+    "frob_profile_enable": (_i, [_vp, _i]),
+    "frob_profile_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_d),
+                               ctypes.POINTER(_d)]),
     "frob_status_string": (ctypes.c_char_p, [_i]),
 }
 

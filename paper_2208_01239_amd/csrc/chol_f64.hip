@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_potrf_small_f64(double* a, int lda, int
   }
 }
 
-void potrf_rec(hipStream_t s, double* a, int lda, int n, int k0, int* info) {
+void potrf_rec(hipStream_t s, double* a, int lda, int n, int k0, int* info, double* work) {
   if (n <= CB) {
     hipLaunchKernelGGL(k_potrf_small_f64, dim3(1), dim3(256), 0, s, a, lda, n, k0, info);
     FROB_LAUNCH_CHECK();
@@ -63,23 +63,25 @@ void potrf_rec(hipStream_t s, double* a, int lda, int n, int k0, int* info) {
   int n1 = (n / 2 + CB - 1) / CB * CB;
   if (n1 >= n) n1 = n - CB;
   const int n2 = n - n1;
-  potrf_rec(s, a, lda, n1, k0, info);
+  potrf_rec(s, a, lda, n1, k0, info, work);
   // L21 = A21 L11^{-T}:  X op(T) = B with T = L11 (stored lower), op = transpose (upper)
   DOp L11{a, lda, nullptr};
   DOut A21{a + (long long)n1 * lda, lda, nullptr, nullptr};
-  trsm_f64(s, true, TRI_UPPER, true, n1, n2, L11, A21);
+  trsm_f64(s, true, TRI_UPPER, true, n1, n2, L11, A21, work);
   // A22 -= L21 L21^T, lower triangle only
   DOp L21{a + (long long)n1 * lda, lda, nullptr};
   DOut A22{a + (long long)n1 * lda + n1, lda, nullptr, nullptr};
   gemm_f64(s, false, true, n2, n2, n1, -1.0, L21, TRI_NONE, L21, TRI_NONE, 1.0, A22, true);
-  potrf_rec(s, a + (long long)n1 * lda + n1, lda, n2, k0 + n1, info);
+  potrf_rec(s, a + (long long)n1 * lda + n1, lda, n2, k0 + n1, info, work);
 }
 
 }  // namespace
 
-void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info) {
+size_t potrf_work_elems(int n) { return trsm_work_elems(n / 2 + CB); }
+
+void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info, double* work) {
   if (n <= 0) return;
-  potrf_rec(s, a, lda, n, 0, info);
+  potrf_rec(s, a, lda, n, 0, info, work);
 }
 
 }  // namespace frob

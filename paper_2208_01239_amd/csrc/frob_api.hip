@@ -49,9 +49,59 @@ void* ws_reserve(frob_handle* h, size_t bytes) {
   return h->ws;
 }
 
+size_t solver_work_elems(int n) {
+  size_t w = trsm_work_elems(n);
+  w = std::max(w, getrf_work_elems(n));
+  w = std::max(w, potrf_work_elems(n));
+  w = std::max(w, trtri_tmp_elems(n));
+  return w;
+}
+
 void read_info(frob_handle* h) {
   FROB_HIP(hipMemcpyAsync(h->hinfo, h->dinfo, sizeof(int) * INFO_SLOTS, hipMemcpyDeviceToHost, h->stream));
   FROB_HIP(hipStreamSynchronize(h->stream));
+  prof_resolve(h);
+}
+
+static hipEvent_t prof_event(frob_handle* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  FROB_HIP(hipEventCreate(&e));
+  return e;
+}
+
+ProfScope::ProfScope(frob_handle* hh, int c, double fl) : h(hh), cls(c), flops(fl) {
+  if (!h || !h->prof) return;
+  e0 = prof_event(h);
+  FROB_HIP(hipEventRecord(e0, h->stream));
+}
+
+ProfScope::~ProfScope() {
+  if (!h || !h->prof || !e0) return;
+  try {
+    hipEvent_t e1 = prof_event(h);
+    if (hipEventRecord(e1, h->stream) != hipSuccess) return;
+    h->pending.push_back({e0, e1, cls, flops});
+  } catch (...) {
+  }
+}
+
+void prof_resolve(frob_handle* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      h->prof_ms[p.cls] += ms;
+      h->prof_flops[p.cls] += p.flops;
+      h->prof_count[p.cls] += 1;
+    }
+    h->pool.push_back(p.e0);
+    h->pool.push_back(p.e1);
+  }
+  h->pending.clear();
 }
 
 }  // namespace frob
@@ -93,13 +143,14 @@ struct GenWs {
   double *F, *Y, *C, *W, *tmp;
   int *p1, *p2;
   int ld;
+  frob_handle* h;
 };
 
 size_t gen_ws_bytes(int n) {
   Carve c(nullptr);
   const size_t nn = (size_t)n * n;
   c.take<double>(nn); c.take<double>(nn); c.take<double>(nn); c.take<double>(nn);
-  c.take<double>(tmp_elems(n));
+  c.take<double>(solver_work_elems(n));
   c.take<int>(n); c.take<int>(n);
   return c.off;
 }
@@ -108,9 +159,10 @@ GenWs gen_ws_carve(Carve& c, int n) {
   GenWs w;
   const size_t nn = (size_t)n * n;
   w.F = c.take<double>(nn); w.Y = c.take<double>(nn); w.C = c.take<double>(nn); w.W = c.take<double>(nn);
-  w.tmp = c.take<double>(tmp_elems(n));
+  w.tmp = c.take<double>(solver_work_elems(n));
   w.p1 = c.take<int>(n); w.p2 = c.take<int>(n);
   w.ld = n;
+  w.h = nullptr;
   return w;
 }
 
@@ -120,19 +172,22 @@ void frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double*
   const int ld = w.ld;
   // step 1: P1 A = L1 U1
   copy_f64(s, n, n, A, lda, nullptr, w.F, ld);
-  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0);
+  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0, w.tmp);
   // step 2: Y = U1^{-1} L1^{-1} P1 B
   copy_f64(s, n, n, B, ldb, w.p1, w.Y, ld);
   DOp LU1{w.F, ld, w.p1};
   DOut Yo{w.Y, ld, nullptr, nullptr};
-  trsm_f64(s, false, TRI_LOWER_UNIT, false, n, n, LU1, Yo);
-  trsm_f64(s, false, TRI_UPPER, false, n, n, LU1, Yo);
+  trsm_f64(s, false, TRI_LOWER_UNIT, false, n, n, LU1, Yo, w.tmp);
+  trsm_f64(s, false, TRI_UPPER, false, n, n, LU1, Yo, w.tmp);
   // step 3: C = A + B Y
   copy_f64(s, n, n, A, lda, nullptr, w.C, ld);
-  gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
-           DOut{w.C, ld, nullptr, nullptr});
+  {
+    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+    gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
+             DOut{w.C, ld, nullptr, nullptr});
+  }
   // step 4: P2 C = L2 U2   (a zero pivot here means M is singular, Lemma 2.3)
-  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1);
+  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1, w.tmp);
 }
 
 void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, double* Xr, double* Xi,
@@ -141,12 +196,15 @@ void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* 
   frob_lu_front(s, n, A, lda, B, ldb, w, dinfo);
   // step 5, first block row: Re X = C^{-1} = U2^{-1} L2^{-1} P2
   DOp LU2{w.C, ld, w.p2};
-  trtri_f64(s, TRI_UPPER, false, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp, tmp_ld(n));
-  trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr});
+  trtri_f64(s, TRI_UPPER, false, n, LU2, w.W, ld, w.tmp);
+  trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp);
   permute_cols_f64(s, n, n, w.W, ld, w.p2, Xr, ldx);
   // step 5, second block row: Im X = -Y C^{-1}
-  gemm_f64(s, false, false, n, n, n, -1.0, DOp{w.Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
-           DOut{Xi, ldx, nullptr, nullptr});
+  {
+    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+    gemm_f64(s, false, false, n, n, n, -1.0, DOp{w.Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
+             DOut{Xi, ldx, nullptr, nullptr});
+  }
 }
 
 }  // namespace
@@ -193,6 +251,8 @@ frob_status_t frob_destroy(frob_handle_t h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->dinfo) (void)hipFree(h->dinfo);
   if (h->hinfo) (void)hipHostFree(h->hinfo);
+  for (auto& p : h->pending) { (void)hipEventDestroy(p.e0); (void)hipEventDestroy(p.e1); }
+  for (auto e : h->pool) (void)hipEventDestroy(e);
   delete h;
   return FROB_OK;
 }
@@ -220,6 +280,7 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
     sz.take<char>(ns_ws_bytes(n, o.refine));
     Carve c((char*)ws_reserve(h, sz.off));
     GenWs w = gen_ws_carve(c, n);
+    w.h = h;
     double* As = c.take<double>(nn);
     double* Bs = c.take<double>(nn);
     frob_result_t r;
@@ -275,38 +336,41 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     const size_t nn = (size_t)n * n;
     Carve sz(nullptr);
     for (int k = 0; k < 4; ++k) sz.take<double>(nn);
-    sz.take<double>(tmp_elems(n));
+    sz.take<double>(solver_work_elems(n));
     sz.take<char>(ns_ws_bytes(n, o.refine));
     Carve c((char*)ws_reserve(h, sz.off));
     double* F = c.take<double>(nn);   // R1^T (lower), later W = R2^{-T}
     double* X1 = c.take<double>(nn);
     double* Y = c.take<double>(nn);
     double* Cm = c.take<double>(nn);  // C, then R2^T
-    double* tmp = c.take<double>(tmp_elems(n));
+    double* tmp = c.take<double>(solver_work_elems(n));
     const int ld = n;
     fill_i32(s, INFO_SLOTS, 0, h->dinfo);
     // step 1: A = R1^T R1 (stored as the lower factor L1 = R1^T)
     copy_f64(s, n, n, A, lda, nullptr, F, ld);
-    potrf_f64(s, n, F, ld, h->dinfo + 0);
+    potrf_f64(s, n, F, ld, h->dinfo + 0, tmp);
     // steps 2-3: R1^T X1 = B (forward), R1 Y = X1 (backward)
     copy_f64(s, n, n, B, ldb, nullptr, X1, ld);
-    trsm_f64(s, false, TRI_LOWER, false, n, n, DOp{F, ld, nullptr}, DOut{X1, ld, nullptr, nullptr});
+    trsm_f64(s, false, TRI_LOWER, false, n, n, DOp{F, ld, nullptr}, DOut{X1, ld, nullptr, nullptr}, tmp);
     copy_f64(s, n, n, X1, ld, nullptr, Y, ld);
-    trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr});
+    trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr}, tmp);
     // steps 4-5: C = A - X1^T X1 (B skew gives B A^{-1} B = -X1^T X1), lower triangle
     copy_f64(s, n, n, A, lda, nullptr, Cm, ld);
     gemm_f64(s, true, false, n, n, n, -1.0, DOp{X1, ld, nullptr}, TRI_NONE, DOp{X1, ld, nullptr}, TRI_NONE, 1.0,
              DOut{Cm, ld, nullptr, nullptr}, true);
     // step 6: C = R2^T R2
-    potrf_f64(s, n, Cm, ld, h->dinfo + 1);
+    potrf_f64(s, n, Cm, ld, h->dinfo + 1, tmp);
     // steps 7-8: Re X = C^{-1} = R2^{-1} R2^{-T} = W^T W with W = (R2^T)^{-1} lower
-    trtri_f64(s, TRI_LOWER, false, n, DOp{Cm, ld, nullptr}, DOut{F, ld, nullptr, nullptr}, tmp, tmp_ld(n));
+    trtri_f64(s, TRI_LOWER, false, n, DOp{Cm, ld, nullptr}, F, ld, tmp);
     gemm_f64(s, true, false, n, n, n, 1.0, DOp{F, ld, nullptr}, TRI_UPPER, DOp{F, ld, nullptr}, TRI_LOWER, 0.0,
              DOut{Xr, ldx, nullptr, nullptr}, true);
     mirror_lower_f64(s, n, Xr, ldx, 1.0);
     // step 9: Im X = -Y C^{-1}
-    gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
-             DOut{Xi, ldx, nullptr, nullptr});
+    {
+      ProfScope ps(h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+      gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
+               DOut{Xi, ldx, nullptr, nullptr});
+    }
     read_info(h);
     frob_result_t r;
     std::memset(&r, 0, sizeof(r));
@@ -338,6 +402,7 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
     sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q);
     Carve c((char*)ws_reserve(h, sz.off));
     GenWs w = gen_ws_carve(c, n);
+    w.h = h;
     double* As = c.take<double>(nn);
     double* Bs = c.take<double>(nn);
     double* Z = c.take<double>((size_t)n * q);   // [x1 y1]
@@ -359,8 +424,8 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
         rotate_f64(s, n, nrhs, mu, Z, q, Z + nrhs, q, Z, q, Z + nrhs, q);
       }
       DOp LU2{w.C, w.ld, w.p2};
-      trsm_f64(s, false, TRI_LOWER_UNIT, false, n, q, LU2, DOut{Z, q, nullptr, nullptr});
-      trsm_f64(s, false, TRI_UPPER, false, n, q, LU2, DOut{Z, q, nullptr, nullptr});
+      trsm_f64(s, false, TRI_LOWER_UNIT, false, n, q, LU2, DOut{Z, q, nullptr, nullptr}, w.tmp);
+      trsm_f64(s, false, TRI_UPPER, false, n, q, LU2, DOut{Z, q, nullptr, nullptr}, w.tmp);
       // step 6: [x2 y2] = A^{-1} B [y1 x1] = Y [y1 x1]
       copy_f64(s, n, nrhs, Z + nrhs, q, nullptr, V, q);
       copy_f64(s, n, nrhs, Z, q, nullptr, V + nrhs, q);
@@ -399,6 +464,24 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
     if (!done) st = FROB_SINGULAR;
     if (res) *res = r;
     return st;
+  });
+}
+
+frob_status_t frob_profile_enable(frob_handle_t h, int on) {
+  if (!h) return FROB_E_ARG;
+  h->prof = on ? 1 : 0;
+  for (int k = 0; k < 16; ++k) { h->prof_ms[k] = 0; h->prof_flops[k] = 0; h->prof_count[k] = 0; }
+  return FROB_OK;
+}
+
+frob_status_t frob_profile_read(frob_handle_t h, int cls, long long* launches, double* total_ms, double* flops) {
+  if (!h || cls < 0 || cls >= 16) return FROB_E_ARG;
+  return guarded(h, [&]() -> frob_status_t {
+    prof_resolve(h);
+    if (launches) *launches = h->prof_count[cls];
+    if (total_ms) *total_ms = h->prof_ms[cls];
+    if (flops) *flops = h->prof_flops[cls];
+    return FROB_OK;
   });
 }
 

@@ -3,22 +3,24 @@
 //   C = alpha * op(A) * op(B) + beta * C       (row-major, op = N or T)
 //
 // with optional row indirection on A, B and C, an optional column scatter on
-// C, triangular interpretation of op(A)/op(B) (entries outside the triangle are
-// read as zero and skipped along k, a unit diagonal reads as one), a
-// lower-triangle-only output mode, and a batch index on blockIdx.z.  This one
-// kernel serves the trailing updates of the factorizations (row-indirect NN),
-// the triangular solves and inverses (trmm-like products), the symmetric
-// rank-k updates (lower-only), and the plain products B*Y and -Y*C^{-1}.
+// C, triangular interpretation of op(A)/op(B) (entries outside the triangle
+// read as zero and the k range is clipped to the triangle, a unit diagonal
+// reads as one), a lower-triangle-only output mode, and a batch index on
+// blockIdx.z.  This one kernel serves the trailing updates of the
+// factorizations (row-indirect NN), the triangular solves and inverses
+// (trmm-like products), the symmetric rank-k updates (lower-only), and the
+// plain products B*Y and -Y*C^{-1}.
 //
 // Tiling: 256 threads = 4 wave64s, block tile BM x BN, k-step 16.  Each wave
 // owns a (BM/WM) x (BN/WN) sub-tile built from 16x16 v_mfma_f64_16x16x4f64
-// tiles.  Operand tiles are staged through LDS in the same orientation as in
-// HBM (no transposition on the way in; the fragment read indexing handles op),
-// with padding chosen so the 16-lane fragment reads hit distinct banks.  The
-// next k-tile is fetched into registers while the current one is multiplied.
-// Linear block ids are remapped so that each of the 8 XCDs (hardware assigns
-// block b to XCD b % 8) works on a contiguous band of tiles, which keeps the
-// shared A rows in that XCD's L2.
+// tiles.  Operand tiles are staged through a double-buffered LDS ring in the
+// same orientation as in HBM (the fragment read indexing applies op), so a
+// k-step costs one workgroup barrier; the next tile's global loads (16-byte
+// when the operand is 16-byte aligned with an even leading dimension) are in
+// flight while the current tile is multiplied.  Padding keeps the 16-lane
+// fragment reads on distinct banks.  Linear block ids are remapped so that
+// each of the 8 XCDs (hardware assigns block b to XCD b % 8) works on a
+// contiguous band of tiles, which keeps the shared A rows in that XCD's L2.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -31,7 +33,9 @@ struct GemmF64Params {
   DOut C;
   int triA, triB;
   int lowerOnly;
-  long long sA, sB, sC;
+  int vecA, vecB;
+  long long sA, sB, sC;      // batch strides of the data pointers
+  int rsA, rsB, rsC;         // batch strides of the row-index pointers
   int tilesM, tilesN;
 };
 
@@ -46,21 +50,40 @@ __device__ __forceinline__ double tri_mask(double v, int tri, int r, int c) {
   }
 }
 
+// two consecutive doubles p[0], p[1]; n_ok = how many of them are in range (0..2)
+__device__ __forceinline__ void load2(const double* p, int n_ok, bool vec, double& x, double& y) {
+  if (n_ok >= 2) {
+    if (vec) {
+      const double2 t = *reinterpret_cast<const double2*>(p);
+      x = t.x; y = t.y;
+    } else {
+      x = p[0]; y = p[1];
+    }
+  } else if (n_ok == 1) {
+    x = p[0]; y = 0.0;
+  } else {
+    x = 0.0; y = 0.0;
+  }
+}
+
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
   static_assert(WM * WN == 4, "four waves");
   static_assert(FM >= 1 && FN >= 1, "tile too small");
-  constexpr int A_LD = TA ? (BM + 16) : (BK + 1);
+  static_assert(BM >= 32 && BN >= 32, "tile sides must be >= 32");
+  // A tile: !TA row-band [BM][BK+2]; TA k-band [BK][BM+16]
+  constexpr int A_LD = TA ? (BM + 16) : (BK + 2);
   constexpr int A_SZ = TA ? BK * A_LD : BM * A_LD;
-  constexpr int B_LD = TB ? (BK + 1) : (BN + 16);
+  // B tile: !TB k-band [BK][BN+16]; TB row-band [BN][BK+2]
+  constexpr int B_LD = TB ? (BK + 2) : (BN + 16);
   constexpr int B_SZ = TB ? BN * B_LD : BK * B_LD;
-  constexpr int A_PER = BM * BK / 256;
-  constexpr int B_PER = BN * BK / 256;
-  __shared__ double As[A_SZ];
-  __shared__ double Bs[B_SZ];
+  // pairs per thread per tile
+  constexpr int A_P = BM * BK / 512;
+  constexpr int B_P = BN * BK / 512;
+  __shared__ __attribute__((aligned(16))) double smem[2 * (A_SZ + B_SZ)];
 
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
@@ -75,9 +98,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
   const double* __restrict__ Ap = g.A.p + z * g.sA;
   const double* __restrict__ Bp = g.B.p + z * g.sB;
   double* __restrict__ Cp = g.C.p + z * g.sC;
+  const int* __restrict__ rA = g.A.rows ? g.A.rows + z * g.rsA : nullptr;
+  const int* __restrict__ rB = g.B.rows ? g.B.rows + z * g.rsB : nullptr;
+  const int* __restrict__ rC = g.C.rows ? g.C.rows + z * g.rsC : nullptr;
   const int M = g.M, N = g.N;
+  const bool vecA = g.vecA != 0, vecB = g.vecB != 0;
 
-  // k range that can hold non-zero products for this tile
   int kbeg = 0, kend = g.K;
   if (g.triA == TRI_UPPER || g.triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
   if (g.triA == TRI_LOWER || g.triA == TRI_LOWER_UNIT) kend = min(kend, bm0 + BM);
@@ -91,60 +117,118 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
   const int wm0 = (w / WN) * (BM / WM);
   const int wn0 = (w % WN) * (BN / WN);
 
-  double ra[A_PER], rb[B_PER];
+  // ---- per-thread load coordinates (fixed across k-steps) ----
+  // row-band: 8 pairs per 16-wide row, 32 rows per pass; k-band: C/2 pairs per row
+  const double* aRow[TA ? 1 : A_P];  // !TA: row pointers of A (rows fixed across k)
+  int aRowOk[TA ? 1 : A_P];
+  const double* bRow[TB ? B_P : 1];  // TB: row pointers of B
+  int bRowOk[TB ? B_P : 1];
+  if (!TA) {
+#pragma unroll
+    for (int p = 0; p < A_P; ++p) {
+      const int gi = bm0 + tid / 8 + 32 * p;
+      aRowOk[p] = gi < M;
+      const int pr = gi < M ? (rA ? rA[gi] : gi) : 0;
+      aRow[p] = Ap + (long long)pr * g.A.ld;
+    }
+  }
+  if (TB) {
+#pragma unroll
+    for (int p = 0; p < B_P; ++p) {
+      const int gj = bn0 + tid / 8 + 32 * p;
+      bRowOk[p] = gj < N;
+      const int pr = gj < N ? (rB ? rB[gj] : gj) : 0;
+      bRow[p] = Bp + (long long)pr * g.B.ld;
+    }
+  }
+
+  double ra[A_P][2], rb[B_P][2];
 
   auto load_tiles = [&](int kt) {
+    if (!TA) {
+      const int kq = (tid & 7) * 2;
+      const int gk = kt + kq;
+      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
 #pragma unroll
-    for (int r = 0; r < A_PER; ++r) {
-      const int e = tid + r * 256;
-      int i, k;
-      if (!TA) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
-      const int gi = bm0 + i, gk = kt + k;
-      double v = 0.0;
-      if (gi < M && gk < kend) {
-        if (!TA) {
-          const int pr = g.A.rows ? g.A.rows[gi] : gi;
-          v = Ap[(long long)pr * g.A.ld + gk];
-        } else {
-          const int pr = g.A.rows ? g.A.rows[gk] : gk;
-          v = Ap[(long long)pr * g.A.ld + gi];
+      for (int p = 0; p < A_P; ++p) {
+        load2(aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ra[p][0], ra[p][1]);
+        if (g.triA) {
+          const int gi = bm0 + tid / 8 + 32 * p;
+          ra[p][0] = tri_mask(ra[p][0], g.triA, gi, gk);
+          ra[p][1] = tri_mask(ra[p][1], g.triA, gi, gk + 1);
         }
-        v = tri_mask(v, g.triA, gi, gk);
       }
-      ra[r] = v;
+    } else {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+      const int col = (tid % TPR) * 2;
+      const int gi = bm0 + col;
+      const int ncol = gi + 1 < M ? 2 : (gi < M ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < A_P; ++p) {
+        const int gk = kt + tid / TPR + RPP * p;
+        const bool ok = gk < kend;
+        const int pr = ok ? (rA ? rA[gk] : gk) : 0;
+        load2(Ap + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ra[p][0], ra[p][1]);
+        if (g.triA) {
+          ra[p][0] = tri_mask(ra[p][0], g.triA, gi, gk);
+          ra[p][1] = tri_mask(ra[p][1], g.triA, gi + 1, gk);
+        }
+      }
     }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+      const int col = (tid % TPR) * 2;
+      const int gj = bn0 + col;
+      const int ncol = gj + 1 < N ? 2 : (gj < N ? 1 : 0);
 #pragma unroll
-    for (int r = 0; r < B_PER; ++r) {
-      const int e = tid + r * 256;
-      int k, j;
-      if (!TB) { k = e / BN; j = e % BN; } else { j = e / BK; k = e % BK; }
-      const int gk = kt + k, gj = bn0 + j;
-      double v = 0.0;
-      if (gj < N && gk < kend) {
-        if (!TB) {
-          const int pr = g.B.rows ? g.B.rows[gk] : gk;
-          v = Bp[(long long)pr * g.B.ld + gj];
-        } else {
-          const int pr = g.B.rows ? g.B.rows[gj] : gj;
-          v = Bp[(long long)pr * g.B.ld + gk];
+      for (int p = 0; p < B_P; ++p) {
+        const int gk = kt + tid / TPR + RPP * p;
+        const bool ok = gk < kend;
+        const int pr = ok ? (rB ? rB[gk] : gk) : 0;
+        load2(Bp + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, rb[p][0], rb[p][1]);
+        if (g.triB) {
+          rb[p][0] = tri_mask(rb[p][0], g.triB, gk, gj);
+          rb[p][1] = tri_mask(rb[p][1], g.triB, gk, gj + 1);
         }
-        v = tri_mask(v, g.triB, gk, gj);
       }
-      rb[r] = v;
+    } else {
+      const int kq = (tid & 7) * 2;
+      const int gk = kt + kq;
+      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < B_P; ++p) {
+        load2(bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, rb[p][0], rb[p][1]);
+        if (g.triB) {
+          const int gj = bn0 + tid / 8 + 32 * p;
+          rb[p][0] = tri_mask(rb[p][0], g.triB, gk, gj);
+          rb[p][1] = tri_mask(rb[p][1], g.triB, gk + 1, gj);
+        }
+      }
     }
   };
-  auto store_tiles = [&]() {
+
+  auto store_tiles = [&](int stage) {
+    double* As = smem + stage * (A_SZ + B_SZ);
+    double* Bs = As + A_SZ;
 #pragma unroll
-    for (int r = 0; r < A_PER; ++r) {
-      const int e = tid + r * 256;
-      if (!TA) { As[(e / BK) * A_LD + (e % BK)] = ra[r]; }
-      else { As[(e / BM) * A_LD + (e % BM)] = ra[r]; }
+    for (int p = 0; p < A_P; ++p) {
+      int off;
+      if (!TA) off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
+      else {
+        constexpr int TPR = BM / 2, RPP = 256 / TPR;
+        off = (tid / TPR + RPP * p) * A_LD + (tid % TPR) * 2;
+      }
+      *reinterpret_cast<double2*>(As + off) = double2{ra[p][0], ra[p][1]};
     }
 #pragma unroll
-    for (int r = 0; r < B_PER; ++r) {
-      const int e = tid + r * 256;
-      if (!TB) { Bs[(e / BN) * B_LD + (e % BN)] = rb[r]; }
-      else { Bs[(e / BK) * B_LD + (e % BK)] = rb[r]; }
+    for (int p = 0; p < B_P; ++p) {
+      int off;
+      if (TB) off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
+      else {
+        constexpr int TPR = BN / 2, RPP = 256 / TPR;
+        off = (tid / TPR + RPP * p) * B_LD + (tid % TPR) * 2;
+      }
+      *reinterpret_cast<double2*>(Bs + off) = double2{rb[p][0], rb[p][1]};
     }
   };
 
@@ -154,11 +238,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  if (nk > 0) load_tiles(kbeg);
-  for (int it = 0; it < nk; ++it) {
-    store_tiles();
+  if (nk > 0) {
+    load_tiles(kbeg);
+    store_tiles(0);
     __syncthreads();
+  }
+  for (int it = 0; it < nk; ++it) {
+    const int stage = it & 1;
     if (it + 1 < nk) load_tiles(kbeg + (it + 1) * BK);
+    const double* As = smem + stage * (A_SZ + B_SZ);
+    const double* Bs = As + A_SZ;
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
@@ -179,6 +268,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
         for (int b = 0; b < FN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+    if (it + 1 < nk) store_tiles(stage ^ 1);
     __syncthreads();
   }
 
@@ -186,20 +276,22 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64Params g) {
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
+    for (int v = 0; v < 4; ++v) {
+      const int i = bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v;
+      if (i >= M) continue;
+      const int pr = rC ? rC[i] : i;
+      double* crow = Cp + (long long)pr * g.C.ld;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v;
+      for (int b = 0; b < FN; ++b) {
         const int j = bn0 + wn0 + b * 16 + (lane & 15);
-        if (i < M && j < N && (!g.lowerOnly || i >= j)) {
-          const int pr = g.C.rows ? g.C.rows[i] : i;
-          const int pc = g.C.cols ? g.C.cols[j] : j;
-          double* cp = Cp + (long long)pr * g.C.ld + pc;
+        if (j < N && (!g.lowerOnly || i >= j)) {
+          double* cp = crow + (g.C.cols ? g.C.cols[j] : j);
           double val = g.alpha * acc[a][b][v];
           if (g.beta != 0.0) val += g.beta * *cp;
           *cp = val;
         }
       }
+    }
 }
 
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>
@@ -225,18 +317,26 @@ static void launch_pick(const GemmF64Params& p, int batch, int cfg, hipStream_t 
 }
 
 int gemm_pick_cfg(int M, int N, int need) {
-  if (need == GEMM_NEED_FULL_M) return M <= 64 ? GEMM_CFG_64x64 : GEMM_CFG_128x128;
-  if (need == GEMM_NEED_FULL_N) return N <= 64 ? GEMM_CFG_64x64 : GEMM_CFG_128x128;
+  if (need == GEMM_NEED_FULL_M) {
+    if (M > 128) throw std::runtime_error("gemm_f64: in-place product taller than 128");
+    return M <= 64 ? GEMM_CFG_64x64 : GEMM_CFG_128x32;
+  }
+  if (need == GEMM_NEED_FULL_N) {
+    if (N > 128) throw std::runtime_error("gemm_f64: in-place product wider than 128");
+    return N <= 64 ? GEMM_CFG_64x64 : GEMM_CFG_32x128;
+  }
   if (N <= 32) return GEMM_CFG_128x32;
   if (M <= 32) return GEMM_CFG_32x128;
   const long long big_tiles = (long long)ceil_div(M, 128) * ceil_div(N, 128);
-  if (big_tiles >= 192) return GEMM_CFG_128x128;
+  if (big_tiles >= 160) return GEMM_CFG_128x128;
   return GEMM_CFG_64x64;
 }
 
-void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
-              int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
-              long long sC, int need) {
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
+                      int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
+                      long long sC, int rsA, int rsB, int rsC, int need) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0 && beta == 1.0) return;
   GemmF64Params p;
@@ -245,12 +345,23 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
   p.A = A; p.B = B; p.C = C;
   p.triA = triA; p.triB = triB;
   p.lowerOnly = lowerOnly ? 1 : 0;
+  // 16-byte loads need 16-byte aligned rows in every batch entry
+  p.vecA = aligned16(A.p) && (A.ld % 2 == 0) && (sA % 2 == 0);
+  p.vecB = aligned16(B.p) && (B.ld % 2 == 0) && (sB % 2 == 0);
   p.sA = sA; p.sB = sB; p.sC = sC;
+  p.rsA = rsA; p.rsB = rsB; p.rsC = rsC;
   const int cfg = gemm_pick_cfg(M, N, need);
   if (!ta && !tb) launch_pick<false, false>(p, batch, cfg, s);
   else if (!ta && tb) launch_pick<false, true>(p, batch, cfg, s);
   else if (ta && !tb) launch_pick<true, false>(p, batch, cfg, s);
   else launch_pick<true, true>(p, batch, cfg, s);
+}
+
+void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
+              int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
+              long long sC, int need) {
+  gemm_f64_batched(s, ta, tb, M, N, K, alpha, A, triA, B, triB, beta, C, lowerOnly, batch, sA, sB, sC, 0, 0, 0,
+                   need);
 }
 
 }  // namespace frob

@@ -2,9 +2,18 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "../../include/frobinv.h"
 #include "common.hpp"
+
+// Optional per-kernel-class timing: HIP events recorded on the handle's stream
+// around selected launches, resolved after the call's final synchronization.
+struct frob_prof_pending {
+  hipEvent_t e0, e1;
+  int cls;
+  double flops;
+};
 
 struct frob_handle {
   int device = 0;
@@ -14,6 +23,12 @@ struct frob_handle {
   int* dinfo = nullptr;          // device status words (factorization info)
   int* hinfo = nullptr;          // pinned host copy
   uint64_t rng = 0;              // splitmix64 state for the shift mu
+  int prof = 0;                  // profiling enabled
+  std::vector<frob_prof_pending> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[16] = {0};
+  double prof_flops[16] = {0};
+  long long prof_count[16] = {0};
 };
 
 namespace frob {
@@ -35,9 +50,21 @@ struct Carve {
   }
 };
 
-// scratch for the triangular inverse recursion: (n/2 + 64) rows of n entries
-inline int tmp_ld(int n) { return n; }
-inline size_t tmp_elems(int n) { return (size_t)(n / 2 + 64) * (size_t)n + 64; }
+// scratch for the triangular solves / inverses / factorizations of order n
+size_t solver_work_elems(int n);
+
+// kernel classes for frob_profile_read
+enum { PROF_GEMM_NNN = 0, PROF_FACTOR = 1, PROF_TRSM = 2, PROF_ALL_CALL = 3, PROF_BATCHED = 4, PROF_ADJOINT = 5 };
+// Record an event pair around the launches issued between begin and end.
+struct ProfScope {
+  frob_handle* h;
+  int cls;
+  double flops;
+  hipEvent_t e0 = nullptr;
+  ProfScope(frob_handle* hh, int c, double fl);
+  ~ProfScope();
+};
+void prof_resolve(frob_handle* h);
 
 uint64_t splitmix64(uint64_t& x);
 double draw_mu(frob_handle* h);

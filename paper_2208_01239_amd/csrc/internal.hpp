@@ -18,6 +18,11 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
               int triB, double beta, DOut C, bool lowerOnly = false, int batch = 1, long long sA = 0,
               long long sB = 0, long long sC = 0, int need = GEMM_NEED_ANY);
 
+// Batched variant with separate strides for the row-index arrays.
+void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
+                      int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
+                      long long sC, int rsA, int rsB, int rsC, int need = GEMM_NEED_ANY);
+
 // Planar complex GEMM, C = alpha op(A) op(B) + beta C with real alpha/beta and
 // op in {N, T, C (conjugate transpose)}; four real MFMA products per tile.
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
@@ -36,11 +41,17 @@ void trsm_small_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr,
 // --------------------------------------------------- blocked triangular drivers
 // Recursive triangular solve (left or right) built from the small solves and
 // GEMM updates.  Arguments as for trsm_small_*, any order nt.
-void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B);
+// `work` must hold trsm_work_elems(nt) doubles (diagonal-block inverses).
+size_t trsm_work_elems(int nt);
+void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, double* work);
+// Inverses of the diagonal blocks of op(T) of order nb (a power of two >= 64),
+// written on the diagonal of D (n x n, ld D.ld); `tmp` holds n*nb/4 + 64 doubles.
+void dinv_f64(hipStream_t s, int tri, bool trans, int n, DOp T, int nb, double* D, int ldd, double* tmp);
 void trsm_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B);
-// W = op(T)^{-1} for a triangle of order n into a separate dense buffer W
-// (only W's triangle is meaningful).  tmp must hold n*n/4 (+slack) entries.
-void trtri_f64(hipStream_t s, int tri, bool trans, int n, DOp T, DOut W, double* tmp, int ldtmp);
+// W = op(T)^{-1} for a triangle of order n into a separate plain buffer W
+// (n x n, ld ldw; the other triangle is set to zero).  tmp holds trtri_tmp_elems(n).
+size_t trtri_tmp_elems(int n);
+void trtri_f64(hipStream_t s, int tri, bool trans, int n, DOp T, double* W, int ldw, double* tmp);
 void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, ZOut W, double* tmp_re, double* tmp_im, int ldtmp);
 
 // ------------------------------------------------------------- factorizations
@@ -48,12 +59,15 @@ void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, ZOut W, double* tm
 // pivoting through the index array perm (initialised to the identity here):
 // logical row i of P A = L U lives in physical row perm[i].  *info (device)
 // receives the 1-based column of the first exactly-zero pivot or stays 0.
-void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info);
+// `work` holds getrf_work_elems(n) doubles.
+size_t getrf_work_elems(int n);
+void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work);
 void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info);
 // Cholesky A = L L^T (lower, in place in the lower triangle of a; the strict
 // upper triangle is not referenced).  *info receives the 1-based index of the
 // first non-positive pivot.
-void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info);
+size_t potrf_work_elems(int n);
+void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info, double* work);
 void potrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* info);
 
 // ------------------------------------------------------------ elementwise ops
