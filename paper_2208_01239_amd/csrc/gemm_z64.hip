@@ -1,0 +1,376 @@
+// gemm_z64.hip -- planar complex FP64 matrix-core GEMM for gfx950 (the
+// complex-arithmetic baselines: Algorithms 4 and 8 in complex arithmetic).
+//
+//   C = alpha * op(A) * op(B) + beta * C,   op in {N, T, C = conjugate transpose},
+//
+// real alpha, beta; complex matrices stored planar (separate real and
+// imaginary arrays with one leading dimension).  Same tiling, staging, row
+// indirection, triangular masks, lower-only output and XCD-aware block order
+// as the real kernel in gemm_f64.hip; each complex tile product is four real
+// v_mfma_f64_16x16x4f64 products on the two planes:
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
+// with the imaginary fragment of a conjugated operand negated once per k-step.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace frob {
+
+struct GemmZ64Params {
+  int M, N, K;
+  double alpha, beta;
+  ZOp A, B;
+  ZOut C;
+  int conjA, conjB;
+  int triA, triB;
+  int lowerOnly;
+  int vecA, vecB;
+  long long sA, sB, sC;      // batch strides (both planes)
+  int rsA, rsB, rsC;         // batch strides of the row-index pointers
+  int tilesM, tilesN;
+};
+
+__device__ __forceinline__ void ztri_mask(double& re, double& im, int tri, int r, int c) {
+  switch (tri) {
+    case TRI_LOWER: if (c > r) { re = 0.0; im = 0.0; } break;
+    case TRI_LOWER_UNIT: if (c > r) { re = 0.0; im = 0.0; } else if (c == r) { re = 1.0; im = 0.0; } break;
+    case TRI_UPPER: if (c < r) { re = 0.0; im = 0.0; } break;
+    case TRI_UPPER_UNIT: if (c < r) { re = 0.0; im = 0.0; } else if (c == r) { re = 1.0; im = 0.0; } break;
+    default: break;
+  }
+}
+
+__device__ __forceinline__ void zload2(const double* p, int n_ok, bool vec, double& x, double& y) {
+  if (n_ok >= 2) {
+    if (vec) {
+      const double2 t = *reinterpret_cast<const double2*>(p);
+      x = t.x; y = t.y;
+    } else {
+      x = p[0]; y = p[1];
+    }
+  } else if (n_ok == 1) {
+    x = p[0]; y = 0.0;
+  } else {
+    x = 0.0; y = 0.0;
+  }
+}
+
+template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
+  constexpr int BK = 16;
+  constexpr int FM = BM / WM / 16;
+  constexpr int FN = BN / WN / 16;
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  static_assert(BM >= 32 && BN >= 32, "tile sides must be >= 32");
+  // A tile: !TA row-band [BM][BK+2]; TA k-band [BK][BM+16]
+  constexpr int A_LD = TA ? (BM + 16) : (BK + 2);
+  constexpr int A_SZ = TA ? BK * A_LD : BM * A_LD;
+  // B tile: !TB k-band [BK][BN+16]; TB row-band [BN][BK+2]
+  constexpr int B_LD = TB ? (BK + 2) : (BN + 16);
+  constexpr int B_SZ = TB ? BN * B_LD : BK * B_LD;
+  // pairs per thread per tile
+  constexpr int A_P = BM * BK / 512;
+  constexpr int B_P = BN * BK / 512;
+  __shared__ __attribute__((aligned(16))) double smem[2 * 2 * (A_SZ + B_SZ)];  // [stage][re A, im A, re B, im B]
+
+  const int tiles = g.tilesM * g.tilesN;
+  const int per = (tiles + 7) / 8;
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per + (bid >> 3);
+  if (t >= tiles) return;
+  const int bm0 = (t / g.tilesN) * BM;
+  const int bn0 = (t % g.tilesN) * BN;
+  if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
+
+  const long long z = blockIdx.z;
+  const double* __restrict__ Ar = g.A.re + z * g.sA;
+  const double* __restrict__ Ai = g.A.im + z * g.sA;
+  const double* __restrict__ Br = g.B.re + z * g.sB;
+  const double* __restrict__ Bi = g.B.im + z * g.sB;
+  double* __restrict__ Cre = g.C.re + z * g.sC;
+  double* __restrict__ Cim = g.C.im + z * g.sC;
+  const int* __restrict__ rA = g.A.rows ? g.A.rows + z * g.rsA : nullptr;
+  const int* __restrict__ rB = g.B.rows ? g.B.rows + z * g.rsB : nullptr;
+  const int* __restrict__ rC = g.C.rows ? g.C.rows + z * g.rsC : nullptr;
+  const int M = g.M, N = g.N;
+  const bool vecA = g.vecA != 0, vecB = g.vecB != 0;
+
+  int kbeg = 0, kend = g.K;
+  if (g.triA == TRI_UPPER || g.triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
+  if (g.triA == TRI_LOWER || g.triA == TRI_LOWER_UNIT) kend = min(kend, bm0 + BM);
+  if (g.triB == TRI_LOWER || g.triB == TRI_LOWER_UNIT) kbeg = max(kbeg, bn0);
+  if (g.triB == TRI_UPPER || g.triB == TRI_UPPER_UNIT) kend = min(kend, bn0 + BN);
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm0 = (w / WN) * (BM / WM);
+  const int wn0 = (w % WN) * (BN / WN);
+
+  // ---- per-thread load coordinates (fixed across k-steps) ----
+  // row-band: 8 pairs per 16-wide row, 32 rows per pass; k-band: C/2 pairs per row
+  long long aRow[TA ? 1 : A_P];  // !TA: row offsets of A (rows fixed across k)
+  int aRowOk[TA ? 1 : A_P];
+  long long bRow[TB ? B_P : 1];  // TB: row offsets of B
+  int bRowOk[TB ? B_P : 1];
+  if (!TA) {
+#pragma unroll
+    for (int p = 0; p < A_P; ++p) {
+      const int gi = bm0 + tid / 8 + 32 * p;
+      aRowOk[p] = gi < M;
+      const int pr = gi < M ? (rA ? rA[gi] : gi) : 0;
+      aRow[p] = (long long)pr * g.A.ld;
+    }
+  }
+  if (TB) {
+#pragma unroll
+    for (int p = 0; p < B_P; ++p) {
+      const int gj = bn0 + tid / 8 + 32 * p;
+      bRowOk[p] = gj < N;
+      const int pr = gj < N ? (rB ? rB[gj] : gj) : 0;
+      bRow[p] = (long long)pr * g.B.ld;
+    }
+  }
+
+  double ra[A_P][2], rb[B_P][2], ia[A_P][2], ib[B_P][2];
+
+  auto load_tiles = [&](int kt) {
+    if (!TA) {
+      const int kq = (tid & 7) * 2;
+      const int gk = kt + kq;
+      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < A_P; ++p) {
+        zload2(Ar + aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ra[p][0], ra[p][1]);
+        zload2(Ai + aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ia[p][0], ia[p][1]);
+        if (g.triA) {
+          const int gi = bm0 + tid / 8 + 32 * p;
+          ztri_mask(ra[p][0], ia[p][0], g.triA, gi, gk);
+          ztri_mask(ra[p][1], ia[p][1], g.triA, gi, gk + 1);
+        }
+      }
+    } else {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+      const int col = (tid % TPR) * 2;
+      const int gi = bm0 + col;
+      const int ncol = gi + 1 < M ? 2 : (gi < M ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < A_P; ++p) {
+        const int gk = kt + tid / TPR + RPP * p;
+        const bool ok = gk < kend;
+        const int pr = ok ? (rA ? rA[gk] : gk) : 0;
+        zload2(Ar + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ra[p][0], ra[p][1]);
+        zload2(Ai + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ia[p][0], ia[p][1]);
+        if (g.triA) {
+          ztri_mask(ra[p][0], ia[p][0], g.triA, gi, gk);
+          ztri_mask(ra[p][1], ia[p][1], g.triA, gi + 1, gk);
+        }
+      }
+    }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+      const int col = (tid % TPR) * 2;
+      const int gj = bn0 + col;
+      const int ncol = gj + 1 < N ? 2 : (gj < N ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < B_P; ++p) {
+        const int gk = kt + tid / TPR + RPP * p;
+        const bool ok = gk < kend;
+        const int pr = ok ? (rB ? rB[gk] : gk) : 0;
+        zload2(Br + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, rb[p][0], rb[p][1]);
+        zload2(Bi + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, ib[p][0], ib[p][1]);
+        if (g.triB) {
+          ztri_mask(rb[p][0], ib[p][0], g.triB, gk, gj);
+          ztri_mask(rb[p][1], ib[p][1], g.triB, gk, gj + 1);
+        }
+      }
+    } else {
+      const int kq = (tid & 7) * 2;
+      const int gk = kt + kq;
+      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+#pragma unroll
+      for (int p = 0; p < B_P; ++p) {
+        zload2(Br + bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, rb[p][0], rb[p][1]);
+        zload2(Bi + bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, ib[p][0], ib[p][1]);
+        if (g.triB) {
+          const int gj = bn0 + tid / 8 + 32 * p;
+          ztri_mask(rb[p][0], ib[p][0], g.triB, gk, gj);
+          ztri_mask(rb[p][1], ib[p][1], g.triB, gk + 1, gj);
+        }
+      }
+    }
+  };
+
+  auto store_tiles = [&](int stage) {
+    double* As = smem + stage * 2 * (A_SZ + B_SZ);
+    double* AsI = As + A_SZ;
+    double* Bs = AsI + A_SZ;
+    double* BsI = Bs + B_SZ;
+#pragma unroll
+    for (int p = 0; p < A_P; ++p) {
+      int off;
+      if (!TA) off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
+      else {
+        constexpr int TPR = BM / 2, RPP = 256 / TPR;
+        off = (tid / TPR + RPP * p) * A_LD + (tid % TPR) * 2;
+      }
+      *reinterpret_cast<double2*>(As + off) = double2{ra[p][0], ra[p][1]};
+      *reinterpret_cast<double2*>(AsI + off) = double2{ia[p][0], ia[p][1]};
+    }
+#pragma unroll
+    for (int p = 0; p < B_P; ++p) {
+      int off;
+      if (TB) off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
+      else {
+        constexpr int TPR = BN / 2, RPP = 256 / TPR;
+        off = (tid / TPR + RPP * p) * B_LD + (tid % TPR) * 2;
+      }
+      *reinterpret_cast<double2*>(Bs + off) = double2{rb[p][0], rb[p][1]};
+      *reinterpret_cast<double2*>(BsI + off) = double2{ib[p][0], ib[p][1]};
+    }
+  };
+
+  d4 acc[FM][FN], acci[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) { acc[a][b] = d4{0.0, 0.0, 0.0, 0.0}; acci[a][b] = d4{0.0, 0.0, 0.0, 0.0}; }
+  const double sA = g.conjA ? -1.0 : 1.0, sB = g.conjB ? -1.0 : 1.0;
+
+  if (nk > 0) {
+    load_tiles(kbeg);
+    store_tiles(0);
+    __syncthreads();
+  }
+  for (int it = 0; it < nk; ++it) {
+    const int stage = it & 1;
+    if (it + 1 < nk) load_tiles(kbeg + (it + 1) * BK);
+    const double* As = smem + stage * 2 * (A_SZ + B_SZ);
+    const double* AsI = As + A_SZ;
+    const double* Bs = AsI + A_SZ;
+    const double* BsI = Bs + B_SZ;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int k = kk * 4 + (lane >> 4);
+      double af[FM], afi[FM], afn[FM], bf[FN], bfi[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int i = wm0 + a * 16 + (lane & 15);
+        af[a] = TA ? As[k * A_LD + i] : As[i * A_LD + k];
+        afi[a] = sA * (TA ? AsI[k * A_LD + i] : AsI[i * A_LD + k]);
+        afn[a] = -afi[a];
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int j = wn0 + b * 16 + (lane & 15);
+        bf[b] = TB ? Bs[j * B_LD + k] : Bs[k * B_LD + j];
+        bfi[b] = sB * (TB ? BsI[j * B_LD + k] : BsI[k * B_LD + j]);
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(afn[a], bfi[b], acc[a][b], 0, 0, 0);
+          acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bfi[b], acci[a][b], 0, 0, 0);
+          acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(afi[a], bf[b], acci[a][b], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) store_tiles(stage ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: lane holds D[l/16 + 4v][l%16] of each 16x16 tile
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v;
+      if (i >= M) continue;
+      const int pr = rC ? rC[i] : i;
+      double* crow = Cre + (long long)pr * g.C.ld;
+      double* crowi = Cim + (long long)pr * g.C.ld;
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int j = bn0 + wn0 + b * 16 + (lane & 15);
+        if (j < N && (!g.lowerOnly || i >= j)) {
+          const int pc = g.C.cols ? g.C.cols[j] : j;
+          double vr = g.alpha * acc[a][b][v], vi = g.alpha * acci[a][b][v];
+          if (g.beta != 0.0) { vr += g.beta * crow[pc]; vi += g.beta * crowi[pc]; }
+          crow[pc] = vr;
+          crowi[pc] = vi;
+        }
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
+  GemmZ64Params p = p0;
+  p.tilesM = ceil_div(p.M, BM);
+  p.tilesN = ceil_div(p.N, BN);
+  const int tiles = p.tilesM * p.tilesN;
+  const int grid = 8 * ((tiles + 7) / 8);
+  hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  FROB_LAUNCH_CHECK();
+}
+
+enum { ZCFG_64x64 = 0, ZCFG_128x32 = 1, ZCFG_32x128 = 2, ZCFG_128x64 = 3 };
+
+template <bool TA, bool TB>
+static void launch_pick_z(const GemmZ64Params& p, int batch, int cfg, hipStream_t s) {
+  switch (cfg) {
+    case ZCFG_64x64: launch_cfg_z<64, 64, 2, 2, TA, TB>(p, batch, s); break;
+    case ZCFG_128x32: launch_cfg_z<128, 32, 4, 1, TA, TB>(p, batch, s); break;
+    case ZCFG_32x128: launch_cfg_z<32, 128, 1, 4, TA, TB>(p, batch, s); break;
+    default: throw std::runtime_error("gemm_z64: bad tile config");
+  }
+}
+
+static int zpick(int M, int N, int need) {
+  if (need == GEMM_NEED_FULL_M) {
+    if (M > 128) throw std::runtime_error("gemm_z64: in-place product taller than 128");
+    return M <= 64 ? ZCFG_64x64 : ZCFG_128x32;
+  }
+  if (need == GEMM_NEED_FULL_N) {
+    if (N > 128) throw std::runtime_error("gemm_z64: in-place product wider than 128");
+    return N <= 64 ? ZCFG_64x64 : ZCFG_32x128;
+  }
+  if (N <= 32) return ZCFG_128x32;
+  if (M <= 32) return ZCFG_32x128;
+  return ZCFG_64x64;
+}
+
+static bool zaligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+void gemm_z64_batched(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha, ZOp A, int triA, ZOp B,
+                      int triB, double beta, ZOut C, bool lowerOnly, int batch, long long sA, long long sB,
+                      long long sC, int rsA, int rsB, int rsC, int need) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0 && beta == 1.0) return;
+  GemmZ64Params p;
+  p.M = M; p.N = N; p.K = K < 0 ? 0 : K;
+  p.alpha = alpha; p.beta = beta;
+  p.A = A; p.B = B; p.C = C;
+  p.conjA = opA == OP_C; p.conjB = opB == OP_C;
+  p.triA = triA; p.triB = triB;
+  p.lowerOnly = lowerOnly ? 1 : 0;
+  p.vecA = zaligned16(A.re) && zaligned16(A.im) && (A.ld % 2 == 0) && (sA % 2 == 0);
+  p.vecB = zaligned16(B.re) && zaligned16(B.im) && (B.ld % 2 == 0) && (sB % 2 == 0);
+  p.sA = sA; p.sB = sB; p.sC = sC;
+  p.rsA = rsA; p.rsB = rsB; p.rsC = rsC;
+  const bool ta = opA != OP_N, tb = opB != OP_N;
+  const int cfg = zpick(M, N, need);
+  if (!ta && !tb) launch_pick_z<false, false>(p, batch, cfg, s);
+  else if (!ta && tb) launch_pick_z<false, true>(p, batch, cfg, s);
+  else if (ta && !tb) launch_pick_z<true, false>(p, batch, cfg, s);
+  else launch_pick_z<true, true>(p, batch, cfg, s);
+}
+
+void gemm_z64(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha, ZOp A, int triA, ZOp B, int triB,
+              double beta, ZOut C, bool lowerOnly, int need) {
+  gemm_z64_batched(s, opA, opB, M, N, K, alpha, A, triA, B, triB, beta, C, lowerOnly, 1, 0, 0, 0, 0, 0, 0, need);
+}
+
+}  // namespace frob

@@ -28,6 +28,9 @@ void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, doub
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 void gemm_z64(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha, ZOp A, int triA, ZOp B,
               int triB, double beta, ZOut C, bool lowerOnly = false, int need = GEMM_NEED_ANY);
+void gemm_z64_batched(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha, ZOp A, int triA, ZOp B,
+                      int triB, double beta, ZOut C, bool lowerOnly, int batch, long long sA, long long sB,
+                      long long sC, int rsA, int rsB, int rsC, int need = GEMM_NEED_ANY);
 
 // ------------------------------------------------------- small triangular solves
 // In-place solve with a triangle of order nt <= 64 (one LDS-resident block):
@@ -37,6 +40,7 @@ void gemm_z64(hipStream_t s, int opA, int opB, int M, int N, int K, double alpha
 // identity (B is then output only, nr = nt).
 void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, bool identity);
 void trsm_small_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B, bool identity);
+size_t trsm_z_work_elems(int nt);   // doubles, both planes
 
 // --------------------------------------------------- blocked triangular drivers
 // Recursive triangular solve (left or right) built from the small solves and
@@ -47,12 +51,13 @@ void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DO
 // Inverses of the diagonal blocks of op(T) of order nb (a power of two >= 64),
 // written on the diagonal of D (n x n, ld D.ld); `tmp` holds n*nb/4 + 64 doubles.
 void dinv_f64(hipStream_t s, int tri, bool trans, int n, DOp T, int nb, double* D, int ldd, double* tmp);
-void trsm_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B);
+void trsm_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B, double* work);
 // W = op(T)^{-1} for a triangle of order n into a separate plain buffer W
 // (n x n, ld ldw; the other triangle is set to zero).  tmp holds trtri_tmp_elems(n).
 size_t trtri_tmp_elems(int n);
 void trtri_f64(hipStream_t s, int tri, bool trans, int n, DOp T, double* W, int ldw, double* tmp);
-void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, ZOut W, double* tmp_re, double* tmp_im, int ldtmp);
+size_t trtri_z_tmp_elems(int n);
+void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, double* Wre, double* Wim, int ldw, double* tmp);
 
 // ------------------------------------------------------------- factorizations
 // LU with partial pivoting of the n x n matrix a (row-major, lda), in place,
@@ -62,13 +67,15 @@ void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, ZOut W, double* tm
 // `work` holds getrf_work_elems(n) doubles.
 size_t getrf_work_elems(int n);
 void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work);
-void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info);
+size_t getrf_z_work_elems(int n);
+void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work);
 // Cholesky A = L L^T (lower, in place in the lower triangle of a; the strict
 // upper triangle is not referenced).  *info receives the 1-based index of the
 // first non-positive pivot.
 size_t potrf_work_elems(int n);
 void potrf_f64(hipStream_t s, int n, double* a, int lda, int* info, double* work);
-void potrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* info);
+size_t potrf_z_work_elems(int n);
+void potrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* info, double* work);
 
 // ------------------------------------------------------------ elementwise ops
 void iota_i32(hipStream_t s, int n, int* p);

@@ -216,3 +216,63 @@ def test_determinism(h):
     X1 = gpu_general(h, A, B)
     X2 = gpu_general(h, A, B)
     assert np.array_equal(X1[0], X2[0]) and np.array_equal(X1[1], X2[1])
+
+
+# ----------------------------------------------------------------------------- complex-arithmetic baselines
+def gpu_cinv(h, fn, A, B, form, ld=None):
+    Xr, Xi, res = fn(h, to_dev(A, ld), to_dev(B, ld), form=form)
+    return to_host(Xr), to_host(Xi), res
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("n", [1, 2, 7, 31, 32, 33, 64, 65, 100, 129, 257, 300, 513])
+def test_cinv_lu_baseline(h, n, form):
+    """Algorithm 4 in complex arithmetic on the GPU vs the oracle's Algorithm 4."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.general(n, 4000 + n)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    Xr, Xi, _ = gpu_cinv(h, fi.frob_cinv_lu, A, B, form)
+    e = relF(Xr, Xi, Rr, Ri)
+    print(f"cinv_lu n={n} form={form} relF={e:.2e}")
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 64, 65, 128, 129, 257, 513])
+def test_cinv_chol_baseline(h, n, form):
+    """Algorithm 8 in complex arithmetic on the GPU vs the oracle's Algorithm 8."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.hpd(n, 5000 + n)
+    Rr, Ri, info, _ = oracle.cinv_chol(A, B)
+    assert info == 0
+    Xr, Xi, _ = gpu_cinv(h, fi.frob_cinv_chol, A, B, form)
+    e = relF(Xr, Xi, Rr, Ri)
+    print(f"cinv_chol n={n} form={form} relF={e:.2e}")
+    assert e <= TOL
+    assert np.abs(Xr - Xr.T).max() <= 1e-13 * np.abs(Xr).max()
+    assert np.abs(Xi + Xi.T).max() <= 1e-13 * np.abs(Xr).max()
+
+
+def test_baselines_reject_singular_and_indefinite(h):
+    import paper_2208_01239_amd as fi
+    g = json.load(open(os.path.join(GOLD, "moore_penrose_3x3.json")))
+    A, B = np.array(g["Mr"]), np.array(g["Mi"])
+    for form in (0, 1):
+        with pytest.raises(fi.FrobSingularError):
+            gpu_cinv(h, fi.frob_cinv_lu, A, B, form)
+        with pytest.raises(fi.FrobNotHPDError):
+            gpu_cinv(h, fi.frob_cinv_chol, np.diag([1.0, -1.0, 2.0]), np.zeros((3, 3)), form)
+
+
+def test_config1_frobenius_vs_gpu_complex_lu(h):
+    """n = 128, seed 0: the GPU Frobenius result and the GPU complex-LU result
+    both match the oracle's complex LU (configuration of the headline metric)."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.general(128, 0)
+    Rr, Ri, _, _, _ = oracle.cinv_lu(A, B)
+    Fr, Fi, _ = gpu_general(h, A, B)
+    for form in (0, 1):
+        Cr, Ci, _ = gpu_cinv(h, fi.frob_cinv_lu, A, B, form)
+        assert relF(Cr, Ci, Rr, Ri) <= TOL
+    assert relF(Fr, Fi, Rr, Ri) <= TOL
