@@ -272,26 +272,45 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
     __syncthreads();
   }
 
-  // epilogue: lane holds D[l/16 + 4v][l%16] of each 16x16 tile
+  // epilogue: lane holds D[l/16 + 4v][l%16] of each 16x16 tile.  The reads
+  // of C (beta != 0) are issued per 16-row tile as one unconditional batch
+  // at clamped addresses, so they overlap instead of costing one memory
+  // latency each.
+  int pc[FN];
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+  for (int b = 0; b < FN; ++b) {
+    const int jc = min(bn0 + wn0 + b * 16 + (lane & 15), N - 1);
+    pc[b] = g.C.cols ? g.C.cols[jc] : jc;
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    double* crow[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ic = min(bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v, M - 1);
+      crow[v] = Cp + (long long)(rC ? rC[ic] : ic) * g.C.ld;
+    }
+    double cold[4][FN];
+    if (g.beta != 0.0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) cold[v][b] = crow[v][pc[b]];
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v;
-      if (i >= M) continue;
-      const int pr = rC ? rC[i] : i;
-      double* crow = Cp + (long long)pr * g.C.ld;
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
         const int j = bn0 + wn0 + b * 16 + (lane & 15);
-        if (j < N && (!g.lowerOnly || i >= j)) {
-          double* cp = crow + (g.C.cols ? g.C.cols[j] : j);
+        if (i < M && j < N && (!g.lowerOnly || i >= j)) {
           double val = g.alpha * acc[a][b][v];
-          if (g.beta != 0.0) val += g.beta * *cp;
-          *cp = val;
+          if (g.beta != 0.0) val += g.beta * cold[v][b];
+          crow[v][pc[b]] = val;
         }
       }
     }
+  }
 }
 
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>

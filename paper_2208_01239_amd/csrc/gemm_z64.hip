@@ -281,28 +281,48 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
     __syncthreads();
   }
 
-  // epilogue: lane holds D[l/16 + 4v][l%16] of each 16x16 tile
+  // epilogue: lane holds D[l/16 + 4v][l%16] of each 16x16 tile; C is read
+  // (beta != 0) per 16-row tile in one unconditional batch at clamped
+  // addresses so the reads overlap
+  int pc[FN];
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+  for (int b = 0; b < FN; ++b) {
+    const int jc = min(bn0 + wn0 + b * 16 + (lane & 15), N - 1);
+    pc[b] = g.C.cols ? g.C.cols[jc] : jc;
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    long long ro[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ic = min(bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v, M - 1);
+      ro[v] = (long long)(rC ? rC[ic] : ic) * g.C.ld;
+    }
+    double cr[4][FN], ci[4][FN];
+    if (g.beta != 0.0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          cr[v][b] = Cre[ro[v] + pc[b]];
+          ci[v][b] = Cim[ro[v] + pc[b]];
+        }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = bm0 + wm0 + a * 16 + (lane >> 4) + 4 * v;
-      if (i >= M) continue;
-      const int pr = rC ? rC[i] : i;
-      double* crow = Cre + (long long)pr * g.C.ld;
-      double* crowi = Cim + (long long)pr * g.C.ld;
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
         const int j = bn0 + wn0 + b * 16 + (lane & 15);
-        if (j < N && (!g.lowerOnly || i >= j)) {
-          const int pc = g.C.cols ? g.C.cols[j] : j;
+        if (i < M && j < N && (!g.lowerOnly || i >= j)) {
           double vr = g.alpha * acc[a][b][v], vi = g.alpha * acci[a][b][v];
-          if (g.beta != 0.0) { vr += g.beta * crow[pc]; vi += g.beta * crowi[pc]; }
-          crow[pc] = vr;
-          crowi[pc] = vi;
+          if (g.beta != 0.0) { vr += g.beta * cr[v][b]; vi += g.beta * ci[v][b]; }
+          Cre[ro[v] + pc[b]] = vr;
+          Cim[ro[v] + pc[b]] = vi;
         }
       }
     }
+  }
 }
 
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>

@@ -36,9 +36,10 @@ void gemm_z64_batched(hipStream_t s, int opA, int opB, int M, int N, int K, doub
 // In-place solve with a triangle of order nt <= 64 (one LDS-resident block):
 //   left:  op(T) X = B   (B is nt x nr),   right: X op(T) = B  (B is nr x nt).
 // `tri` describes op(T) (lower/upper, unit/non-unit) in logical coordinates;
-// `trans` selects op(T) = T^T.  If `identity` is set the right-hand side is the
-// identity (B is then output only, nr = nt).
-void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, bool identity);
+// `trans` selects op(T) = T^T.
+void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B);
+// Complex analogue; with `identity` set the right-hand side is the identity
+// (B is then output only, nr = nt).
 void trsm_small_z64(hipStream_t s, bool right, int tri, int opT, int nt, int nr, ZOp T, ZOut B, bool identity);
 size_t trsm_z_work_elems(int nt);   // doubles, both planes
 

@@ -3,9 +3,9 @@
 // Recursive column splitting: factor the left half, solve U12 = L11^{-1} A12,
 // update A22 -= L21 U12 with one matrix-core GEMM, factor the right half.  The
 // recursion stops at a "leaf" panel narrow enough to live in the registers of
-// one 1024-thread workgroup (rows-per-thread x columns = 32 doubles per
-// thread), where the pivot search is a wave64 shuffle reduction followed by a
-// 16-entry LDS reduction, with the lowest row index winning ties.
+// one 512-thread workgroup (rows-per-thread x columns <= 64 doubles per
+// thread), where the pivot search is a DPP max-reduction per wave followed by
+// an 8-slot reduction, with the lowest row index winning ties.
 //
 // Pivoting never moves data: rows are addressed through the index array perm
 // (logical row i of P A lives in physical row perm[i]), so a row interchange
@@ -16,296 +16,473 @@
 
 #include "common.hpp"
 #include "internal.hpp"
-#include "devutil.hpp"
+#include "tri_dev.hpp"
 
 namespace frob {
 
 namespace {
 
-constexpr int LEAF_THREADS = 1024;
+constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
+constexpr int LEAF_STAGE = 8192;    // doubles in the LDS stage (64 KiB): one I/O round
+constexpr int LEAF_WMAX = 32;
 
-// One workgroup factors an mm x nc panel (nc <= W) held in registers: thread t
-// owns logical rows t, t + 1024, ... .  The panel moves between HBM and the
-// registers through an LDS stage in rounds of SROWS rows, with all global
-// loads of a round issued before any is consumed (the rows are scattered by
-// the pivot indirection, so these loads are latency-bound).  Per column: every
-// wave reduces its candidates and publishes the winning row (value, index,
-// physical row, W entries) to a parity-double-buffered LDS slot, the owner of
-// row j publishes row j, one barrier, then every thread picks the global
-// winner from the slots, swaps, and updates its rows.
+// One workgroup factors an mm x nc panel (nc <= W) held in registers.  Thread
+// t owns panel rows q = t + s * LEAF_NT (s < R).  Rows never move: each row
+// carries its current logical position pos (GEPP's row interchanges act on
+// these integers only), so a pivot step exchanges no data between threads.
+// Per column j:
+//   - every lane takes its best candidate (largest |a_qj| among rows with
+//     pos >= j, lowest pos on ties);
+//   - the wave maximum is found on an FP32 image of |a_qj| (rounding is
+//     monotone, so the exact maximum is among the lanes that attain the FP32
+//     maximum) with single-instruction DPP steps; a ballot then settles the
+//     winner exactly in FP64 (one lane in the usual case, an exact FP64
+//     comparison among the tied lanes otherwise);
+//   - the wave's winner writes (|value|, pos, row) to a parity-double-
+//     buffered LDS slot; one barrier; every wave reduces the eight slots the
+//     same way and reads the pivot row from the winning slot;
+//   - positions are exchanged and every row below is scaled and updated
+//     (branch-free: rows above are updated with a zero multiplier).
+// The physical row of every panel row is staged in LDS once, so the panel
+// moves between HBM and the registers through the LDS stage with no dependent
+// index loads: rounds of 64 KiB, read and written by the whole workgroup with
+// 16-byte accesses (rows are contiguous), each round's loads issued before the
+// previous round is taken out of the stage.
 //
-// With n2 > 0 the kernel also applies its factorization to the n2 columns to
-// the right of the panel (the sibling panel of a bottom recursion node):
-// U12 = L11^{-1} A12 by substitution in wave 0, then A22 -= L21 U12 with L21
-// still in registers.  That replaces a triangular-solve launch and a GEMM
-// launch per bottom node.
-constexpr int STAGE = 8192;  // doubles in the LDS stage (64 KiB)
+// With n2 > 0 the kernel also applies its factorization to the n2 <= W
+// columns to the right of the panel (the sibling of a bottom recursion node):
+// U12 = L11^{-1} A12 by substitution in wave 0, A22 -= L21 U12 with L21 still
+// in registers.
+// Keys are the bit patterns of FP32 values: for the values used here (>= 0,
+// or negative for "no candidate") signed-integer order agrees with numeric
+// order wherever it matters (any value >= 0 beats any negative one), and an
+// integer max fuses with its DPP operand into one instruction.
+template <int CTRL, int RM>
+__device__ __forceinline__ int upd_dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xF, false);
+}
+// maximum over each row of 16 lanes, left in the row's last lane
+__device__ __forceinline__ int row_max_key(int v) {
+  v = max(v, upd_dpp_i32<0x111, 0xF>(v, v));  // row_shr:1
+  v = max(v, upd_dpp_i32<0x112, 0xF>(v, v));  // row_shr:2
+  v = max(v, upd_dpp_i32<0x114, 0xF>(v, v));  // row_shr:4
+  v = max(v, upd_dpp_i32<0x118, 0xF>(v, v));  // row_shr:8
+  return v;
+}
+// maximum over the wave, the same in every lane
+__device__ __forceinline__ int wave_max_key(int v) {
+  v = row_max_key(v);
+  v = max(v, upd_dpp_i32<0x142, 0xA>(v, v));  // row_bcast:15 into rows 1, 3
+  v = max(v, upd_dpp_i32<0x143, 0xC>(v, v));  // row_bcast:31 into rows 2, 3
+  return __builtin_amdgcn_readlane(v, 63);
+}
+// Exact argmax over the lanes in `cand` of (val desc, key asc); returns the
+// winning lane.  Rare path (several lanes share the FP32 maximum).
+__device__ __forceinline__ int exact_argmax(unsigned long long cand, double val, int key) {
+  int wl = -1;
+  double bv = -1.0;
+  int bk = INT_MAX;
+  while (cand) {
+    const int l = __ffsll((long long)cand) - 1;
+    cand &= cand - 1;
+    const double lv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(val), l),
+                                       __builtin_amdgcn_readlane(__double2loint(val), l));
+    const int lk = __builtin_amdgcn_readlane(key, l);
+    if (lv > bv || (lv == bv && lk < bk)) { bv = lv; bk = lk; wl = l; }
+  }
+  return wl;
+}
 
 template <int R, int W>
-__global__ __launch_bounds__(LEAF_THREADS) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
-                                                              int k0, int mm, int nc, int n2, int* info) {
-  constexpr int NW = LEAF_THREADS / 64;
-  constexpr int SROWS = STAGE / W;                       // rows per staging round
-  constexpr int PER = STAGE / LEAF_THREADS;              // staged elements per thread per round
-  static_assert(STAGE % LEAF_THREADS == 0 && STAGE % W == 0, "stage shape");
-  __shared__ double stage[STAGE];
-  __shared__ int s_ph[SROWS];
+__global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
+                                                         int k0, int mm, int nc, int n2, int* info) {
+  constexpr int NT = LEAF_NT, NW = NT / 64, HW = W / 2;
+  constexpr int SR = LEAF_STAGE / W;                 // rows per I/O round
+  constexpr int PER = LEAF_STAGE / 2 / NT;           // 16-byte pieces per thread per round
+  static_assert(W % 2 == 0 && LEAF_STAGE % (2 * NT) == 0 && NW <= 16, "leaf shape");
+  __shared__ __align__(16) double stage[LEAF_STAGE];
+  __shared__ int s_ph[R * NT];                       // physical row of panel row q
   __shared__ double s_cv[2][NW];
-  __shared__ int s_ci[2][NW];
-  __shared__ int s_cph[2][NW];
-  __shared__ double s_crow[2][NW][W];
-  __shared__ double s_jrow[2][W];
-  __shared__ int s_jph[2];
-  __shared__ double s_u[W][W];
+  __shared__ int s_ck[2][NW];
+  __shared__ __align__(16) double s_crow[2][NW][W];
+  __shared__ double s_l[W][W + 1];
+  __shared__ double s_u[W][W + 1];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
+  const bool vbase = ((lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(a) & 15) == 0);
   double v[R][W];
-  int ph[R];
+  int pos[R];
 #pragma unroll
   for (int s = 0; s < R; ++s) {
-    ph[s] = -1;
+    const int q = t + s * NT;
+    pos[s] = q < mm ? q : -1;      // padding rows: never candidates, never updated
+    if (q < mm) s_ph[q] = perm[k0 + q];
 #pragma unroll
     for (int c = 0; c < W; ++c) v[s][c] = 0.0;
   }
+  __syncthreads();
 
-  // ---- load the panel (columns k0 .. k0 + nc) through the stage ----
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
-    int pr[PER];
-    double x[PER];
+  // ---- cooperative panel I/O: piece e = t + u NT of a round is
+  //      (stage row e / HW, columns 2 (e % HW) + {0, 1}) ----
+  const int nrounds = (mm + SR - 1) / SR;
+  auto load_round = [&](int r0, int col0, int ncol, double2* x) {
+    const bool vec = vbase && (col0 & 1) == 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS, r = e / W;
-      pr[i] = r < nrow ? perm[k0 + r0 + r] : 0;
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * NT, i = e / HW, c = 2 * (e % HW);
+      double2 val = make_double2(0.0, 0.0);
+      if (r0 + i < mm && c < ncol) {
+        const double* src = a + (long long)s_ph[r0 + i] * lda + col0 + c;
+        if (vec && c + 1 < ncol) val = *reinterpret_cast<const double2*>(src);
+        else {
+          val.x = src[0];
+          if (c + 1 < ncol) val.y = src[1];
+        }
+      }
+      x[u] = val;
     }
+  };
+  auto put_round = [&](const double2* x) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS, r = e / W, c = e % W;
-      x[i] = (r < nrow && c < nc) ? a[(long long)pr[i] * lda + k0 + c] : 0.0;
-    }
+    for (int u = 0; u < PER; ++u) reinterpret_cast<double2*>(stage)[t + u * NT] = x[u];
+  };
+  auto store_round = [&](int r0, int col0, int ncol) {
+    const bool vec = vbase && (col0 & 1) == 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS;
-      stage[e] = x[i];
-      if (e % W == 0 && e / W < nrow) s_ph[e / W] = pr[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * LEAF_THREADS;
-      if (q >= r0 && q < r0 + nrow) {
-        ph[s] = s_ph[q - r0];
-#pragma unroll
-        for (int c = 0; c < W; ++c) v[s][c] = stage[(q - r0) * W + c];
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * NT, i = e / HW, c = 2 * (e % HW);
+      if (r0 + i < mm && c < ncol) {
+        double* dst = a + (long long)s_ph[r0 + i] * lda + col0 + c;
+        const double2 val = reinterpret_cast<const double2*>(stage)[e];
+        if (vec && c + 1 < ncol) *reinterpret_cast<double2*>(dst) = val;
+        else {
+          dst[0] = val.x;
+          if (c + 1 < ncol) dst[1] = val.y;
+        }
       }
     }
-    __syncthreads();
+  };
+
+  // ---- load the panel ----
+  {
+    double2 x[PER];
+    load_round(0, k0, nc, x);
+    for (int r = 0; r < nrounds; ++r) {
+      const int r0 = r * SR;
+      put_round(x);
+      __syncthreads();
+      if (r + 1 < nrounds) load_round(r0 + SR, k0, nc, x);
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const int q = t + s * NT;
+        if (q >= r0 && q < r0 + SR && q < mm) {
+#pragma unroll
+          for (int c = 0; c < W; c += 2) {
+            const double2 y = reinterpret_cast<const double2*>(stage)[((q - r0) * W + c) / 2];
+            v[s][c] = y.x;
+            v[s][c + 1] = y.y;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
 
   // ---- factor ----
   int first_zero = 0;
-#pragma unroll
-  for (int j = 0; j < W; ++j) {
-    if (j >= nc) continue;  // uniform
-    const int par = j & 1;
+  // one column step per compile-time j (keeps every register index static)
+  auto column = [&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    if (j >= nc) return;  // uniform
+    constexpr int par = j & 1;
     double best = -1.0;
     int bq = INT_MAX;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int q = t + s * LEAF_THREADS;
       const double xv = fabs(v[s][j]);
-      const bool ok = q >= j && q < mm && xv > best;
+      const bool ok = pos[s] >= j && (xv > best || (xv == best && pos[s] < bq));
       best = ok ? xv : best;
-      bq = ok ? q : bq;
+      bq = ok ? pos[s] : bq;
     }
-    double wbest;
-    int wq;
-    const int wl = wave_argmax(best, bq, wbest, wq);
-    if (lane == wl) {
-      const int s = (wq - t) / LEAF_THREADS;
+    // (NaN entries are never candidates; a lane without one holds -1)
+    const int bf = __float_as_int((float)best);
+    const int wmf = wave_max_key(bf);
+    if (wmf >= 0) {
+      const unsigned long long tied = __ballot(bf == wmf);
+      const int wl = (__popcll(tied) == 1) ? __ffsll((long long)tied) - 1 : exact_argmax(tied, best, bq);
+      if (lane == wl) {
 #pragma unroll
-      for (int ss = 0; ss < R; ++ss)
-        if (ss == s) {
+        for (int s = 0; s < R; ++s)
+          if (pos[s] == bq) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) s_crow[par][wv][c] = v[ss][c];
-          s_cph[par][wv] = ph[ss];
-        }
-    }
-    if (lane == 0) { s_cv[par][wv] = wbest; s_ci[par][wv] = wq; }
-    if ((j & (LEAF_THREADS - 1)) == t) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) s_jrow[par][c] = v[j / LEAF_THREADS][c];
-      s_jph[par] = ph[j / LEAF_THREADS];
+            for (int c = 0; c < W; c += 2)
+              *reinterpret_cast<double2*>(&s_crow[par][wv][c]) = make_double2(v[s][c], v[s][c + 1]);
+          }
+        s_cv[par][wv] = best;
+        s_ck[par][wv] = bq;
+      }
+    } else if (lane == 0) {
+      s_cv[par][wv] = -1.0;
+      s_ck[par][wv] = INT_MAX;
     }
     __syncthreads();
-    double gb = -1.0;
-    int gq = INT_MAX, gw = -1;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const double cv = s_cv[par][w];
-      const int ci = s_ci[par][w];
-      const bool ok = ci != INT_MAX && (cv > gb || (cv == gb && ci < gq));
-      gb = ok ? cv : gb;
-      gq = ok ? ci : gq;
-      gw = ok ? w : gw;
-    }
-    const bool have = gw >= 0;               // false only for an all-NaN column
-    const int p = have ? gq : j;
-    double prow[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) prow[c] = have ? s_crow[par][gw][c] : s_jrow[par][c];
-    const int pph = have ? s_cph[par][gw] : s_jph[par];
-    if (p != j) {
-      // row j takes the pivot row, row p takes the old row j
-      if ((j & (LEAF_THREADS - 1)) == t) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) v[j / LEAF_THREADS][c] = prow[c];
-        ph[j / LEAF_THREADS] = pph;
-      }
-      if ((p & (LEAF_THREADS - 1)) == t) {
-#pragma unroll
-        for (int ss = 0; ss < R; ++ss)
-          if (ss == p / LEAF_THREADS) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) v[ss][c] = s_jrow[par][c];
-            ph[ss] = s_jph[par];
-          }
-      }
-    }
-    const double piv = prow[j];
-    if (piv == 0.0) {
-      if (!first_zero) first_zero = k0 + j + 1;
+    const double sv = lane < NW ? s_cv[par][lane] : -2.0;
+    const int sk = lane < NW ? s_ck[par][lane] : INT_MAX;
+    const int sf = __float_as_int((float)sv);
+    const int gmf = __builtin_amdgcn_readlane(row_max_key(sf), 15);
+    int p;
+    const double* prow;
+    if (gmf >= 0) {
+      const unsigned long long tied = __ballot(lane < NW && sf == gmf);
+      const int gw = (__popcll(tied) == 1) ? __ffsll((long long)tied) - 1 : exact_argmax(tied, sv, sk);
+      p = __builtin_amdgcn_readlane(sk, gw);
+      prow = s_crow[par][gw];
     } else {
-      // scale by the reciprocal unless it would overflow (as LAPACK's getf2 does)
-      const bool recip = fabs(piv) >= 2.2250738585072014e-308;
-      const double rp = 1.0 / piv;
+      // every candidate is NaN: keep row j in place (uniform slow path)
+      p = j;
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+        if (pos[s] == j) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) s_crow[par][0][c] = v[s][c];
+        }
+      __syncthreads();
+      prow = s_crow[par][0];
+    }
+    // row interchange j <-> p on the positions only
+#pragma unroll
+    for (int s = 0; s < R; ++s) pos[s] = pos[s] == p ? j : (pos[s] == j ? p : pos[s]);
+    const double piv = prow[j];
+    if (piv == 0.0 && !first_zero) first_zero = k0 + j + 1;
+    // scale by the reciprocal unless it would overflow (as LAPACK's getf2
+    // does); a zero pivot leaves the (all-zero) column and the rows as they are
+    const bool nz = piv != 0.0;
+    double pr[W];
+#pragma unroll
+    for (int c = j + 1; c < W; ++c) pr[c] = prow[c];
+    auto update = [&](auto scale) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        const int q = t + s * LEAF_THREADS;
-        const bool below = q > j && q < mm;
-        const double l = below ? (recip ? v[s][j] * rp : v[s][j] / piv) : 0.0;
-        if (below) v[s][j] = l;
+        const bool below = nz && pos[s] > j;
+        const double q = scale(v[s][j]);
+        const double l = below ? q : 0.0;
+        v[s][j] = below ? q : v[s][j];
 #pragma unroll
-        for (int c = 0; c < W; ++c)
-          if (c > j) v[s][c] -= l * prow[c];
+        for (int c = j + 1; c < W; ++c) v[s][c] = fma(-l, pr[c], v[s][c]);
       }
+    };
+    if (fabs(piv) >= 2.2250738585072014e-308) {   // uniform
+      const double rp = 1.0 / piv;
+      update([rp](double x) { return x * rp; });
+    } else {
+      update([piv](double x) { return x / piv; });
     }
-  }
+  };
+  StaticFor<0, W>::run(column);
   if (t == 0 && first_zero && *info == 0) *info = first_zero;
 
-  // ---- store the panel (and the new row order) through the stage ----
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
+  // ---- store the panel ----
+  for (int r = 0; r < nrounds; ++r) {
+    const int r0 = r * SR;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int q = t + s * LEAF_THREADS;
-      if (q >= r0 && q < r0 + nrow) {
-        s_ph[q - r0] = ph[s];
-        perm[k0 + q] = ph[s];
+      const int q = t + s * NT;
+      if (q >= r0 && q < r0 + SR && q < mm) {
 #pragma unroll
-        for (int c = 0; c < W; ++c) stage[(q - r0) * W + c] = v[s][c];
+        for (int c = 0; c < W; c += 2)
+          reinterpret_cast<double2*>(stage)[((q - r0) * W + c) / 2] = make_double2(v[s][c], v[s][c + 1]);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS, r = e / W, c = e % W;
-      if (r < nrow && c < nc) a[(long long)s_ph[r] * lda + k0 + c] = stage[e];
-    }
+    store_round(r0, k0, nc);
     __syncthreads();
   }
 
-  if (n2 <= 0) return;
-  // ---- sibling update: columns k0 + nc .. k0 + nc + n2 ----
-  const int cs = k0 + nc;
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
-    // physical rows of this round (final order) and the sibling block
+  if (n2 > 0) {
+    // ---- sibling update: columns cs .. cs + n2 ----
+    const int cs = k0 + nc;
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * LEAF_THREADS;
-      if (q >= r0 && q < r0 + nrow) s_ph[q - r0] = ph[s];
+    for (int s = 0; s < R; ++s)
+      if (pos[s] >= 0 && pos[s] < nc) {
+        const int i = pos[s];
+#pragma unroll
+        for (int k = 0; k < W; ++k) s_l[i][k] = v[s][k];
+        const double* src = a + (long long)s_ph[t + s * NT] * lda + cs;
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < n2) s_u[i][c] = src[c];
+      }
+    __syncthreads();
+    if (t < n2) {
+      // U12 = L11^{-1} A12, column t, in place
+      for (int i = 1; i < nc; ++i) {
+        double acc = s_u[i][t];
+        for (int k = 0; k < i; ++k) acc -= s_l[i][k] * s_u[k][t];
+        s_u[i][t] = acc;
+      }
     }
     __syncthreads();
-    double x[PER];
+    double2 x[PER];
+    load_round(0, cs, n2, x);
+    for (int r = 0; r < nrounds; ++r) {
+      const int r0 = r * SR;
+      put_round(x);
+      __syncthreads();
+      if (r + 1 < nrounds) load_round(r0 + SR, cs, n2, x);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS, r = e / W, c = e % W;
-      x[i] = (r < nrow && c < n2) ? a[(long long)s_ph[r] * lda + cs + c] : 0.0;
-    }
+      for (int s = 0; s < R; ++s) {
+        const int q = t + s * NT;
+        if (q >= r0 && q < r0 + SR && q < mm) {
+          double* row = stage + (q - r0) * W;
+          const bool top = pos[s] < nc;
+          const int pi = top ? pos[s] : 0;
+#pragma unroll 1
+          for (int c = 0; c < n2; ++c) {
+            double acc = row[c];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) stage[t + i * LEAF_THREADS] = x[i];
-    __syncthreads();
-    if (r0 == 0 && t < 64) {
-      // U12 = L11^{-1} A12: top rows q < nc are lanes q of wave 0 (s = 0)
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        if (k < nc) {
-          if (t > k && t < nc) {
-            const double l = v[0][k];
-#pragma unroll
-            for (int c = 0; c < W; ++c) stage[t * W + c] -= l * stage[k * W + c];
+            for (int k = 0; k < W; ++k)
+              if (k < nc) acc = fma(-v[s][k], s_u[k][c], acc);
+            row[c] = top ? s_u[pi][c] : acc;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
       }
-      for (int e = t; e < W * W; e += 64) s_u[e / W][e % W] = (e / W < nc) ? stage[e] : 0.0;
+      __syncthreads();
+      store_round(r0, cs, n2);
+      __syncthreads();
     }
-    __syncthreads();
-    // A22 -= L21 U12 on the staged rows below the top nc rows
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * LEAF_THREADS;
-      if (q >= r0 && q < r0 + nrow && q >= nc) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) {
-          double acc = stage[(q - r0) * W + c];
-#pragma unroll
-          for (int k = 0; k < W; ++k)
-            if (k < nc) acc -= v[s][k] * s_u[k][c];
-          stage[(q - r0) * W + c] = acc;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * LEAF_THREADS, r = e / W, c = e % W;
-      if (r < nrow && c < n2) a[(long long)s_ph[r] * lda + cs + c] = stage[e];
-    }
-    __syncthreads();
   }
+
+  // ---- the new row order ----
+#pragma unroll
+  for (int s = 0; s < R; ++s)
+    if (pos[s] >= 0) perm[k0 + pos[s]] = s_ph[t + s * NT];
 }
 
-// widest leaf for a panel with mm rows
+// widest leaf for a panel with mm rows (R * W <= 32 doubles per thread keeps
+// the panel, the pivot row and the I/O staging within 256 VGPRs)
 inline int leaf_width(int mm) {
-  const int R = ceil_div(mm, LEAF_THREADS);
-  if (R <= 1) return 16;
-  if (R <= 2) return 8;
+  const int R = ceil_div(mm, LEAF_NT);
+  if (R <= 1) return 32;
+  if (R <= 2) return 16;
   if (R <= 4) return 8;
   if (R <= 8) return 4;
-  if (R <= 16) return 2;
+  if (R <= 32) return 2;
   return 0;
 }
 
 void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, int nc, int n2, int* info) {
-  const int R = ceil_div(mm, LEAF_THREADS);
+  const int R = ceil_div(mm, LEAF_NT);
   if (nc > leaf_width(mm) || n2 > leaf_width(mm)) throw std::runtime_error("getrf_f64: leaf wider than its template");
-  dim3 g(1), b(LEAF_THREADS);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
+  dim3 g(1), b(LEAF_NT);
+  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
+  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_f64<8, 4>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_f64<16, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
+  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_f64<32, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
   else throw std::runtime_error("getrf_f64: matrix order above 16384 is not supported");
   FROB_LAUNCH_CHECK();
 }
 
+// Internal recursion node with n1, n2 <= 64 in one launch (replaces a
+// triangular-solve launch and a GEMM launch): every workgroup solves
+// U12 = L11^{-1} A12 (quad substitution on an LDS copy of the unit lower
+// L11), then updates its 64 rows of A22 -= L21 U12.  A12 may be overwritten
+// with U12 only after every workgroup has read it: the workgroups count
+// themselves on *cnt and the last one writes U12 and resets the counter.
+constexpr int NODE_MAX = 64;
+__global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int lda, const int* __restrict__ perm,
+                                                     int k0, int mm, int n1, int n2, int* cnt) {
+  constexpr int LD = NODE_MAX + 1;
+  __shared__ double Ls[NODE_MAX * LD];   // L11, then the block of L21
+  __shared__ double Us[NODE_MAX * LD];   // U12
+  __shared__ double rd[NODE_MAX];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int cs = k0 + n1;                  // first column of A12 / A22
+  const int r0 = n1 + blockIdx.x * NODE_MAX;   // this workgroup's first row of L21 / A22
+  // Every global load has an in-range (clamped) address and is issued
+  // unconditionally in an unrolled batch, so the loads overlap (one memory
+  // latency instead of one per element); out-of-range values are replaced
+  // afterwards.  L21 and A22 are fetched up front and wait in registers while
+  // U12 is solved.
+  const int wr = tid >> 6, lc = tid & 63;  // a wave reads rows wr + 4u, 64 consecutive columns
+  const int c = tid >> 2, g = tid & 3;     // quad layout of the solve
+  const int ti = tid >> 4, tj = tid & 15;  // 4x4 outputs per thread in the product
+  int pl[16], pb[16], px[16], qr[4];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    pl[u] = perm[k0 + min(wr + 4 * u, n1 - 1)];
+    pb[u] = perm[k0 + min(r0 + wr + 4 * u, mm - 1)];
+    px[u] = perm[k0 + min(4 * u + g, n1 - 1)];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) qr[i] = perm[k0 + min(r0 + ti + 16 * i, mm - 1)];
+  double vl[16], vb[16], x[16], acc[4][4];
+  {
+    const int cl = min(lc, n1 - 1), cx = cs + min(c, n2 - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      vl[u] = a[(long long)pl[u] * lda + k0 + cl];
+      x[u] = a[(long long)px[u] * lda + cx];
+      vb[u] = a[(long long)pb[u] * lda + k0 + cl];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = a[(long long)qr[i] * lda + cs + min(tj + 16 * j, n2 - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int r = wr + 4 * u;
+    Ls[r * LD + lc] = (r < n1 && lc < r) ? vl[u] : (r == lc ? 1.0 : 0.0);
+    x[u] = (4 * u + g < n1 && c < n2) ? x[u] : 0.0;
+  }
+  if (tid < NODE_MAX) rd[tid] = 1.0;
+  __syncthreads();
+  quad_lower_solve<LD>(Ls, rd, x, g, opaque_zero());
+  __syncthreads();   // every wave is done with L11
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int r = wr + 4 * u;
+    Us[(4 * u + g) * LD + c] = x[u];
+    Ls[r * LD + lc] = (r0 + r < mm && lc < n1) ? vb[u] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n1; ++k) {
+    double lv[4], uv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lv[i] = Ls[(ti + 16 * i) * LD + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) uv[j] = Us[k * LD + tj + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(-lv[i], uv[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + ti + 16 * i, cc = tj + 16 * j;
+      if (r < mm && cc < n2) a[(long long)qr[i] * lda + cs + cc] = acc[i][j];
+    }
+  // every read of A12 by this workgroup is complete (its values fed the solve)
+  if (tid == 0) s_last = atomicAdd(cnt, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (s_last) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = wr + 4 * u;
+      if (r < n1 && lc < n2) a[(long long)pl[u] * lda + cs + lc] = Us[r * LD + lc];
+    }
+    if (tid == 0) atomicExch(cnt, 0);
+  }
+}
+
 // factor columns [k0, k0 + n) over logical rows [k0, m)
-void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int n, int* info, double* work) {
+void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int n, int* info, double* work, int* cnt) {
   const int mm = m - k0;
   const int wmax = leaf_width(mm);
   if (n <= wmax) {
@@ -318,10 +495,18 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   if (n1 <= wmax && n2 <= wmax) {
     // bottom node: the left leaf also updates its sibling's columns
     launch_leaf(s, a, lda, perm, k0, mm, n1, n2, info);
-    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work);
+    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
     return;
   }
-  getrf_rec(s, a, lda, perm, k0, m, n1, info, work);
+  getrf_rec(s, a, lda, perm, k0, m, n1, info, work, cnt);
+  if (n1 <= NODE_MAX && n2 <= NODE_MAX) {
+    const int rows = m - k0 - n1;
+    hipLaunchKernelGGL(k_lu_node_f64, dim3(rows > 0 ? ceil_div(rows, NODE_MAX) : 1), dim3(256), 0, s, a, lda, perm, k0,
+                       m - k0, n1, n2, cnt);
+    FROB_LAUNCH_CHECK();
+    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
+    return;
+  }
   // U12 = L11^{-1} A12 (unit lower), rows through perm
   DOp L11{a + k0, lda, perm + k0};
   DOut A12{a + k0 + n1, lda, perm + k0, nullptr};
@@ -331,17 +516,20 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   DOp U12{a + k0 + n1, lda, perm + k0};
   DOut A22{a + k0 + n1, lda, perm + k0 + n1, nullptr};
   gemm_f64(s, false, false, m - k0 - n1, n2, n1, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
-  getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work);
+  getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
 }
 
 }  // namespace
 
-size_t getrf_work_elems(int n) { return trsm_work_elems(n / 2 + 8); }
+size_t getrf_work_elems(int n) { return trsm_work_elems(n / 2 + 8) + 64; }
 
 void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work) {
   if (n <= 0) return;
   iota_i32(s, n, perm);
-  getrf_rec(s, a, lda, perm, 0, n, n, info, work);
+  // the node kernels' workgroup counter lives in the first 64 doubles of work
+  int* cnt = reinterpret_cast<int*>(work);
+  fill_i32(s, 1, 0, cnt);
+  getrf_rec(s, a, lda, perm, 0, n, n, info, work + 64, cnt);
 }
 
 }  // namespace frob

@@ -1,220 +1,117 @@
 // tri_f64.hip -- triangular solves and triangular inverses in FP64.
 //
-// The base case keeps a triangle of order <= 64 in LDS together with a
-// 64-column strip of the right-hand side and runs substitution there; the
-// four lanes that share a right-hand-side column sit in one wave, so a step of
-// the substitution needs only wave-level ordering, not a workgroup barrier.
-// Larger triangles are handled recursively: halve the triangle, solve one
-// half, update the other half's right-hand side with one GEMM, solve the
-// second half.  Triangular inverses use the same recursion with
-// W21 = -W22 (T21 W11) (lower) or W12 = -W11 (T12 W22) (upper).
+// Base case (triangle of order <= 64): one workgroup loads the triangle into
+// LDS and solves for a 64-wide strip of the right-hand side by substitution,
+// four threads per right-hand side (the quad substitution of tri_dev.hpp).
+// Larger triangles: the 64x64 diagonal blocks are inverted by the same
+// kernel (identity right-hand sides), doubled to 128 by batched GEMMs (W21 = -W22 (T21 W11) for lower,
+// W12 = -W11 (T12 W22) for upper), and the solve recursion then needs only
+// GEMMs.
 #include "common.hpp"
 #include "internal.hpp"
+#include "tri_dev.hpp"
 
 namespace frob {
 
 namespace {
 
-constexpr int TS = 64;  // order of the LDS-resident triangle
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+constexpr int TS = 64;   // order of the LDS-resident triangle
+constexpr int LS = TS + 1;  // LDS row stride (odd: column reads are conflict-free)
 
 __device__ __forceinline__ bool tri_is_lower(int tri) { return tri == TRI_LOWER || tri == TRI_LOWER_UNIT; }
 __device__ __forceinline__ bool tri_is_unit(int tri) { return tri == TRI_LOWER_UNIT || tri == TRI_UPPER_UNIT; }
-__device__ __forceinline__ int tri_flip(int tri) {
-  switch (tri) {
-    case TRI_LOWER: return TRI_UPPER;
-    case TRI_LOWER_UNIT: return TRI_UPPER_UNIT;
-    case TRI_UPPER: return TRI_LOWER;
-    case TRI_UPPER_UNIT: return TRI_LOWER_UNIT;
-    default: return tri;
-  }
-}
 
-// Solve T' X' = B' for a 64-column strip, where (left side)  T' = op(T), X' = X,
-// or (right side) T' = op(T)^T, X' = X^T, B' = B^T.
-template <bool RIGHT>
-__device__ __forceinline__ void trsm_small_body(int tri, int trans, int nt, int nr, const DOp& T, const DOut& B,
-                                                int identity, int c0) {
-  __shared__ double Ts[TS][TS + 1];
-  __shared__ double Xs[TS][TS + 1];
+// Modes of the base-case kernel.
+enum : int { SM_LEFT = 0, SM_RIGHT = 1, SM_INV = 2 };
+
+// Base case, 256 threads, triangle of order nt <= 64:
+//   SM_LEFT : B(:, strip) <- op(T)^{-1} B(:, strip)      (B is nt x nr)
+//   SM_RIGHT: B(strip, :) <- B(strip, :) op(T)^{-1}      (B is nr x nt)
+//   SM_INV  : D block y <- op(T_yy)^{-1}, T_yy the y-th 64x64 diagonal block
+// Each is M x = b for 64 columns x at once: M = op(T) with x the columns of
+// the strip (left, inverse: b = identity columns), or M = op(T)^T with x the
+// rows of the strip (right).  An upper M is solved as J M J (J reverses the
+// order of the first nt indices), which is lower.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trsm64_f64(int tri, int trans, int n, int nr, DOp T, DOut B, double* D,
+                                                   int ldd) {
+  __shared__ double Ls[TS * LS];
+  __shared__ double rd[TS];
   const int tid = threadIdx.x;
-  const int triP = RIGHT ? tri_flip(tri) : tri;   // triangle of T'
-  const bool tT = (trans != 0) != RIGHT;          // T'(i,k) = stored(k,i) if tT
-  const bool lower = tri_is_lower(triP);
-  const bool unit = tri_is_unit(triP);
-
-  // T' into LDS (masked to its triangle; unit diagonal read as one)
-  for (int e = tid; e < TS * TS; e += 256) {
-    const int r = e / TS, cc = e % TS;          // stored coordinates (coalesced reads)
-    const int i = tT ? cc : r, k = tT ? r : cc;  // logical coordinates in T'
-    double v = 0.0;
-    if (i < nt && k < nt) {
-      const bool in = lower ? (k <= i) : (k >= i);
-      if (in) {
-        if (unit && i == k) v = 1.0;
-        else {
-          const int pr = T.rows ? T.rows[r] : r;
-          v = T.p[(long long)pr * T.ld + cc];
-        }
-      }
-    }
-    Ts[i][k] = v;
+  const bool unit = tri_is_unit(tri);
+  const bool right = MODE == SM_RIGHT;
+  const bool mLower = tri_is_lower(tri) != right;           // `tri` describes op(T); M = op(T)^T on the right
+  const bool sT = (trans != 0) != right;                    // M(i,k) = stored(k,i)
+  int nt = n, d0 = 0;
+  if (MODE == SM_INV) {
+    d0 = blockIdx.y * TS;
+    nt = min(TS, n - d0);
   }
-  // B' strip into LDS: Xs[k][c] = B'(k, c0 + c)
-  for (int e = tid; e < TS * TS; e += 256) {
-    int k, c;
-    if (!RIGHT) { k = e / TS; c = e % TS; } else { c = e / TS; k = e % TS; }
-    const int gc = c0 + c;
-    double v = 0.0;
-    if (k < nt && gc < nr) {
-      if (identity) v = (k == gc) ? 1.0 : 0.0;
-      else if (!RIGHT) {
-        const int pr = B.rows ? B.rows[k] : k;
-        v = B.p[(long long)pr * B.ld + gc];
-      } else {
-        const int pr = B.rows ? B.rows[gc] : gc;
-        v = B.p[(long long)pr * B.ld + k];
-      }
+  auto rv = [&](int i) { return (mLower || i >= nt) ? i : nt - 1 - i; };   // solve index <-> logical index
+  // Global loads: in-range (clamped) addresses, issued unconditionally in
+  // unrolled batches so that they overlap; out-of-range values are replaced.
+  const int wr = tid >> 6, lc = tid & 63;      // T: a wave reads stored rows wr + 4u, columns lc
+  const int c = tid >> 2, g = tid & 3;         // quad layout of the solve
+  const int s0 = blockIdx.x * TS;
+  double tv[16], x[16];
+  int prx[16];                                 // left: physical rows of x
+  double* bpr = nullptr;                       // right: the strip row of this thread's x
+  {
+    const int cc = min(lc, nt - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = min(wr + 4 * u, nt - 1);
+      const int pr = T.rows ? T.rows[d0 + r] : d0 + r;
+      tv[u] = T.p[(long long)pr * T.ld + d0 + cc];
     }
-    Xs[k][c] = v;
+    if (MODE == SM_LEFT) {
+      const int col = s0 + min(c, nr - 1);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int li = min(rv(4 * m + g), nt - 1);
+        prx[m] = B.rows ? B.rows[li] : li;
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) x[m] = B.p[(long long)prx[m] * B.ld + col];
+    } else if (MODE == SM_RIGHT) {
+      const int row = s0 + min(c, nr - 1);
+      bpr = B.p + (long long)(B.rows ? B.rows[row] : row) * B.ld;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) x[m] = bpr[min(rv(4 * m + g), nt - 1)];
+    }
+  }
+  // ---- M into LDS in solve coordinates, padded with the identity ----
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int r = wr + 4 * u, cc = lc;           // stored coordinates
+    const int i = sT ? cc : r, k = sT ? r : cc;  // logical M(i, k)
+    const int si = rv(i), sk = rv(k);            // solve coordinates
+    const bool in = i < nt && k < nt && (sk < si || (i == k && !unit));
+    Ls[si * LS + sk] = in ? tv[u] : (si == sk ? 1.0 : 0.0);
   }
   __syncthreads();
-
-  // wave w owns columns [16w, 16w + 16); lane group g = lane / 16 owns rows = g (mod 4)
-  const int lane = tid & 63;
-  const int c = (tid >> 6) * 16 + (lane & 15);
-  const int g = lane >> 4;
-  if (lower) {
-    for (int k = 0; k < nt; ++k) {
-      if ((k & 3) == g && !unit) Xs[k][c] = Xs[k][c] / Ts[k][k];
-      wave_sync();
-      const double xk = Xs[k][c];
-      for (int i = k + 1 + ((g - (k + 1)) & 3); i < nt; i += 4) Xs[i][c] -= Ts[i][k] * xk;
-      wave_sync();
-    }
-  } else {
-    for (int k = nt - 1; k >= 0; --k) {
-      if ((k & 3) == g && !unit) Xs[k][c] = Xs[k][c] / Ts[k][k];
-      wave_sync();
-      const double xk = Xs[k][c];
-      for (int i = g; i < k; i += 4) Xs[i][c] -= Ts[i][k] * xk;
-      wave_sync();
-    }
+  if (tid < TS) rd[tid] = 1.0 / Ls[tid * LS + tid];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int si = 4 * m + g, li = rv(si);
+    if (MODE == SM_INV) x[m] = (si == c) ? 1.0 : 0.0;
+    else x[m] = (li < nt && s0 + c < nr) ? x[m] : 0.0;
   }
   __syncthreads();
+  quad_lower_solve<LS>(Ls, rd, x, g, MODE == SM_INV ? (tid >> 6) * 4 : opaque_zero());
 
-  for (int e = tid; e < TS * TS; e += 256) {
-    int k, cc;
-    if (!RIGHT) { k = e / TS; cc = e % TS; } else { cc = e / TS; k = e % TS; }
-    const int gc = c0 + cc;
-    if (k < nt && gc < nr) {
-      if (!RIGHT) {
-        const int pr = B.rows ? B.rows[k] : k;
-        B.p[(long long)pr * B.ld + (B.cols ? B.cols[gc] : gc)] = Xs[k][cc];
-      } else {
-        const int pr = B.rows ? B.rows[gc] : gc;
-        B.p[(long long)pr * B.ld + (B.cols ? B.cols[k] : k)] = Xs[k][cc];
-      }
+  // ---- results ----
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int si = 4 * m + g, li = rv(si);
+    if (MODE == SM_INV) {
+      // column c of (J M J)^{-1} is column rv(c) of M^{-1}, row si is row li
+      if (li < nt && c < nt) D[(long long)(d0 + li) * ldd + d0 + rv(c)] = x[m];
+    } else if (li < nt && s0 + c < nr) {
+      if (MODE == SM_LEFT) B.p[(long long)prx[m] * B.ld + s0 + c] = x[m];
+      else bpr[li] = x[m];
     }
   }
-}
-
-template <bool RIGHT>
-__global__ __launch_bounds__(256) void k_trsm_small_f64(int tri, int trans, int nt, int nr, DOp T, DOut B,
-                                                        int identity) {
-  trsm_small_body<RIGHT>(tri, trans, nt, nr, T, B, identity, blockIdx.x * TS);
-}
-
-// Left solve op(T) X = B with a triangle of order nt <= NT held in LDS and one
-// right-hand-side column per lane held in registers (x[NT], fully unrolled):
-// step k finalizes x_k and subtracts T(i,k) x_k from the rows below (above);
-// T(i,k) is the same for every lane, so each LDS read is a broadcast.
-template <int NT>
-__device__ __forceinline__ void trsm_left_reg_body(int tri, int trans, int nt, int nr, const DOp& T, const DOut& B,
-                                                   int identity, int c0) {
-  __shared__ double Ts[NT][NT + 1];
-  const int lane = threadIdx.x;
-  const bool lower = tri_is_lower(tri), unit = tri_is_unit(tri);
-  for (int e = lane; e < NT * NT; e += 64) {
-    const int r = e / NT, cc = e % NT;           // stored coordinates (coalesced)
-    const int i = trans ? cc : r, k = trans ? r : cc;
-    double v = 0.0;
-    if (i < nt && k < nt && (lower ? k <= i : k >= i)) {
-      if (unit && i == k) v = 1.0;
-      else {
-        const int pr = T.rows ? T.rows[r] : r;
-        v = T.p[(long long)pr * T.ld + cc];
-      }
-    }
-    Ts[i][k] = v;
-  }
-  const int c = c0 + lane;
-  const bool act = c < nr;
-  double x[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    double v = 0.0;
-    if (i < nt && act) {
-      if (identity) v = (i == c) ? 1.0 : 0.0;
-      else {
-        const int pr = B.rows ? B.rows[i] : i;
-        v = B.p[(long long)pr * B.ld + c];
-      }
-    }
-    x[i] = v;
-  }
-  __syncthreads();
-  if (lower) {
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      if (k < nt) {
-        if (!unit) x[k] = x[k] / Ts[k][k];
-#pragma unroll
-        for (int i = k + 1; i < NT; ++i)
-          if (i < nt) x[i] -= Ts[i][k] * x[k];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int k = NT - 1; k >= 0; --k) {
-      if (k < nt) {
-        if (!unit) x[k] = x[k] / Ts[k][k];
-#pragma unroll
-        for (int i = 0; i < k; ++i) x[i] -= Ts[i][k] * x[k];
-      }
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int i = 0; i < NT; ++i)
-      if (i < nt) {
-        const int pr = B.rows ? B.rows[i] : i;
-        B.p[(long long)pr * B.ld + (B.cols ? B.cols[c] : c)] = x[i];
-      }
-  }
-}
-
-template <int NT>
-__global__ __launch_bounds__(64) void k_trsm_left_reg_f64(int tri, int trans, int nt, int nr, DOp T, DOut B,
-                                                          int identity) {
-  trsm_left_reg_body<NT>(tri, trans, nt, nr, T, B, identity, blockIdx.x * 64);
-}
-
-// Inverse of every 64x64 diagonal block of op(T) (order n), block y written to
-// D + 64y * ldd + 64y (identity right-hand side, register-resident columns).
-__global__ __launch_bounds__(64) void k_tri_inv64_reg_f64(int tri, int trans, int n, DOp T, double* D, int ldd) {
-  const int d = blockIdx.y * TS;
-  const int nt = min(TS, n - d);
-  DOp Tb = T;
-  Tb.p = T.p + d + (T.rows ? 0 : (long long)d * T.ld);
-  Tb.rows = T.rows ? T.rows + d : nullptr;
-  DOut Db{D + (long long)d * ldd + d, ldd, nullptr, nullptr};
-  trsm_left_reg_body<TS>(tri, trans, nt, nt, Tb, Db, 1, 0);
 }
 
 inline bool host_lower(int tri) { return tri == TRI_LOWER || tri == TRI_LOWER_UNIT; }
@@ -245,24 +142,17 @@ inline DOp as_op(DOut B) {
 
 }  // namespace
 
-void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, bool identity) {
+void trsm_small_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B) {
   if (nt <= 0 || nr <= 0) return;
   if (nt > TS) throw std::runtime_error("trsm_small_f64: triangle larger than 64");
-  if (B.cols && !identity) throw std::runtime_error("trsm_small_f64: column scatter needs identity mode");
+  if (B.cols) throw std::runtime_error("trsm_small_f64: column scatter not supported");
   const int grid = ceil_div(nr, TS);
-  if (right) {
-    hipLaunchKernelGGL(k_trsm_small_f64<true>, dim3(grid), dim3(256), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
-                       identity ? 1 : 0);
-  } else if (nt <= 16) {
-    hipLaunchKernelGGL(k_trsm_left_reg_f64<16>, dim3(grid), dim3(64), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
-                       identity ? 1 : 0);
-  } else if (nt <= 32) {
-    hipLaunchKernelGGL(k_trsm_left_reg_f64<32>, dim3(grid), dim3(64), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
-                       identity ? 1 : 0);
-  } else {
-    hipLaunchKernelGGL(k_trsm_left_reg_f64<64>, dim3(grid), dim3(64), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
-                       identity ? 1 : 0);
-  }
+  if (right)
+    hipLaunchKernelGGL(k_trsm64_f64<SM_RIGHT>, dim3(grid), dim3(256), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
+                       (double*)nullptr, 0);
+  else
+    hipLaunchKernelGGL(k_trsm64_f64<SM_LEFT>, dim3(grid), dim3(256), 0, s, tri, trans ? 1 : 0, nt, nr, T, B,
+                       (double*)nullptr, 0);
   FROB_LAUNCH_CHECK();
 }
 
@@ -294,7 +184,8 @@ inline Strided diag_strided(DOp T, bool trans, int r, int c, int st) {
 
 void dinv_f64(hipStream_t s, int tri, bool trans, int n, DOp T, int nb, double* D, int ldd, double* tmp) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_tri_inv64_reg_f64, dim3(1, ceil_div(n, TS)), dim3(64), 0, s, tri, trans ? 1 : 0, n, T, D, ldd);
+  hipLaunchKernelGGL(k_trsm64_f64<SM_INV>, dim3(1, ceil_div(n, TS)), dim3(256), 0, s, tri, trans ? 1 : 0, n, 0, T,
+                     DOut{nullptr, 0, nullptr, nullptr}, D, ldd);
   FROB_LAUNCH_CHECK();
   const bool lower = host_lower(tri);
   const int triW = lower ? TRI_LOWER : TRI_UPPER;
@@ -400,7 +291,7 @@ size_t trsm_work_elems(int nt) { return (size_t)nt * nt + (size_t)nt * (DNB / 4)
 void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, double* work) {
   if (nt <= 0 || nr <= 0) return;
   if (nt <= TS) {
-    trsm_small_f64(s, right, tri, trans, nt, nr, T, B, false);
+    trsm_small_f64(s, right, tri, trans, nt, nr, T, B);
     return;
   }
   if (B.cols) throw std::runtime_error("trsm_f64: column scatter not supported");
