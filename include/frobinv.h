@@ -42,7 +42,8 @@ typedef enum {
                                is invertible iff M is); with the shift disabled, also a singular real part A */
   FROB_NOT_HPD = 2,         /* a Cholesky factorization met a non-positive pivot (Lemma 4.5 says A and C are
                                positive definite whenever M is Hermitian positive definite) */
-  FROB_NO_CONVERGENCE = 3,  /* iterative refinement did not reduce the residual below its tolerance */
+  FROB_NO_CONVERGENCE = 3,  /* Newton-Schulz refinement cannot start: ||I - M X||_F >= 1 for the unrefined
+                               inverse (X is returned unrefined) */
   FROB_E_ARG = -1,          /* invalid argument (null pointer, n out of range, leading dimension too small) */
   FROB_E_ALLOC = -2,        /* device or pinned-host allocation failed */
   FROB_E_HIP = -3,          /* a HIP runtime call failed */
@@ -58,12 +59,27 @@ typedef enum {
   FROB_SHIFT_ON = 2     /* always Algorithm 6                                                               */
 } frob_shift_t;
 
+/* Operand precision of the matrix-core products inside the factorizations,
+ * triangular solves and GEMMs (the mixed-precision variant).  Storage stays
+ * FP64; FP32/BF16 operands are rounded when a tile is staged and accumulated
+ * in FP32.  Pivot search, scaling, the Cholesky diagonal blocks and the small
+ * triangular base cases stay FP64.  FP64 accuracy is recovered with
+ * Newton-Schulz refinement (opts.refine), whose residual I - M X is formed in
+ * FP64. */
+typedef enum {
+  FROB_PREC_F64 = 0,
+  FROB_PREC_F32 = 1,
+  FROB_PREC_BF16 = 2
+} frob_prec_t;
+
 typedef struct {
   int shift;            /* frob_shift_t, default FROB_SHIFT_AUTO                                            */
   double mu;            /* shift to use when shifting; mu <= 0 draws mu ~ U(0,1) from the handle's generator  */
   uint64_t seed;        /* 0: keep the handle's generator state; otherwise reseed it first                   */
-  int refine;           /* number of Newton-Schulz steps X <- X + X (I - M X) after the inversion (0 = none)  */
-  int reserved[7];
+  int refine;           /* maximum number of Newton-Schulz steps X <- X + X (I - M X) (0 = none)           */
+  int prec;             /* frob_prec_t, default FROB_PREC_F64                                               */
+  double refine_tol;    /* stop refining once ||I - M X||_F / sqrt(n) <= refine_tol (<= 0: 1e-14)            */
+  int reserved[4];
 } frob_opts_t;
 
 typedef struct {
@@ -72,7 +88,9 @@ typedef struct {
   double mu_used;       /* shift actually applied (0 if none)                                               */
   int shifts_tried;     /* number of shifts drawn (Algorithm 6 re-draws when A - mu B is singular)           */
   int refine_steps;     /* Newton-Schulz steps applied                                                     */
-  double reserved[4];
+  double resid0;        /* ||I - M X||_F / sqrt(n) of the unrefined inverse (refine > 0 only)              */
+  double resid;         /* the same for the returned inverse (refine > 0 only)                             */
+  double reserved[2];
 } frob_result_t;
 
 /* Fill *opts with the defaults (FROB_SHIFT_AUTO, mu drawn, no refinement). */
@@ -137,6 +155,20 @@ frob_status_t frob_cinv_lu(frob_handle_t handle, int n, const double *Mr, const 
  * (W = R^{-H} by a triangular inverse, X = W^H W). */
 frob_status_t frob_cinv_chol(frob_handle_t handle, int n, const double *Mr, const double *Mi, int ldm, double *Xr,
                              double *Xi, int ldx, int form, frob_result_t *res);
+
+/* Reverse-mode derivative of the inversion for a batch of matrices (the
+ * adjoint line of growth): with X = M^{-1} and G = dL/dRe X + i dL/dIm X,
+ *   dM = dL/dRe M + i dL/dIm M = -X^H G X^H
+ * (from dX = -X dM X; for L = Re tr(W X), G = W^H).  Both complex products
+ * use Gauss's three-real-multiplication scheme (Proposition 2.2, tau = 1):
+ * three batched real matrix-core GEMMs each instead of four.
+ *   storage : FROB_PREC_F64 (double arrays, FP64 GEMMs) or FROB_PREC_F32
+ *             (float arrays, FP32 GEMMs with FP32 accumulation)
+ *   Xr, Xi, Gr, Gi : batch x n x n inputs, contiguous (matrix b at offset b n^2)
+ *   dMr, dMi       : batch x n x n outputs; must not alias the inputs
+ * Returns FROB_E_ARG for bad sizes, a bad storage code, null or aliased pointers. */
+frob_status_t frob_inv_adjoint(frob_handle_t handle, int batch, int n, int storage, const void *Xr, const void *Xi,
+                               const void *Gr, const void *Gi, void *dMr, void *dMi);
 
 /* Kernel timing with HIP events (for measurement).  When enabled, the library
  * records an event pair on the handle's stream around every launch of a

@@ -14,12 +14,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNotHPDError,  # noqa: F401
-                   FrobSingularError, frob_opts_t, frob_result_t)
+from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_SHIFT_AUTO, FROB_SHIFT_OFF,  # noqa: F401
+                   FROB_SHIFT_ON, FrobError, FrobNoConvergenceError, FrobNotHPDError, FrobSingularError,
+                   frob_opts_t, frob_result_t)
 
 __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_cinv_lu", "frob_cinv_chol",
-           "FrobError", "FrobSingularError", "FrobNotHPDError", "FROB_SHIFT_OFF", "FROB_SHIFT_AUTO",
-           "FROB_SHIFT_ON", "load_library"]
+           "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
+           "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16", "load_library"]
 
 
 def load_library():
@@ -90,13 +91,15 @@ def _mat(t, n_rows, n_cols, name):
     return ctypes.c_void_p(t.data_ptr()), int(t.stride(0))
 
 
-def _opts(shift, mu, seed, refine):
+def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0):
     o = frob_opts_t()
     _lib.load().frob_default_opts(ctypes.byref(o))
     o.shift = int(shift)
     o.mu = float(mu)
     o.seed = int(seed)
     o.refine = int(refine)
+    o.prec = int(prec)
+    o.refine_tol = float(refine_tol)
     return o
 
 
@@ -105,8 +108,12 @@ def _empty_like_sq(A, n):
     return torch.empty((n, n), dtype=torch.float64, device=A.device)
 
 
-def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0):
-    """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting)."""
+def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0,
+                     prec=FROB_PREC_F64, refine_tol=0.0):
+    """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting).
+
+    prec: operand precision of the matrix-core products (FROB_PREC_F64/F32/BF16);
+    refine: maximum number of Newton-Schulz steps (residual formed in FP64)."""
     n = A.shape[0]
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
     Xi = _empty_like_sq(A, n) if Xi is None else Xi
@@ -117,13 +124,13 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
-    o, r = _opts(shift, mu, seed, refine), frob_result_t()
+    o, r = _opts(shift, mu, seed, refine, prec, refine_tol), frob_result_t()
     st = _lib.load().frob_inv_general(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, "frob_inv_general", r)
     return Xr, Xi, r.as_dict()
 
 
-def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0):
+def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_F64, refine_tol=0.0):
     """(A + iB)^{-1} for Hermitian positive definite A + iB (Algorithm 7)."""
     n = A.shape[0]
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
@@ -135,7 +142,7 @@ def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0):
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
-    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine), frob_result_t()
+    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol), frob_result_t()
     st = _lib.load().frob_inv_hpd(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, "frob_inv_hpd", r)
     return Xr, Xi, r.as_dict()
@@ -189,3 +196,36 @@ def frob_cinv_lu(h: Handle, Mr, Mi, Xr=None, Xi=None, *, form=1):
 def frob_cinv_chol(h: Handle, Mr, Mi, Xr=None, Xi=None, *, form=1):
     """Baseline: complex-arithmetic Cholesky inversion (Algorithm 8; form 0 as printed, 1 potri style)."""
     return _cinv("frob_cinv_chol", h, Mr, Mi, Xr, Xi, form)
+
+
+def _batch3(t, name, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dim() != 3:
+        raise TypeError(f"{name}: expected a (batch, n, n) tensor on a ROCm device")
+    if t.dtype not in (torch.float32, torch.float64) or (dtype is not None and t.dtype != dtype):
+        raise TypeError(f"{name}: expected float32 or float64 matching the other operands")
+    if t.shape[1] != t.shape[2] or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous square matrices")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def frob_inv_adjoint(h: Handle, Xr, Xi, Gr, Gi, dMr=None, dMi=None):
+    """dM = -X^H G X^H for a batch of matrices (reverse-mode derivative of M -> M^{-1}).
+
+    All operands are (batch, n, n) contiguous float32 or float64 tensors; G is the
+    gradient with respect to X in PyTorch's convention (dL/dRe X + i dL/dIm X)."""
+    import torch
+    dt = Xr.dtype
+    b, n = Xr.shape[0], Xr.shape[1]
+    dMr = torch.empty_like(Xr) if dMr is None else dMr
+    dMi = torch.empty_like(Xr) if dMi is None else dMi
+    ptrs = [_batch3(t, nm, dt) for t, nm in ((Xr, "Xr"), (Xi, "Xi"), (Gr, "Gr"), (Gi, "Gi"), (dMr, "dMr"),
+                                              (dMi, "dMi"))]
+    for t in (Xi, Gr, Gi, dMr, dMi):
+        if t.shape != Xr.shape:
+            raise ValueError("all operands must have the same shape")
+    storage = FROB_PREC_F32 if dt == torch.float32 else FROB_PREC_F64
+    h.bind_stream()
+    st = _lib.load().frob_inv_adjoint(h.ptr, b, n, storage, *ptrs)
+    _lib.check(st, "frob_inv_adjoint")
+    return dMr, dMi

@@ -26,21 +26,26 @@ FROB_E_INTERNAL = -4
 FROB_SHIFT_OFF = 0
 FROB_SHIFT_AUTO = 1
 FROB_SHIFT_ON = 2
+FROB_PREC_F64 = 0
+FROB_PREC_F32 = 1
+FROB_PREC_BF16 = 2
 
 
 class frob_opts_t(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("refine", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+                ("refine", ctypes.c_int), ("prec", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("reserved", ctypes.c_int * 4)]
 
 
 class frob_result_t(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int), ("stage", ctypes.c_int), ("mu_used", ctypes.c_double),
                 ("shifts_tried", ctypes.c_int), ("refine_steps", ctypes.c_int),
-                ("reserved", ctypes.c_double * 4)]
+                ("resid0", ctypes.c_double), ("resid", ctypes.c_double), ("reserved", ctypes.c_double * 2)]
 
     def as_dict(self):
         return {"info": self.info, "stage": self.stage, "mu_used": self.mu_used,
-                "shifts_tried": self.shifts_tried, "refine_steps": self.refine_steps}
+                "shifts_tried": self.shifts_tried, "refine_steps": self.refine_steps,
+                "resid0": self.resid0, "resid": self.resid}
 
 
 _vp = ctypes.c_void_p
@@ -61,6 +66,7 @@ SIGNATURES = {
     "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
+    "frob_inv_adjoint": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "frob_profile_enable": (_i, [_vp, _i]),
     "frob_profile_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_d),
                                ctypes.POINTER(_d)]),
@@ -105,6 +111,10 @@ class FrobNotHPDError(FrobError):
     pass
 
 
+class FrobNoConvergenceError(FrobError):
+    """Newton-Schulz refinement could not start (||I - M X||_F >= 1); X is unrefined."""
+
+
 def check(status: int, where: str, result: frob_result_t | None = None):
     if status == FROB_OK:
         return
@@ -112,4 +122,6 @@ def check(status: int, where: str, result: frob_result_t | None = None):
         raise FrobSingularError(status, where, result)
     if status == FROB_NOT_HPD:
         raise FrobNotHPDError(status, where, result)
+    if status == FROB_NO_CONVERGENCE:
+        raise FrobNoConvergenceError(status, where, result)
     raise FrobError(status, where, result)

@@ -49,6 +49,31 @@ __global__ void k_axpby(int m, int n, double a, const double* __restrict__ X, in
   *y = (b == 0.0) ? a * x : a * x + b * *y;
 }
 
+// R <- I - R (real and imaginary planes), sumsq += ||R||_F^2 (one atomic per block)
+__global__ void k_resid_form(int n, double* __restrict__ Rr, double* __restrict__ Ri, int ld, double* sumsq) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  double acc = 0.0;
+  if (j < n) {
+    double* pr = Rr + (long long)i * ld + j;
+    double* pi = Ri + (long long)i * ld + j;
+    const double vr = (i == j ? 1.0 : 0.0) - *pr, vi = -*pi;
+    *pr = vr;
+    *pi = vi;
+    acc = vr * vr + vi * vi;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  __shared__ double part[EB / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < EB / 64; ++w) t += part[w];
+    atomicAdd(sumsq, t);
+  }
+}
+
 __global__ void k_rotate(int m, int n, double mu, const double* __restrict__ A, int lda,
                          const double* __restrict__ B, int ldb, double* X1, int ld1, double* X2, int ld2) {
   const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
@@ -76,6 +101,12 @@ __global__ void k_zero_upper(int n, double* a, int lda) {
 }
 
 }  // namespace
+
+void resid_form_f64(hipStream_t s, int n, double* Rr, double* Ri, int ld, double* sumsq) {
+  fill_f64(s, 1, 1, 0.0, sumsq, 1);
+  hipLaunchKernelGGL(k_resid_form, grid2d(n, n), dim3(EB), 0, s, n, Rr, Ri, ld, sumsq);
+  FROB_LAUNCH_CHECK();
+}
 
 void iota_i32(hipStream_t s, int n, int* p) {
   if (n <= 0) return;

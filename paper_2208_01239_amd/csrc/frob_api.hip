@@ -7,6 +7,7 @@
 // The complex-arithmetic baselines (Algorithms 4 and 8) live in cbase.hip.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <new>
 
 #include "../../include/frobinv.h"
@@ -219,6 +220,8 @@ void frob_default_opts(frob_opts_t* o) {
   o->mu = 0.0;
   o->seed = 0;
   o->refine = 0;
+  o->prec = FROB_PREC_F64;
+  o->refine_tol = 0.0;
 }
 
 frob_status_t frob_create(frob_handle_t* out, int device) {
@@ -236,6 +239,8 @@ frob_status_t frob_create(frob_handle_t* out, int device) {
     h->stream = nullptr;   // the device's null stream until frob_set_stream says otherwise
     FROB_HIP(hipMalloc((void**)&h->dinfo, sizeof(int) * INFO_SLOTS));
     FROB_HIP(hipHostMalloc((void**)&h->hinfo, sizeof(int) * INFO_SLOTS, hipHostMallocDefault));
+    FROB_HIP(hipMalloc((void**)&h->dnorm, sizeof(double)));
+    FROB_HIP(hipHostMalloc((void**)&h->hnorm, sizeof(double), hipHostMallocDefault));
   } catch (...) {
     frob_destroy(h);
     return FROB_E_HIP;
@@ -251,6 +256,8 @@ frob_status_t frob_destroy(frob_handle_t h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->dinfo) (void)hipFree(h->dinfo);
   if (h->hinfo) (void)hipHostFree(h->hinfo);
+  if (h->dnorm) (void)hipFree(h->dnorm);
+  if (h->hnorm) (void)hipHostFree(h->hnorm);
   for (auto& p : h->pending) { (void)hipEventDestroy(p.e0); (void)hipEventDestroy(p.e1); }
   for (auto e : h->pool) (void)hipEventDestroy(e);
   delete h;
@@ -269,7 +276,9 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
                                double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
   if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
-  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.refine < 0) return FROB_E_ARG;
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.refine < 0 || o.prec < FROB_PREC_F64 ||
+      o.prec > FROB_PREC_BF16)
+    return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;
@@ -287,6 +296,7 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
     std::memset(&r, 0, sizeof(r));
     frob_status_t st = FROB_OK;
     bool done = false;
+    LowPrecScope lp(o.prec);   // FP32 / BF16 operands in the products of the factorization passes
     if (o.shift != FROB_SHIFT_ON) {
       fill_i32(s, INFO_SLOTS, 0, h->dinfo);
       frob_lu_pass(s, n, A, lda, B, ldb, Xr, Xi, ldx, w, h->dinfo);
@@ -317,7 +327,8 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
     }
     if (!done) st = FROB_SINGULAR;
     if (st == FROB_OK && o.refine > 0) {
-      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, c, &r);
+      LowPrecScope fp64(LP_NONE);   // the residual is formed in FP64
+      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, c, &r);
     } else if (st == FROB_OK) {
       FROB_HIP(hipStreamSynchronize(s));
     }
@@ -330,7 +341,7 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
                            double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
   if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
-  if (o.refine < 0) return FROB_E_ARG;
+  if (o.refine < 0 || o.prec < FROB_PREC_F64 || o.prec > FROB_PREC_BF16) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
@@ -346,6 +357,7 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     double* tmp = c.take<double>(solver_work_elems(n));
     const int ld = n;
     fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+    std::unique_ptr<LowPrecScope> lp(new LowPrecScope(o.prec));
     // step 1: A = R1^T R1 (stored as the lower factor L1 = R1^T)
     copy_f64(s, n, n, A, lda, nullptr, F, ld);
     potrf_f64(s, n, F, ld, h->dinfo + 0, tmp);
@@ -371,13 +383,15 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
       gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
                DOut{Xi, ldx, nullptr, nullptr});
     }
+    lp.reset();
     read_info(h);
     frob_result_t r;
     std::memset(&r, 0, sizeof(r));
     frob_status_t st = FROB_OK;
     if (h->hinfo[0]) { st = FROB_NOT_HPD; r.info = h->hinfo[0]; r.stage = 1; }
     else if (h->hinfo[1]) { st = FROB_NOT_HPD; r.info = h->hinfo[1]; r.stage = 2; }
-    if (st == FROB_OK && o.refine > 0) st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, c, &r);
+    if (st == FROB_OK && o.refine > 0)
+      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, c, &r);
     if (res) *res = r;
     return st;
   });
@@ -390,7 +404,7 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
       ldxy < nrhs)
     return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
-  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON) return FROB_E_ARG;
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.prec != FROB_PREC_F64) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;

@@ -353,11 +353,24 @@ int gemm_pick_cfg(int M, int N, int need) {
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+namespace {
+thread_local int t_lp_mode = LP_NONE;
+}
+int lp_mode() { return t_lp_mode; }
+LowPrecScope::LowPrecScope(int mode) : prev(t_lp_mode) { t_lp_mode = mode; }
+LowPrecScope::~LowPrecScope() { t_lp_mode = prev; }
+
 void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
                       int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
                       long long sC, int rsA, int rsB, int rsC, int need) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0 && beta == 1.0) return;
+  if (t_lp_mode != LP_NONE && triA == TRI_NONE && triB == TRI_NONE && need == GEMM_NEED_ANY && !C.cols &&
+      K >= 32 && (batch == 1 || (rsA == 0 && rsB == 0 && rsC == 0))) {
+    gemm_lp(s, t_lp_mode, ta, tb, M, N, K, alpha, A.p, A.ld, A.rows, B.p, B.ld, B.rows, beta, C.p, C.ld, C.rows,
+            lowerOnly, batch, sA, sB, sC);
+    return;
+  }
   GemmF64Params p;
   p.M = M; p.N = N; p.K = K < 0 ? 0 : K;
   p.alpha = alpha; p.beta = beta;

@@ -22,6 +22,8 @@ struct frob_handle {
   size_t ws_cap = 0;
   int* dinfo = nullptr;          // device status words (factorization info)
   int* hinfo = nullptr;          // pinned host copy
+  double* dnorm = nullptr;       // device scalar for residual norms
+  double* hnorm = nullptr;       // pinned host copy
   uint64_t rng = 0;              // splitmix64 state for the shift mu
   int prof = 0;                  // profiling enabled
   std::vector<frob_prof_pending> pending;
@@ -72,9 +74,10 @@ void* ws_reserve(frob_handle* h, size_t bytes);
 void read_info(frob_handle* h);
 
 // Newton-Schulz refinement X <- X + X (I - M X) with complex products done by
-// Gauss's three-real-multiplication scheme (Proposition 2.2, tau = 1).
+// Gauss's three-real-multiplication scheme (Proposition 2.2, tau = 1); the
+// residual is formed in FP64, the correction product in precision `prec`.
 size_t ns_ws_bytes(int n, int steps);
 frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
-                        double* Xi, int ldx, int steps, Carve& c, frob_result_t* r);
+                        double* Xi, int ldx, int max_steps, double tol, int prec, Carve& c, frob_result_t* r);
 
 }  // namespace frob

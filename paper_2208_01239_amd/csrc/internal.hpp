@@ -23,6 +23,27 @@ void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, doub
                       int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,
                       long long sC, int rsA, int rsB, int rsC, int need = GEMM_NEED_ANY);
 
+// ------------------------------------------------------ low-precision GEMM
+// Same product with the operands rounded to FP32 or BF16 when staged and FP32
+// accumulation (gemm_lp.hip); storage FP64 or FP32.
+enum { LP_NONE = 0, LP_F32 = 1, LP_BF16 = 2 };
+void gemm_lp(hipStream_t s, int mode, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+             const int* rA, const double* B, int ldb, const int* rB, double beta, double* C, int ldc, const int* rC,
+             bool lowerOnly, int batch, long long sA, long long sB, long long sC);
+void gemm_lp(hipStream_t s, int mode, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+             const int* rA, const float* B, int ldb, const int* rB, double beta, float* C, int ldc, const int* rC,
+             bool lowerOnly, int batch, long long sA, long long sB, long long sC);
+// While a LowPrecScope is alive on the calling host thread, gemm_f64 sends its
+// plain products (no triangular operand, no in-place requirement, no column
+// scatter, K >= 32) to gemm_lp in that mode: the mixed-precision
+// factorizations reuse the FP64 drivers unchanged.
+int lp_mode();
+struct LowPrecScope {
+  int prev;
+  explicit LowPrecScope(int mode);
+  ~LowPrecScope();
+};
+
 // Planar complex GEMM, C = alpha op(A) op(B) + beta C with real alpha/beta and
 // op in {N, T, C (conjugate transpose)}; four real MFMA products per tile.
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
@@ -81,6 +102,8 @@ void potrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* info,
 // ------------------------------------------------------------ elementwise ops
 void iota_i32(hipStream_t s, int n, int* p);
 void fill_i32(hipStream_t s, int n, int v, int* p);
+// R <- I - R for a planar complex n x n R; *sumsq (device) <- ||I - R||_F^2
+void resid_form_f64(hipStream_t s, int n, double* Rr, double* Ri, int ld, double* sumsq);
 void copy_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* src_rows, double* dst, int ldd);
 void fill_f64(hipStream_t s, int m, int n, double v, double* dst, int ldd);
 void identity_f64(hipStream_t s, int n, double* dst, int ldd);

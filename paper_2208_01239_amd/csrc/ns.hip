@@ -1,11 +1,19 @@
-// ns.hip -- Newton-Schulz refinement of a computed inverse in FP64.
+// ns.hip -- Newton-Schulz refinement of a computed inverse.
 //
 //   R = I - M X,   X <- X + X R,     so that I - M X_new = (I - M X)^2.
+//
+// The residual and its norm are formed in FP64; the correction X R may use a
+// lower operand precision (its error is relative to the already small R).
+// Refinement stops when ||R||_F / sqrt(n) reaches the tolerance, when it no
+// longer halves (the FP64 rounding floor, about u kappa(M)), or after the
+// step limit; it does not start when ||R||_F >= 1.
 //
 // Both complex products are formed from three real matrix-core GEMMs with
 // Gauss's scheme (Proposition 2.2 with tau = 1):
 //   (P + iQ)(S + iT):  M1 = (P - Q)(S + T), M2 = P T, M3 = Q S,
 //                      real = M1 - M2 + M3, imag = M2 + M3.
+#include <cmath>
+
 #include "common.hpp"
 #include "handle.hpp"
 #include "internal.hpp"
@@ -40,7 +48,7 @@ static void gauss3m(hipStream_t s, int n, const double* Pr, int ldp, const doubl
 }
 
 frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
-                        double* Xi, int ldx, int steps, Carve& c, frob_result_t* r) {
+                        double* Xi, int ldx, int max_steps, double tol, int prec, Carve& c, frob_result_t* r) {
   hipStream_t s = h->stream;
   const size_t nn = (size_t)n * n;
   double* Rr = c.take<double>(nn);
@@ -49,20 +57,40 @@ frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const d
   double* Ui = c.take<double>(nn);
   double* T1 = c.take<double>(nn);
   double* T2 = c.take<double>(nn);
-  for (int k = 0; k < steps; ++k) {
-    // (Rr, Ri) = M X ; then R = I - M X
+  if (!(tol > 0.0)) tol = 1e-14;
+  const double rn = std::sqrt((double)n);
+  double prev = 0.0;
+  int steps = 0;
+  frob_status_t st = FROB_OK;
+  for (int k = 0;; ++k) {
+    // R = I - M X in FP64, and its Frobenius norm
     gauss3m(s, n, A, lda, B, Xr, ldx, Xi, Rr, Ri, n, T1, T2);
-    identity_f64(s, n, Ur, n);
-    axpby_f64(s, n, n, 1.0, Ur, n, -1.0, Rr, n);                   // Rr = I - Re(M X)
-    axpby_f64(s, n, n, 0.0, Ur, n, -1.0, Ri, n);                   // Ri = -Im(M X)
-    // (Ur, Ui) = X R ; X += X R
-    gauss3m(s, n, Xr, ldx, Xi, Rr, n, Ri, Ur, Ui, n, T1, T2);
+    resid_form_f64(s, n, Rr, Ri, n, h->dnorm);
+    FROB_HIP(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    FROB_HIP(hipStreamSynchronize(s));
+    const double fro = std::sqrt(*h->hnorm);
+    const double rho = fro / rn;
+    if (k == 0) {
+      r->resid0 = rho;
+      // I - M X_{k+1} = (I - M X_k)^2: a Frobenius norm >= 1 gives no guarantee of convergence
+      if (!(fro < 1.0)) { st = FROB_NO_CONVERGENCE; r->resid = rho; break; }
+    }
+    r->resid = rho;
+    if (rho <= tol) break;                              // converged
+    if (k > 0 && rho > 0.5 * prev) break;               // no longer contracting: rounding floor reached
+    if (k == max_steps) break;
+    // X <- X + X R
+    {
+      LowPrecScope lp(prec);
+      gauss3m(s, n, Xr, ldx, Xi, Rr, n, Ri, Ur, Ui, n, T1, T2);
+    }
     axpby_f64(s, n, n, 1.0, Ur, n, 1.0, Xr, ldx);
     axpby_f64(s, n, n, 1.0, Ui, n, 1.0, Xi, ldx);
+    prev = rho;
+    ++steps;
   }
-  FROB_HIP(hipStreamSynchronize(s));
   r->refine_steps = steps;
-  return FROB_OK;
+  return st;
 }
 
 }  // namespace frob
