@@ -9,8 +9,13 @@ value is inversions per second on this one GPU.
 
 Also measured (outside the timed steps, same protocol): the HPD path
 (Algorithm 7) on M = Z Z^H + n I, and the complex-arithmetic baselines
-(Algorithms 4 and 8, both as printed and in LAPACK getri/potri form) when the
-library provides them.  The dominant kernel (the n x n x n FP64 matrix-core
+(Algorithms 4 and 8, both as printed and in LAPACK getri/potri form); the
+mixed-precision variant (FP32 / BF16 matrix-core operands plus Newton-Schulz
+refinement with an FP64 residual) on the same matrices; the batched line
+(2048 matrices, orders uniform in [16, 512], half general and half HPD, one
+persistent launch, FP64 and FP32) beside a per-matrix complex-LU loop on a
+sample of it; and the adjoint (256 HPD matrices of order 256, dM = -X^H G X^H
+by three-multiplication complex products, FP32 and FP64).  The dominant kernel (the n x n x n FP64 matrix-core
 GEMM) is timed with HIP events on the library's stream during the timed steps
 and reported against the FP64 matrix peak.  The CPU baseline is the FP64
 oracle of the test suite timed on this host on a smaller matrix of the same
@@ -47,11 +52,79 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _events_ms(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(fi, inputs, h, torch, np, log):
+    """2048 matrices, n ~ U{16..512} (seed 4), kind = i mod 2: one persistent launch."""
+    log("[bench] batched: generating 2048 matrices")
+    ns, kinds, mats = inputs.batch(count=2048, seed=4)
+    flops = float(np.sum(np.where(kinds == 0, 26.0 / 3.0, 19.0 / 3.0) * ns.astype(np.float64) ** 3))
+    out = {}
+    fi.frob_batched_tune(h, fi.FROB_PREC_F64)
+    fi.frob_batched_tune(h, fi.FROB_PREC_F32)
+    for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
+        As = [torch.from_numpy(A).to(dt).cuda() for A, _ in mats]
+        Bs = [torch.from_numpy(B).to(dt).cuda() for _, B in mats]
+        plan = fi.BatchedPlan(As, Bs, kinds)
+        ms = _events_ms(torch, lambda: plan.launch(h))
+        bad = int((plan.info_dev != 0).sum())
+        out[f"batched_{tag}"] = {"ms": ms, "inversions_per_s": 2048 / (ms * 1e-3), "alg_tflops": flops / ms / 1e9,
+                                 "nonzero_info": bad}
+        log(f"[bench] batched {tag}: {ms:.2f} ms")
+        del As, Bs, plan
+    # baseline: per-matrix complex-LU / complex-Cholesky loop on a sample, scaled to the batch
+    idx = np.arange(0, 2048, 32)
+    Ms = [(torch.from_numpy(mats[i][0]).cuda(), torch.from_numpy(mats[i][1]).cuda()) for i in idx]
+
+    def loop():
+        for (a, b), i in zip(Ms, idx):
+            (fi.frob_cinv_lu if kinds[i] == 0 else fi.frob_cinv_chol)(h, a, b)
+    ms = _events_ms(torch, loop, reps=1)
+    out["per_matrix_complex_loop_sampled"] = {"ms_sample": ms, "sample": len(idx),
+                                              "ms_scaled_to_2048": ms * 2048 / len(idx)}
+    return out
+
+
+def bench_adjoint(fi, inputs, h, torch, np, log):
+    """256 HPD matrices of order 256 (seed 5): X by the batched FP32 inversion,
+    then dM = -X^H W^H X^H."""
+    log("[bench] adjoint: generating 256 HPD matrices")
+    mats, ws = inputs.adjoint_batch(count=256, n=256, seed=5)
+    n, b = 256, 256
+    out = {}
+    for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        As = [torch.from_numpy(A).to(dt).cuda() for A, _ in mats]
+        Bs = [torch.from_numpy(B).to(dt).cuda() for _, B in mats]
+        plan = fi.BatchedPlan(As, Bs, [1] * b)
+        fwd_ms = _events_ms(torch, lambda: plan.launch(h))
+        Xr = torch.stack(plan.Xr).contiguous()
+        Xi = torch.stack(plan.Xi).contiguous()
+        Gr = torch.from_numpy(np.stack([w[0].T for w in ws])).to(dt).cuda().contiguous()
+        Gi = torch.from_numpy(np.stack([-w[1].T for w in ws])).to(dt).cuda().contiguous()
+        dMr, dMi = torch.empty_like(Xr), torch.empty_like(Xr)
+        ms = _events_ms(torch, lambda: fi.frob_inv_adjoint(h, Xr, Xi, Gr, Gi, dMr, dMi))
+        out[f"adjoint_{tag}"] = {"forward_batched_ms": fwd_ms, "backward_ms": ms,
+                                 "backward_tflops_3m": 12.0 * b * n ** 3 / ms / 1e9}
+        log(f"[bench] adjoint {tag}: forward {fwd_ms:.2f} ms, backward {ms:.3f} ms")
+        del As, Bs, plan, Xr, Xi, Gr, Gi, dMr, dMi
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding of the "
+              "inversion is not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -133,7 +206,31 @@ def main():
                 except fi.FrobError as e:
                     extra[f"{name}_form{form}_ms"] = None
                     log(f"[bench] {name} form {form} unavailable: {e}")
+        # mixed precision + Newton-Schulz (same general and HPD matrices)
+        for tag, fn, Ma, Mb in (("mp_general", fi.frob_inv_general, dA, dB), ("mp_hpd", fi.frob_inv_hpd, dAh, dBh)):
+            for pname, prec in (("f32", fi.FROB_PREC_F32), ("bf16", fi.FROB_PREC_BF16)):
+                key = f"{tag}_{pname}"
+                log(f"[bench] {key}")
+                try:
+                    res = {}
+
+                    def run_mp():
+                        res.update(fn(h, Ma, Mb, Xr, Xi, prec=prec, refine=8)[2])
+                    t = timed(run_mp, 2, 1)
+                    entry = {"ms": t * 1e3, "refine_steps": res["refine_steps"], "resid0": res["resid0"],
+                             "resid": res["resid"]}
+                    if tag == "mp_general" and os.path.exists(gold):
+                        g = np.load(gold, allow_pickle=False)
+                        gc = g["cols"]
+                        gr, gi = Xr[:, gc].cpu().numpy(), Xi[:, gc].cpu().numpy()
+                        entry["relF_vs_oracle_sampled_cols"] = float(np.sqrt(
+                            np.sum((gr - g["xr"]) ** 2 + (gi - g["xi"]) ** 2) / np.sum(g["xr"] ** 2 + g["xi"] ** 2)))
+                    extra[key] = entry
+                except fi.FrobError as e:
+                    extra[key] = {"status": str(e)}
         del dAh, dBh
+        extra.update(bench_batched(fi, inputs, h, torch, np, log))
+        extra.update(bench_adjoint(fi, inputs, h, torch, np, log))
 
     cpu = None
     if not args.no_cpu_baseline:

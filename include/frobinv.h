@@ -170,6 +170,35 @@ frob_status_t frob_cinv_chol(frob_handle_t handle, int n, const double *Mr, cons
 frob_status_t frob_inv_adjoint(frob_handle_t handle, int batch, int n, int storage, const void *Xr, const void *Xi,
                                const void *Gr, const void *Gi, void *dMr, void *dMi);
 
+/* Batched inversion of matrices of uneven order in one persistent launch
+ * (the batching line of growth).  Each workgroup inverts whole matrices,
+ * largest order first, with Algorithm 5 (kind 0, general) or Algorithm 7
+ * (kind 1, Hermitian positive definite: A symmetric positive definite, B
+ * skew-symmetric, lower triangle of A read).
+ *   count           : number of matrices
+ *   nmax            : upper bound of the orders, 1 <= nmax <= 512 (sizes the workspace)
+ *   n_dev, kind_dev : device arrays of count orders (1..nmax) and kinds
+ *   A_dev, B_dev    : device arrays of count device pointers to n x n inputs (contiguous, row-major)
+ *   Xr_dev, Xi_dev  : device arrays of count device pointers to n x n outputs
+ *   info_dev        : device array of count status words: 0, or 1000000 * stage + column (1-based first
+ *                     zero pivot (kind 0) or non-positive pivot (kind 1); stage 1 = A, stage 2 = C)
+ *   storage         : FROB_PREC_F64 (double matrices) or FROB_PREC_F32 (float matrices, FP32 arithmetic)
+ * Asynchronous on the handle's stream: no host synchronization, no allocation
+ * once the workspace has grown to fit (a first call of the same shape), and
+ * no memset (queue reset by a kernel), so a call can be captured in a HIP
+ * graph and replayed.  The panel width per (kind, order class) comes from
+ * frob_batched_tune (default 16). */
+frob_status_t frob_inv_batched(frob_handle_t handle, int count, int nmax, const int *n_dev, const int *kind_dev,
+                               const void *const *A_dev, const void *const *B_dev, void *const *Xr_dev,
+                               void *const *Xi_dev, int *info_dev, int storage);
+
+/* Autotuner for frob_inv_batched: for each kind and order class (<= 64, 128,
+ * 256, 512) times the persistent kernel on synthetic diagonally dominant
+ * batches with panel widths 8, 16 and 32 and keeps the fastest in the handle.
+ * table_out (may be NULL) receives [kind][class] as 8 ints.  Synchronous;
+ * allocates its own test matrices. */
+frob_status_t frob_batched_tune(frob_handle_t handle, int storage, int table_out[8]);
+
 /* Kernel timing with HIP events (for measurement).  When enabled, the library
  * records an event pair on the handle's stream around every launch of a
  * kernel class and accumulates, per class, the number of launches, their

@@ -19,6 +19,7 @@ from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_SHIFT_AUTO
                    frob_opts_t, frob_result_t)
 
 __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_cinv_lu", "frob_cinv_chol",
+           "frob_inv_adjoint", "frob_inv_batched", "frob_batched_tune", "BatchedPlan",
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
            "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16", "load_library"]
 
@@ -229,3 +230,73 @@ def frob_inv_adjoint(h: Handle, Xr, Xi, Gr, Gi, dMr=None, dMi=None):
     st = _lib.load().frob_inv_adjoint(h.ptr, b, n, storage, *ptrs)
     _lib.check(st, "frob_inv_adjoint")
     return dMr, dMi
+
+
+class BatchedPlan:
+    """Device-side description of a batch for frob_inv_batched: per-matrix
+    orders and kinds and the four pointer arrays, kept alive with the tensors
+    they point to (so that a call can be repeated, or captured in a graph)."""
+
+    def __init__(self, As, Bs, kinds, Xr=None, Xi=None):
+        import torch
+        if not (len(As) == len(Bs) == len(kinds)) or not As:
+            raise ValueError("As, Bs and kinds must be non-empty and of equal length")
+        dt = As[0].dtype
+        if dt not in (torch.float32, torch.float64):
+            raise TypeError("matrices must be float32 or float64")
+        dev = As[0].device
+        for t in list(As) + list(Bs):
+            if t.dtype != dt or t.device != dev or t.dim() != 2 or t.shape[0] != t.shape[1] or not t.is_contiguous():
+                raise ValueError("every matrix must be a contiguous square tensor of the batch's dtype and device")
+        ns = [int(a.shape[0]) for a in As]
+        if min(ns) < 1 or max(ns) > 512:
+            raise ValueError("batched orders must lie in [1, 512]")
+        if any(int(k) not in (0, 1) for k in kinds):
+            raise ValueError("kinds must be 0 (general) or 1 (Hermitian positive definite)")
+        for a, b in zip(As, Bs):
+            if b.shape != a.shape:
+                raise ValueError("A and B of a matrix must have the same order")
+        self.As, self.Bs = list(As), list(Bs)
+        self.Xr = [torch.empty_like(a) for a in As] if Xr is None else list(Xr)
+        self.Xi = [torch.empty_like(a) for a in As] if Xi is None else list(Xi)
+        self.count = len(As)
+        self.nmax = max(ns)
+        self.storage = FROB_PREC_F32 if dt == torch.float32 else FROB_PREC_F64
+
+        def ptrs(ts):
+            return torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+
+        self.n_dev = torch.tensor(ns, dtype=torch.int32, device=dev)
+        self.kind_dev = torch.tensor([int(k) for k in kinds], dtype=torch.int32, device=dev)
+        self.pA, self.pB, self.pXr, self.pXi = ptrs(self.As), ptrs(self.Bs), ptrs(self.Xr), ptrs(self.Xi)
+        self.info_dev = torch.zeros(self.count, dtype=torch.int32, device=dev)
+
+    def launch(self, h: "Handle"):
+        """Enqueue the batched inversion on the handle's stream (asynchronous)."""
+        h.bind_stream()
+        vp = ctypes.c_void_p
+        st = _lib.load().frob_inv_batched(h.ptr, self.count, self.nmax, vp(self.n_dev.data_ptr()),
+                                          vp(self.kind_dev.data_ptr()), vp(self.pA.data_ptr()),
+                                          vp(self.pB.data_ptr()), vp(self.pXr.data_ptr()),
+                                          vp(self.pXi.data_ptr()), vp(self.info_dev.data_ptr()), self.storage)
+        _lib.check(st, "frob_inv_batched")
+
+
+def frob_inv_batched(h: Handle, As, Bs, kinds):
+    """Invert a batch of uneven-order matrices in one persistent launch.
+
+    kinds[i] = 0 (general, Algorithm 5) or 1 (Hermitian positive definite,
+    Algorithm 7).  Returns (Xr list, Xi list, info numpy array)."""
+    import torch
+    plan = BatchedPlan(As, Bs, kinds)
+    plan.launch(h)
+    torch.cuda.current_stream().synchronize()
+    return plan.Xr, plan.Xi, plan.info_dev.cpu().numpy()
+
+
+def frob_batched_tune(h: Handle, storage=FROB_PREC_F64):
+    """Autotune the batched panel widths; returns the table {(kind, class): nb}."""
+    table = (ctypes.c_int * 8)()
+    h.bind_stream()
+    _lib.check(_lib.load().frob_batched_tune(h.ptr, int(storage), table), "frob_batched_tune")
+    return {(k, c): table[4 * k + c] for k in range(2) for c in range(4)}

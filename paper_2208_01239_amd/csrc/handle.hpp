@@ -28,6 +28,8 @@ struct frob_handle {
   int prof = 0;                  // profiling enabled
   std::vector<frob_prof_pending> pending;
   std::vector<hipEvent_t> pool;
+  int batch_nb[2][2][4] = {{{16, 16, 16, 16}, {16, 16, 16, 16}}, {{16, 16, 16, 16}, {16, 16, 16, 16}}};
+                                 // batched panel width [FP64/FP32][general/HPD][order class]
   double prof_ms[16] = {0};
   double prof_flops[16] = {0};
   long long prof_count[16] = {0};
