@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip HPD and baseline measurements")
     ap.add_argument("--cpu-n", type=int, default=1536)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -128,6 +130,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": nbytes, "copies": 3}), flush=True)
+        return
 
     import paper_2208_01239_amd as fi
     from paper_2208_01239_amd import inputs
@@ -246,6 +258,18 @@ def main():
                "sample": f"one n={m} general matrix of the same recipe (seed 0), Algorithm 5 in the FP64 oracle, "
                          f"{tc:.2f} s, scaled to n={n} by (n/{m})^3"}
 
+    # HBM traffic of the dominant kernel from the committed rocprofv3 counter
+    # summary, valid only while the kernel source is the one measured
+    traffic = None
+    tj = os.path.join(ROOT, "profiles", "gemm_f64_128x128_n4096_hbm_traffic.json")
+    if n == 4096 and os.path.exists(tj):
+        import hashlib
+        with open(tj) as f:
+            td = json.load(f)
+        with open(os.path.join(ROOT, "paper_2208_01239_amd", "csrc", "gemm_f64.hip"), "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()
+        if cur == td.get("gemm_f64_hip_sha256"):
+            traffic = td["traffic_bytes_per_launch"]
     gemm_avg_ms = gemm_ms / launches if launches else None
     achieved = (gemm_flops / launches) / (gemm_avg_ms * 1e-3) / 1e12 if launches else None
     line = {
@@ -270,7 +294,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_gemm_f64<128,128> (n x n x n products B*Y and -Y*C^-1)",
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
-                     "avg_launch_ms": gemm_avg_ms, "launches": launches, "traffic": None},
+                     "avg_launch_ms": gemm_avg_ms, "launches": launches, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"},
         "cpu_baseline": cpu,
     }
     line.update(extra)
