@@ -50,23 +50,7 @@ __device__ __forceinline__ double tri_mask(double v, int tri, int r, int c) {
   }
 }
 
-// two consecutive doubles p[0], p[1]; n_ok = how many of them are in range (0..2)
-__device__ __forceinline__ void load2(const double* p, int n_ok, bool vec, double& x, double& y) {
-  if (n_ok >= 2) {
-    if (vec) {
-      const double2 t = *reinterpret_cast<const double2*>(p);
-      x = t.x; y = t.y;
-    } else {
-      x = p[0]; y = p[1];
-    }
-  } else if (n_ok == 1) {
-    x = p[0]; y = 0.0;
-  } else {
-    x = 0.0; y = 0.0;
-  }
-}
-
-template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
@@ -102,7 +86,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   const int* __restrict__ rB = g.B.rows ? g.B.rows + z * g.rsB : nullptr;
   const int* __restrict__ rC = g.C.rows ? g.C.rows + z * g.rsC : nullptr;
   const int M = g.M, N = g.N;
-  const bool vecA = g.vecA != 0, vecB = g.vecB != 0;
 
   int kbeg = 0, kend = g.K;
   if (g.triA == TRI_UPPER || g.triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
@@ -144,91 +127,127 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
 
   double ra[A_P][2], rb[B_P][2];
 
+  // Raw tile loads: every address is clamped into the operand, so the loads
+  // are issued unconditionally and nothing consumes their registers until the
+  // tile is written to LDS (after the current tile's products).  Elements
+  // outside the operand (ragged edges, the k tail) and outside a triangle are
+  // zeroed at that point.  With VEC (16-byte aligned rows, even row extents)
+  // pairs are read with one 16-byte load and never straddle the extent.
+  auto ld_pair = [&](const double* row, int c, int lim, double& x, double& y) {
+    if (VEC) {
+      const double2 t2 = *reinterpret_cast<const double2*>(row + min(c, (lim - 1) & ~1));
+      x = t2.x;
+      y = t2.y;
+    } else {
+      x = row[min(c, lim - 1)];
+      y = row[min(c + 1, lim - 1)];
+    }
+  };
+  // k-band operands (TA for A, !TB for B) address their rows through a row
+  // index that changes with k: the indices of a tile are fetched one k-step
+  // before its data, unconditionally (from a readable stand-in when there is
+  // no index array; the value is then ignored), so no wait on them stalls
+  // the products in between.
+  constexpr int KA = TA ? A_P : 1, KB = TB ? 1 : B_P;
+  const int* rAs = rA ? rA : reinterpret_cast<const int*>(Ap);
+  const int* rBs = rB ? rB : reinterpret_cast<const int*>(Bp);
+  int ixa[KA], ixb[KB];
+  auto load_index = [&](int kt) {
+    if (TA) {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KA; ++p) ixa[p] = rAs[min(kt + tid / TPR + RPP * p, kend - 1)];
+    }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KB; ++p) ixb[p] = rBs[min(kt + tid / TPR + RPP * p, kend - 1)];
+    }
+  };
   auto load_tiles = [&](int kt) {
     if (!TA) {
-      const int kq = (tid & 7) * 2;
-      const int gk = kt + kq;
-      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+      const int gk = kt + (tid & 7) * 2;
 #pragma unroll
-      for (int p = 0; p < A_P; ++p) {
-        load2(aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ra[p][0], ra[p][1]);
-        if (g.triA) {
-          const int gi = bm0 + tid / 8 + 32 * p;
-          ra[p][0] = tri_mask(ra[p][0], g.triA, gi, gk);
-          ra[p][1] = tri_mask(ra[p][1], g.triA, gi, gk + 1);
-        }
-      }
+      for (int p = 0; p < A_P; ++p) ld_pair(aRow[p], gk, kend, ra[p][0], ra[p][1]);
     } else {
       constexpr int TPR = BM / 2, RPP = 256 / TPR;
-      const int col = (tid % TPR) * 2;
-      const int gi = bm0 + col;
-      const int ncol = gi + 1 < M ? 2 : (gi < M ? 1 : 0);
+      const int gi = bm0 + (tid % TPR) * 2;
 #pragma unroll
       for (int p = 0; p < A_P; ++p) {
-        const int gk = kt + tid / TPR + RPP * p;
-        const bool ok = gk < kend;
-        const int pr = ok ? (rA ? rA[gk] : gk) : 0;
-        load2(Ap + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ra[p][0], ra[p][1]);
-        if (g.triA) {
-          ra[p][0] = tri_mask(ra[p][0], g.triA, gi, gk);
-          ra[p][1] = tri_mask(ra[p][1], g.triA, gi + 1, gk);
-        }
+        const int gk = min(kt + tid / TPR + RPP * p, kend - 1);
+        ld_pair(Ap + (long long)(rA ? ixa[p] : gk) * g.A.ld, gi, M, ra[p][0], ra[p][1]);
       }
     }
     if (!TB) {
       constexpr int TPR = BN / 2, RPP = 256 / TPR;
-      const int col = (tid % TPR) * 2;
-      const int gj = bn0 + col;
-      const int ncol = gj + 1 < N ? 2 : (gj < N ? 1 : 0);
+      const int gj = bn0 + (tid % TPR) * 2;
 #pragma unroll
       for (int p = 0; p < B_P; ++p) {
-        const int gk = kt + tid / TPR + RPP * p;
-        const bool ok = gk < kend;
-        const int pr = ok ? (rB ? rB[gk] : gk) : 0;
-        load2(Bp + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, rb[p][0], rb[p][1]);
-        if (g.triB) {
-          rb[p][0] = tri_mask(rb[p][0], g.triB, gk, gj);
-          rb[p][1] = tri_mask(rb[p][1], g.triB, gk, gj + 1);
-        }
+        const int gk = min(kt + tid / TPR + RPP * p, kend - 1);
+        ld_pair(Bp + (long long)(rB ? ixb[p] : gk) * g.B.ld, gj, N, rb[p][0], rb[p][1]);
       }
     } else {
-      const int kq = (tid & 7) * 2;
-      const int gk = kt + kq;
-      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+      const int gk = kt + (tid & 7) * 2;
 #pragma unroll
-      for (int p = 0; p < B_P; ++p) {
-        load2(bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, rb[p][0], rb[p][1]);
-        if (g.triB) {
-          const int gj = bn0 + tid / 8 + 32 * p;
-          rb[p][0] = tri_mask(rb[p][0], g.triB, gk, gj);
-          rb[p][1] = tri_mask(rb[p][1], g.triB, gk + 1, gj);
-        }
-      }
+      for (int p = 0; p < B_P; ++p) ld_pair(bRow[p], gk, kend, rb[p][0], rb[p][1]);
     }
   };
 
-  auto store_tiles = [&](int stage) {
+  // mask and write the loaded tile of k-step kt into LDS stage `stage`
+  auto store_tiles = [&](int stage, int kt) {
     double* As = smem + stage * (A_SZ + B_SZ);
     double* Bs = As + A_SZ;
 #pragma unroll
     for (int p = 0; p < A_P; ++p) {
-      int off;
-      if (!TA) off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
-      else {
+      int off, gi, gk, di, dk;
+      bool ok;
+      if (!TA) {
+        gi = bm0 + tid / 8 + 32 * p;
+        gk = kt + (tid & 7) * 2;
+        di = 0; dk = 1;
+        ok = aRowOk[p];
+        off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
+      } else {
         constexpr int TPR = BM / 2, RPP = 256 / TPR;
+        gi = bm0 + (tid % TPR) * 2;
+        gk = kt + tid / TPR + RPP * p;
+        di = 1; dk = 0;
+        ok = true;
         off = (tid / TPR + RPP * p) * A_LD + (tid % TPR) * 2;
       }
-      *reinterpret_cast<double2*>(As + off) = double2{ra[p][0], ra[p][1]};
+      double x = (ok && gi < M && gk < kend) ? ra[p][0] : 0.0;
+      double y = (ok && gi + di < M && gk + dk < kend) ? ra[p][1] : 0.0;
+      if (g.triA) {
+        x = tri_mask(x, g.triA, gi, gk);
+        y = tri_mask(y, g.triA, gi + di, gk + dk);
+      }
+      *reinterpret_cast<double2*>(As + off) = double2{x, y};
     }
 #pragma unroll
     for (int p = 0; p < B_P; ++p) {
-      int off;
-      if (TB) off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
-      else {
+      int off, gj, gk, dj, dk;
+      bool ok;
+      if (TB) {
+        gj = bn0 + tid / 8 + 32 * p;
+        gk = kt + (tid & 7) * 2;
+        dj = 0; dk = 1;
+        ok = bRowOk[p];
+        off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
+      } else {
         constexpr int TPR = BN / 2, RPP = 256 / TPR;
+        gj = bn0 + (tid % TPR) * 2;
+        gk = kt + tid / TPR + RPP * p;
+        dj = 1; dk = 0;
+        ok = true;
         off = (tid / TPR + RPP * p) * B_LD + (tid % TPR) * 2;
       }
-      *reinterpret_cast<double2*>(Bs + off) = double2{rb[p][0], rb[p][1]};
+      double x = (ok && gj < N && gk < kend) ? rb[p][0] : 0.0;
+      double y = (ok && gj + dj < N && gk + dk < kend) ? rb[p][1] : 0.0;
+      if (g.triB) {
+        x = tri_mask(x, g.triB, gk, gj);
+        y = tri_mask(y, g.triB, gk + dk, gj + dj);
+      }
+      *reinterpret_cast<double2*>(Bs + off) = double2{x, y};
     }
   };
 
@@ -239,13 +258,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
   if (nk > 0) {
+    load_index(kbeg);
     load_tiles(kbeg);
-    store_tiles(0);
+    if (nk > 1) load_index(kbeg + BK);
+    store_tiles(0, kbeg);
     __syncthreads();
   }
   for (int it = 0; it < nk; ++it) {
     const int stage = it & 1;
-    if (it + 1 < nk) load_tiles(kbeg + (it + 1) * BK);
+    if (it + 1 < nk) {
+      load_tiles(kbeg + (it + 1) * BK);
+      if (it + 2 < nk) load_index(kbeg + (it + 2) * BK);
+    }
     const double* As = smem + stage * (A_SZ + B_SZ);
     const double* Bs = As + A_SZ;
 #pragma unroll
@@ -268,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
         for (int b = 0; b < FN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
-    if (it + 1 < nk) store_tiles(stage ^ 1);
+    if (it + 1 < nk) store_tiles(stage ^ 1, kbeg + (it + 1) * BK);
     __syncthreads();
   }
 
@@ -320,7 +344,10 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
   p.tilesN = ceil_div(p.N, BN);
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
-  hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  if (p.vecA && p.vecB)
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -377,9 +404,10 @@ void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, doub
   p.A = A; p.B = B; p.C = C;
   p.triA = triA; p.triB = triB;
   p.lowerOnly = lowerOnly ? 1 : 0;
-  // 16-byte loads need 16-byte aligned rows in every batch entry
-  p.vecA = aligned16(A.p) && (A.ld % 2 == 0) && (sA % 2 == 0);
-  p.vecB = aligned16(B.p) && (B.ld % 2 == 0) && (sB % 2 == 0);
+  // 16-byte loads need 16-byte aligned rows in every batch entry and an even
+  // extent along the rows (the pairs then never cross it)
+  p.vecA = aligned16(A.p) && (A.ld % 2 == 0) && (sA % 2 == 0) && ((ta ? M : K) % 2 == 0);
+  p.vecB = aligned16(B.p) && (B.ld % 2 == 0) && (sB % 2 == 0) && ((tb ? K : N) % 2 == 0);
   p.sA = sA; p.sB = sB; p.sC = sC;
   p.rsA = rsA; p.rsB = rsB; p.rsC = rsC;
   const int cfg = gemm_pick_cfg(M, N, need);

@@ -24,7 +24,6 @@ namespace {
 
 constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 constexpr int LEAF_STAGE = 8192;    // doubles in the LDS stage (64 KiB): one I/O round
-constexpr int LEAF_WMAX = 32;
 
 // One workgroup factors an mm x nc panel (nc <= W) held in registers.  Thread
 // t owns panel rows q = t + s * LEAF_NT (s < R).  Rows never move: each row
