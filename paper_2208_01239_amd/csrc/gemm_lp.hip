@@ -12,7 +12,8 @@
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, block tile BM x BN, k-step
 // 32.  A tile is read from HBM with one batch of unconditional loads at
 // clamped addresses (the next k-step's batch is in flight while the current
-// one is multiplied), rounded, and written to LDS k-major, which is the
+// one is multiplied; row indices are fetched a k-step earlier still),
+// rounded, and written to LDS k-major, which is the
 // order the MFMA fragments read (16 consecutive lanes, 16 consecutive
 // floats).  Fragment layouts (lane l): A[l % 16][k] / B[k][l % 16] with
 // k = l / 16 (FP32, one value) or k = 8 (l / 16) + 0..7 (BF16, eight values);
@@ -61,29 +62,62 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   TS* Cp = g.C + z * g.sC;
   const int M = g.M, N = g.N, K = g.K;
 
-  // element u of this thread's share of a tile: logical (row, k) pairs
+  // Element u of this thread's share of a tile is the logical (row, k) pair
+  // below.  The physical rows of the row-band operands (A for N, B for T) do
+  // not change with k and are looked up once; the k-band operands' row
+  // indices are fetched one k-step ahead of their data, unconditionally (from
+  // a readable stand-in when there is no index array; the value is then
+  // ignored), so no wait on an index stalls the products.
+  constexpr int RA = TA ? 1 : EA, RB = TB ? EB : 1;
+  constexpr int XA = TA ? EA : 1, XB = TB ? 1 : EB;
+  int rowA[RA], rowB[RB], ixa[XA], ixb[XB];
+  if (!TA) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int gi = min(bm0 + (tid + 256 * u) / LBK, M - 1);
+      rowA[u] = g.rA ? g.rA[gi] : gi;
+    }
+  }
+  if (TB) {
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int gj = min(bn0 + (tid + 256 * u) / LBK, N - 1);
+      rowB[u] = g.rB ? g.rB[gj] : gj;
+    }
+  }
+  const int* rAs = g.rA ? g.rA : reinterpret_cast<const int*>(Ap);
+  const int* rBs = g.rB ? g.rB : reinterpret_cast<const int*>(Bp);
+  auto load_index = [&](int k0) {
+    if (TA) {
+#pragma unroll
+      for (int u = 0; u < EA; ++u) ixa[u] = rAs[min(k0 + (tid + 256 * u) / BM, K - 1)];
+    }
+    if (!TB) {
+#pragma unroll
+      for (int u = 0; u < EB; ++u) ixb[u] = rBs[min(k0 + (tid + 256 * u) / BN, K - 1)];
+    }
+  };
   TS ra[EA], rb[EB];
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       const int e = tid + 256 * u;
-      int i, k;
-      if (!TA) { i = e / LBK; k = e % LBK; } else { k = e / BM; i = e % BM; }
-      const int gi = min(bm0 + i, M - 1), gk = min(k0 + k, K - 1);
-      // stored element: A[gi][gk] (N) or A[gk][gi] (T)
-      const int sr = TA ? gk : gi, sc = TA ? gi : gk;
-      const int pr = g.rA ? g.rA[sr] : sr;
-      ra[u] = Ap[(long long)pr * g.lda + sc];
+      if (!TA) {
+        ra[u] = Ap[(long long)rowA[u] * g.lda + min(k0 + e % LBK, K - 1)];
+      } else {
+        const int gk = min(k0 + e / BM, K - 1), gi = min(bm0 + e % BM, M - 1);
+        ra[u] = Ap[(long long)(g.rA ? ixa[u] : gk) * g.lda + gi];
+      }
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = tid + 256 * u;
-      int k, j;
-      if (!TB) { k = e / BN; j = e % BN; } else { j = e / LBK; k = e % LBK; }
-      const int gk = min(k0 + k, K - 1), gj = min(bn0 + j, N - 1);
-      const int sr = TB ? gj : gk, sc = TB ? gk : gj;
-      const int pr = g.rB ? g.rB[sr] : sr;
-      rb[u] = Bp[(long long)pr * g.ldb + sc];
+      if (!TB) {
+        const int gk = min(k0 + e / BN, K - 1), gj = min(bn0 + e % BN, N - 1);
+        rb[u] = Bp[(long long)(g.rB ? ixb[u] : gk) * g.ldb + gj];
+      } else {
+        rb[u] = Bp[(long long)rowB[u] * g.ldb + min(k0 + e % LBK, K - 1)];
+      }
     }
   };
   auto store_tiles = [&](int k0) {
@@ -113,11 +147,18 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
     for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
   const int nk = (K + LBK - 1) / LBK;
-  if (nk > 0) load_tiles(0);
+  if (nk > 0) {
+    load_index(0);
+    load_tiles(0);
+    if (nk > 1) load_index(LBK);
+  }
   for (int it = 0; it < nk; ++it) {
     store_tiles(it * LBK);
     __syncthreads();
-    if (it + 1 < nk) load_tiles((it + 1) * LBK);
+    if (it + 1 < nk) {
+      load_tiles((it + 1) * LBK);
+      if (it + 2 < nk) load_index((it + 2) * LBK);
+    }
     if (MODE == LP_F32) {
 #pragma unroll
       for (int kk = 0; kk < LBK; kk += 4) {

@@ -39,22 +39,7 @@ __device__ __forceinline__ void ztri_mask(double& re, double& im, int tri, int r
   }
 }
 
-__device__ __forceinline__ void zload2(const double* p, int n_ok, bool vec, double& x, double& y) {
-  if (n_ok >= 2) {
-    if (vec) {
-      const double2 t = *reinterpret_cast<const double2*>(p);
-      x = t.x; y = t.y;
-    } else {
-      x = p[0]; y = p[1];
-    }
-  } else if (n_ok == 1) {
-    x = p[0]; y = 0.0;
-  } else {
-    x = 0.0; y = 0.0;
-  }
-}
-
-template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
@@ -93,7 +78,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   const int* __restrict__ rB = g.B.rows ? g.B.rows + z * g.rsB : nullptr;
   const int* __restrict__ rC = g.C.rows ? g.C.rows + z * g.rsC : nullptr;
   const int M = g.M, N = g.N;
-  const bool vecA = g.vecA != 0, vecB = g.vecB != 0;
 
   int kbeg = 0, kend = g.K;
   if (g.triA == TRI_UPPER || g.triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
@@ -135,99 +119,136 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
 
   double ra[A_P][2], rb[B_P][2], ia[A_P][2], ib[B_P][2];
 
+  // Raw tile loads at clamped in-range addresses, issued unconditionally;
+  // nothing reads their registers until the tile is written to LDS after the
+  // current tile's products, where values outside the operand or its
+  // triangle are zeroed.  Row indices of k-band operands are fetched one
+  // k-step ahead (from a readable stand-in when there is no index array).
+  auto ld_pair = [&](const double* row, int c, int lim, double& x, double& y) {
+    if (VEC) {
+      const double2 t2 = *reinterpret_cast<const double2*>(row + min(c, (lim - 1) & ~1));
+      x = t2.x;
+      y = t2.y;
+    } else {
+      x = row[min(c, lim - 1)];
+      y = row[min(c + 1, lim - 1)];
+    }
+  };
+  constexpr int KA = TA ? A_P : 1, KB = TB ? 1 : B_P;
+  const int* rAs = rA ? rA : reinterpret_cast<const int*>(Ar);
+  const int* rBs = rB ? rB : reinterpret_cast<const int*>(Br);
+  int ixa[KA], ixb[KB];
+  auto load_index = [&](int kt) {
+    if (TA) {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KA; ++p) ixa[p] = rAs[min(kt + tid / TPR + RPP * p, kend - 1)];
+    }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KB; ++p) ixb[p] = rBs[min(kt + tid / TPR + RPP * p, kend - 1)];
+    }
+  };
   auto load_tiles = [&](int kt) {
     if (!TA) {
-      const int kq = (tid & 7) * 2;
-      const int gk = kt + kq;
-      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+      const int gk = kt + (tid & 7) * 2;
 #pragma unroll
       for (int p = 0; p < A_P; ++p) {
-        zload2(Ar + aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ra[p][0], ra[p][1]);
-        zload2(Ai + aRow[p] + gk, aRowOk[p] ? nok : 0, vecA, ia[p][0], ia[p][1]);
-        if (g.triA) {
-          const int gi = bm0 + tid / 8 + 32 * p;
-          ztri_mask(ra[p][0], ia[p][0], g.triA, gi, gk);
-          ztri_mask(ra[p][1], ia[p][1], g.triA, gi, gk + 1);
-        }
+        ld_pair(Ar + aRow[p], gk, kend, ra[p][0], ra[p][1]);
+        ld_pair(Ai + aRow[p], gk, kend, ia[p][0], ia[p][1]);
       }
     } else {
       constexpr int TPR = BM / 2, RPP = 256 / TPR;
-      const int col = (tid % TPR) * 2;
-      const int gi = bm0 + col;
-      const int ncol = gi + 1 < M ? 2 : (gi < M ? 1 : 0);
+      const int gi = bm0 + (tid % TPR) * 2;
 #pragma unroll
       for (int p = 0; p < A_P; ++p) {
-        const int gk = kt + tid / TPR + RPP * p;
-        const bool ok = gk < kend;
-        const int pr = ok ? (rA ? rA[gk] : gk) : 0;
-        zload2(Ar + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ra[p][0], ra[p][1]);
-        zload2(Ai + (long long)pr * g.A.ld + gi, ok ? ncol : 0, vecA, ia[p][0], ia[p][1]);
-        if (g.triA) {
-          ztri_mask(ra[p][0], ia[p][0], g.triA, gi, gk);
-          ztri_mask(ra[p][1], ia[p][1], g.triA, gi + 1, gk);
-        }
+        const int gk = min(kt + tid / TPR + RPP * p, kend - 1);
+        const long long ro = (long long)(rA ? ixa[p] : gk) * g.A.ld;
+        ld_pair(Ar + ro, gi, M, ra[p][0], ra[p][1]);
+        ld_pair(Ai + ro, gi, M, ia[p][0], ia[p][1]);
       }
     }
     if (!TB) {
       constexpr int TPR = BN / 2, RPP = 256 / TPR;
-      const int col = (tid % TPR) * 2;
-      const int gj = bn0 + col;
-      const int ncol = gj + 1 < N ? 2 : (gj < N ? 1 : 0);
+      const int gj = bn0 + (tid % TPR) * 2;
 #pragma unroll
       for (int p = 0; p < B_P; ++p) {
-        const int gk = kt + tid / TPR + RPP * p;
-        const bool ok = gk < kend;
-        const int pr = ok ? (rB ? rB[gk] : gk) : 0;
-        zload2(Br + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, rb[p][0], rb[p][1]);
-        zload2(Bi + (long long)pr * g.B.ld + gj, ok ? ncol : 0, vecB, ib[p][0], ib[p][1]);
-        if (g.triB) {
-          ztri_mask(rb[p][0], ib[p][0], g.triB, gk, gj);
-          ztri_mask(rb[p][1], ib[p][1], g.triB, gk, gj + 1);
-        }
+        const int gk = min(kt + tid / TPR + RPP * p, kend - 1);
+        const long long ro = (long long)(rB ? ixb[p] : gk) * g.B.ld;
+        ld_pair(Br + ro, gj, N, rb[p][0], rb[p][1]);
+        ld_pair(Bi + ro, gj, N, ib[p][0], ib[p][1]);
       }
     } else {
-      const int kq = (tid & 7) * 2;
-      const int gk = kt + kq;
-      const int nok = gk + 1 < kend ? 2 : (gk < kend ? 1 : 0);
+      const int gk = kt + (tid & 7) * 2;
 #pragma unroll
       for (int p = 0; p < B_P; ++p) {
-        zload2(Br + bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, rb[p][0], rb[p][1]);
-        zload2(Bi + bRow[p] + gk, bRowOk[p] ? nok : 0, vecB, ib[p][0], ib[p][1]);
-        if (g.triB) {
-          const int gj = bn0 + tid / 8 + 32 * p;
-          ztri_mask(rb[p][0], ib[p][0], g.triB, gk, gj);
-          ztri_mask(rb[p][1], ib[p][1], g.triB, gk + 1, gj);
-        }
+        ld_pair(Br + bRow[p], gk, kend, rb[p][0], rb[p][1]);
+        ld_pair(Bi + bRow[p], gk, kend, ib[p][0], ib[p][1]);
       }
     }
   };
 
-  auto store_tiles = [&](int stage) {
+  auto store_tiles = [&](int stage, int kt) {
     double* As = smem + stage * 2 * (A_SZ + B_SZ);
     double* AsI = As + A_SZ;
     double* Bs = AsI + A_SZ;
     double* BsI = Bs + B_SZ;
 #pragma unroll
     for (int p = 0; p < A_P; ++p) {
-      int off;
-      if (!TA) off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
-      else {
+      int off, gi, gk, di, dk;
+      bool ok;
+      if (!TA) {
+        gi = bm0 + tid / 8 + 32 * p;
+        gk = kt + (tid & 7) * 2;
+        di = 0; dk = 1;
+        ok = aRowOk[p];
+        off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
+      } else {
         constexpr int TPR = BM / 2, RPP = 256 / TPR;
+        gi = bm0 + (tid % TPR) * 2;
+        gk = kt + tid / TPR + RPP * p;
+        di = 1; dk = 0;
+        ok = true;
         off = (tid / TPR + RPP * p) * A_LD + (tid % TPR) * 2;
       }
-      *reinterpret_cast<double2*>(As + off) = double2{ra[p][0], ra[p][1]};
-      *reinterpret_cast<double2*>(AsI + off) = double2{ia[p][0], ia[p][1]};
+      const bool ok0 = ok && gi < M && gk < kend, ok1 = ok && gi + di < M && gk + dk < kend;
+      double xr = ok0 ? ra[p][0] : 0.0, xi = ok0 ? ia[p][0] : 0.0;
+      double yr = ok1 ? ra[p][1] : 0.0, yi = ok1 ? ia[p][1] : 0.0;
+      if (g.triA) {
+        ztri_mask(xr, xi, g.triA, gi, gk);
+        ztri_mask(yr, yi, g.triA, gi + di, gk + dk);
+      }
+      *reinterpret_cast<double2*>(As + off) = double2{xr, yr};
+      *reinterpret_cast<double2*>(AsI + off) = double2{xi, yi};
     }
 #pragma unroll
     for (int p = 0; p < B_P; ++p) {
-      int off;
-      if (TB) off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
-      else {
+      int off, gj, gk, dj, dk;
+      bool ok;
+      if (TB) {
+        gj = bn0 + tid / 8 + 32 * p;
+        gk = kt + (tid & 7) * 2;
+        dj = 0; dk = 1;
+        ok = bRowOk[p];
+        off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
+      } else {
         constexpr int TPR = BN / 2, RPP = 256 / TPR;
+        gj = bn0 + (tid % TPR) * 2;
+        gk = kt + tid / TPR + RPP * p;
+        dj = 1; dk = 0;
+        ok = true;
         off = (tid / TPR + RPP * p) * B_LD + (tid % TPR) * 2;
       }
-      *reinterpret_cast<double2*>(Bs + off) = double2{rb[p][0], rb[p][1]};
-      *reinterpret_cast<double2*>(BsI + off) = double2{ib[p][0], ib[p][1]};
+      const bool ok0 = ok && gj < N && gk < kend, ok1 = ok && gj + dj < N && gk + dk < kend;
+      double xr = ok0 ? rb[p][0] : 0.0, xi = ok0 ? ib[p][0] : 0.0;
+      double yr = ok1 ? rb[p][1] : 0.0, yi = ok1 ? ib[p][1] : 0.0;
+      if (g.triB) {
+        ztri_mask(xr, xi, g.triB, gk, gj);
+        ztri_mask(yr, yi, g.triB, gk + dk, gj + dj);
+      }
+      *reinterpret_cast<double2*>(Bs + off) = double2{xr, yr};
+      *reinterpret_cast<double2*>(BsI + off) = double2{xi, yi};
     }
   };
 
@@ -239,13 +260,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   const double sA = g.conjA ? -1.0 : 1.0, sB = g.conjB ? -1.0 : 1.0;
 
   if (nk > 0) {
+    load_index(kbeg);
     load_tiles(kbeg);
-    store_tiles(0);
+    if (nk > 1) load_index(kbeg + BK);
+    store_tiles(0, kbeg);
     __syncthreads();
   }
   for (int it = 0; it < nk; ++it) {
     const int stage = it & 1;
-    if (it + 1 < nk) load_tiles(kbeg + (it + 1) * BK);
+    if (it + 1 < nk) {
+      load_tiles(kbeg + (it + 1) * BK);
+      if (it + 2 < nk) load_index(kbeg + (it + 2) * BK);
+    }
     const double* As = smem + stage * 2 * (A_SZ + B_SZ);
     const double* AsI = As + A_SZ;
     const double* Bs = AsI + A_SZ;
@@ -277,7 +303,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
           acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(afi[a], bf[b], acci[a][b], 0, 0, 0);
         }
     }
-    if (it + 1 < nk) store_tiles(stage ^ 1);
+    if (it + 1 < nk) store_tiles(stage ^ 1, kbeg + (it + 1) * BK);
     __syncthreads();
   }
 
@@ -332,7 +358,10 @@ static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
   p.tilesN = ceil_div(p.N, BN);
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
-  hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  if (p.vecA && p.vecB)
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -376,11 +405,12 @@ void gemm_z64_batched(hipStream_t s, int opA, int opB, int M, int N, int K, doub
   p.conjA = opA == OP_C; p.conjB = opB == OP_C;
   p.triA = triA; p.triB = triB;
   p.lowerOnly = lowerOnly ? 1 : 0;
-  p.vecA = zaligned16(A.re) && zaligned16(A.im) && (A.ld % 2 == 0) && (sA % 2 == 0);
-  p.vecB = zaligned16(B.re) && zaligned16(B.im) && (B.ld % 2 == 0) && (sB % 2 == 0);
+  const bool ta = opA != OP_N, tb = opB != OP_N;
+  // 16-byte loads: aligned rows and an even extent along the rows
+  p.vecA = zaligned16(A.re) && zaligned16(A.im) && (A.ld % 2 == 0) && (sA % 2 == 0) && ((ta ? M : K) % 2 == 0);
+  p.vecB = zaligned16(B.re) && zaligned16(B.im) && (B.ld % 2 == 0) && (sB % 2 == 0) && ((tb ? K : N) % 2 == 0);
   p.sA = sA; p.sB = sB; p.sC = sC;
   p.rsA = rsA; p.rsB = rsB; p.rsC = rsC;
-  const bool ta = opA != OP_N, tb = opB != OP_N;
   const int cfg = zpick(M, N, need);
   if (!ta && !tb) launch_pick_z<false, false>(p, batch, cfg, s);
   else if (!ta && tb) launch_pick_z<false, true>(p, batch, cfg, s);
