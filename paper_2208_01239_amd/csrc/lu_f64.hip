@@ -23,7 +23,6 @@ namespace frob {
 namespace {
 
 constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
-constexpr int LEAF_STAGE = 8192;    // doubles in the LDS stage (64 KiB): one I/O round
 
 // One workgroup factors an mm x nc panel (nc <= W) held in registers.  Thread
 // t owns panel rows q = t + s * LEAF_NT (s < R).  Rows never move: each row
@@ -31,27 +30,27 @@ constexpr int LEAF_STAGE = 8192;    // doubles in the LDS stage (64 KiB): one I/
 // these integers only), so a pivot step exchanges no data between threads.
 // Per column j:
 //   - every lane takes its best candidate (largest |a_qj| among rows with
-//     pos >= j, lowest pos on ties);
-//   - the wave maximum is found on an FP32 image of |a_qj| (rounding is
-//     monotone, so the exact maximum is among the lanes that attain the FP32
-//     maximum) with single-instruction DPP steps; a ballot then settles the
-//     winner exactly in FP64 (one lane in the usual case, an exact FP64
-//     comparison among the tied lanes otherwise);
+//     pos >= j, lowest pos on ties) by an integer maximum over FP32 images of
+//     |a_qj| (rounding is monotone, so the exact maximum is among the rows
+//     that attain the largest image; exact FP64 comparison only when several
+//     rows of one lane attain it);
+//   - the wave maximum of the images is found with single-instruction DPP
+//     steps; a ballot then settles the winner exactly in FP64 (one lane in the
+//     usual case, an exact FP64 comparison among the tied lanes otherwise);
 //   - the wave's winner writes (|value|, pos, row) to a parity-double-
 //     buffered LDS slot; one barrier; every wave reduces the eight slots the
 //     same way and reads the pivot row from the winning slot;
 //   - positions are exchanged and every row below is scaled and updated
 //     (branch-free: rows above are updated with a zero multiplier).
-// The physical row of every panel row is staged in LDS once, so the panel
-// moves between HBM and the registers through the LDS stage with no dependent
-// index loads: rounds of 64 KiB, read and written by the whole workgroup with
-// 16-byte accesses (rows are contiguous), each round's loads issued before the
-// previous round is taken out of the stage.
+// Each thread reads and writes its own rows straight from and to HBM (rows
+// are scattered through perm, so a row's W contiguous doubles are its own
+// memory transactions either way): one batch of unconditional loads at
+// clamped addresses, one memory latency per panel.
 //
-// With n2 > 0 the kernel also applies its factorization to the n2 <= W
-// columns to the right of the panel (the sibling of a bottom recursion node):
-// U12 = L11^{-1} A12 by substitution in wave 0, A22 -= L21 U12 with L21 still
-// in registers.
+// With n2 > 0 the kernel factors a whole bottom recursion node: after its nc
+// columns it loads the n2 <= W columns to the right, applies the
+// factorization to them (U12 = L11^{-1} A12 by substitution, A22 -= L21 U12
+// with L21 still in registers) and factors them as panel columns nc .. nc+n2.
 // Keys are the bit patterns of FP32 values: for the values used here (>= 0,
 // or negative for "no candidate") signed-integer order agrees with numeric
 // order wherever it matters (any value >= 0 beats any negative one), and an
@@ -92,15 +91,15 @@ __device__ __forceinline__ int exact_argmax(unsigned long long cand, double val,
   return wl;
 }
 
+// the fused sibling update needs a second R x W block of registers; the
+// tallest leaves (more than 16 rows per thread) leave it to a node kernel
+constexpr bool LEAF_SIBLING(int R) { return R <= 16; }
+
 template <int R, int W>
 __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
                                                          int k0, int mm, int nc, int n2, int* info) {
-  constexpr int NT = LEAF_NT, NW = NT / 64, HW = W / 2;
-  constexpr int SR = LEAF_STAGE / W;                 // rows per I/O round
-  constexpr int PER = LEAF_STAGE / 2 / NT;           // 16-byte pieces per thread per round
-  static_assert(W % 2 == 0 && LEAF_STAGE % (2 * NT) == 0 && NW <= 16, "leaf shape");
-  __shared__ __align__(16) double stage[LEAF_STAGE];
-  __shared__ int s_ph[R * NT];                       // physical row of panel row q
+  constexpr int NT = LEAF_NT, NW = NT / 64;
+  static_assert(W % 2 == 0 && NW <= 16, "leaf shape");
   __shared__ double s_cv[2][NW];
   __shared__ int s_ck[2][NW];
   __shared__ __align__(16) double s_crow[2][NW][W];
@@ -110,105 +109,108 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const bool vbase = ((lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(a) & 15) == 0);
-  double v[R][W];
-  int pos[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int q = t + s * NT;
-    pos[s] = q < mm ? q : -1;      // padding rows: never candidates, never updated
-    if (q < mm) s_ph[q] = perm[k0 + q];
-#pragma unroll
-    for (int c = 0; c < W; ++c) v[s][c] = 0.0;
-  }
-  __syncthreads();
 
-  // ---- cooperative panel I/O: piece e = t + u NT of a round is
-  //      (stage row e / HW, columns 2 (e % HW) + {0, 1}) ----
-  const int nrounds = (mm + SR - 1) / SR;
-  auto load_round = [&](int r0, int col0, int ncol, double2* x) {
-    const bool vec = vbase && (col0 & 1) == 0;
+  // ---- this thread's rows q = t + s NT: physical row ph, logical position pos
+  //      (padding rows q >= mm: pos -1, never candidates, never stored) ----
+  int ph[R], pos[R];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = t + u * NT, i = e / HW, c = 2 * (e % HW);
-      double2 val = make_double2(0.0, 0.0);
-      if (r0 + i < mm && c < ncol) {
-        const double* src = a + (long long)s_ph[r0 + i] * lda + col0 + c;
-        if (vec && c + 1 < ncol) val = *reinterpret_cast<const double2*>(src);
-        else {
-          val.x = src[0];
-          if (c + 1 < ncol) val.y = src[1];
-        }
-      }
-      x[u] = val;
-    }
-  };
-  auto put_round = [&](const double2* x) {
+  for (int s = 0; s < R; ++s) ph[s] = perm[k0 + min(t + s * NT, mm - 1)];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) reinterpret_cast<double2*>(stage)[t + u * NT] = x[u];
-  };
-  auto store_round = [&](int r0, int col0, int ncol) {
-    const bool vec = vbase && (col0 & 1) == 0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = t + u * NT, i = e / HW, c = 2 * (e % HW);
-      if (r0 + i < mm && c < ncol) {
-        double* dst = a + (long long)s_ph[r0 + i] * lda + col0 + c;
-        const double2 val = reinterpret_cast<const double2*>(stage)[e];
-        if (vec && c + 1 < ncol) *reinterpret_cast<double2*>(dst) = val;
-        else {
-          dst[0] = val.x;
-          if (c + 1 < ncol) dst[1] = val.y;
-        }
-      }
-    }
-  };
+  for (int s = 0; s < R; ++s) pos[s] = t + s * NT < mm ? t + s * NT : -1;
 
-  // ---- load the panel ----
-  {
-    double2 x[PER];
-    load_round(0, k0, nc, x);
-    for (int r = 0; r < nrounds; ++r) {
-      const int r0 = r * SR;
-      put_round(x);
-      __syncthreads();
-      if (r + 1 < nrounds) load_round(r0 + SR, k0, nc, x);
+  // Columns col0 .. col0 + ncol - 1 of this thread's rows, straight from HBM:
+  // one batch of unconditional loads at clamped addresses (16-byte pairs
+  // when rows are 16-byte aligned and the extent is even), columns beyond
+  // ncol zeroed afterwards.
+  auto load_rows = [&](double (&x)[R][W], int col0, int ncol) {
+    if (vbase && ((col0 | ncol) & 1) == 0) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        const int q = t + s * NT;
-        if (q >= r0 && q < r0 + SR && q < mm) {
+        const double* row = a + (long long)ph[s] * lda + col0;
 #pragma unroll
-          for (int c = 0; c < W; c += 2) {
-            const double2 y = reinterpret_cast<const double2*>(stage)[((q - r0) * W + c) / 2];
-            v[s][c] = y.x;
-            v[s][c + 1] = y.y;
-          }
+        for (int c = 0; c < W; c += 2) {
+          const double2 y = *reinterpret_cast<const double2*>(row + min(c, ncol - 2));
+          x[s][c] = y.x;
+          x[s][c + 1] = y.y;
         }
       }
-      __syncthreads();
+    } else {
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const double* row = a + (long long)ph[s] * lda + col0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) x[s][c] = row[min(c, ncol - 1)];
+      }
     }
-  }
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int c = 0; c < W; ++c) x[s][c] = c < ncol ? x[s][c] : 0.0;
+  };
+  auto store_rows = [&](const double (&x)[R][W], int col0, int ncol) {
+    const bool vec = vbase && ((col0 | ncol) & 1) == 0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      if (pos[s] < 0) continue;
+      double* row = a + (long long)ph[s] * lda + col0;
+      if (vec) {
+#pragma unroll
+        for (int c = 0; c < W; c += 2)
+          if (c < ncol) *reinterpret_cast<double2*>(row + c) = make_double2(x[s][c], x[s][c + 1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < ncol) row[c] = x[s][c];
+      }
+    }
+  };
+
+  double v[R][W];
+  load_rows(v, k0, nc);
 
   // ---- factor ----
   int first_zero = 0;
-  // one column step per compile-time j (keeps every register index static)
-  auto column = [&](auto jc) {
-    constexpr int j = decltype(jc)::value;
-    if (j >= nc) return;  // uniform
-    constexpr int par = j & 1;
+  // One column step: register column jj (compile time, so every register
+  // index is static) of block x, panel column jp = off + jj.
+  auto column = [&](double (&x)[R][W], auto jc, int off, int ncols) __attribute__((always_inline)) {
+    constexpr int jj = decltype(jc)::value;
+    if (jj >= ncols) return;  // uniform
+    const int jp = off + jj;
+    constexpr int par = jj & 1;
+    // FP32 image of |a_qj| as an integer key (-1: not a candidate; NaN never
+    // is); the conversion is monotone, so the exact maximum is among the rows
+    // that attain the largest key
+    auto key = [&](int s) {
+      const double xv = fabs(x[s][jj]);
+      return (pos[s] >= jp && xv == xv) ? __float_as_int((float)xv) : -1;
+    };
+    int kmax = key(0);
+#pragma unroll
+    for (int s = 1; s < R; ++s) kmax = max(kmax, key(s));
     double best = -1.0;
-    int bq = INT_MAX;
+    int bq = INT_MAX, nt = 0;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const double xv = fabs(v[s][j]);
-      const bool ok = pos[s] >= j && (xv > best || (xv == best && pos[s] < bq));
-      best = ok ? xv : best;
-      bq = ok ? pos[s] : bq;
+      const bool m = kmax >= 0 && key(s) == kmax;
+      best = m ? fabs(x[s][jj]) : best;
+      bq = m ? pos[s] : bq;
+      nt += m ? 1 : 0;
     }
-    // (NaN entries are never candidates; a lane without one holds -1)
-    const int bf = __float_as_int((float)best);
-    const int wmf = wave_max_key(bf);
+    if (R > 1 && __ballot(nt > 1)) {
+      // several rows of a lane share the largest key: exact comparison
+      best = -1.0;
+      bq = INT_MAX;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const double xv = fabs(x[s][jj]);
+        const bool ok = kmax >= 0 && key(s) == kmax && (xv > best || (xv == best && pos[s] < bq));
+        best = ok ? xv : best;
+        bq = ok ? pos[s] : bq;
+      }
+    }
+    const int wmf = wave_max_key(kmax);
     if (wmf >= 0) {
-      const unsigned long long tied = __ballot(bf == wmf);
+      const unsigned long long tied = __ballot(kmax == wmf);
       const int wl = (__popcll(tied) == 1) ? __ffsll((long long)tied) - 1 : exact_argmax(tied, best, bq);
       if (lane == wl) {
 #pragma unroll
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
           if (pos[s] == bq) {
 #pragma unroll
             for (int c = 0; c < W; c += 2)
-              *reinterpret_cast<double2*>(&s_crow[par][wv][c]) = make_double2(v[s][c], v[s][c + 1]);
+              *reinterpret_cast<double2*>(&s_crow[par][wv][c]) = make_double2(x[s][c], x[s][c + 1]);
           }
         s_cv[par][wv] = best;
         s_ck[par][wv] = bq;
@@ -238,37 +240,37 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
       p = __builtin_amdgcn_readlane(sk, gw);
       prow = s_crow[par][gw];
     } else {
-      // every candidate is NaN: keep row j in place (uniform slow path)
-      p = j;
+      // every candidate is NaN: keep row jp in place (uniform slow path)
+      p = jp;
 #pragma unroll
       for (int s = 0; s < R; ++s)
-        if (pos[s] == j) {
+        if (pos[s] == jp) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) s_crow[par][0][c] = v[s][c];
+          for (int c = 0; c < W; ++c) s_crow[par][0][c] = x[s][c];
         }
       __syncthreads();
       prow = s_crow[par][0];
     }
-    // row interchange j <-> p on the positions only
+    // row interchange jp <-> p on the positions only
 #pragma unroll
-    for (int s = 0; s < R; ++s) pos[s] = pos[s] == p ? j : (pos[s] == j ? p : pos[s]);
-    const double piv = prow[j];
-    if (piv == 0.0 && !first_zero) first_zero = k0 + j + 1;
+    for (int s = 0; s < R; ++s) pos[s] = pos[s] == p ? jp : (pos[s] == jp ? p : pos[s]);
+    const double piv = prow[jj];
+    if (piv == 0.0 && !first_zero) first_zero = k0 + jp + 1;
     // scale by the reciprocal unless it would overflow (as LAPACK's getf2
     // does); a zero pivot leaves the (all-zero) column and the rows as they are
     const bool nz = piv != 0.0;
     double pr[W];
 #pragma unroll
-    for (int c = j + 1; c < W; ++c) pr[c] = prow[c];
+    for (int c = jj + 1; c < W; ++c) pr[c] = prow[c];
     auto update = [&](auto scale) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        const bool below = nz && pos[s] > j;
-        const double q = scale(v[s][j]);
+        const bool below = nz && pos[s] > jp;
+        const double q = scale(x[s][jj]);
         const double l = below ? q : 0.0;
-        v[s][j] = below ? q : v[s][j];
+        x[s][jj] = below ? q : x[s][jj];
 #pragma unroll
-        for (int c = j + 1; c < W; ++c) v[s][c] = fma(-l, pr[c], v[s][c]);
+        for (int c = jj + 1; c < W; ++c) x[s][c] = fma(-l, pr[c], x[s][c]);
       }
     };
     if (fabs(piv) >= 2.2250738585072014e-308) {   // uniform
@@ -278,84 +280,73 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
       update([piv](double x) { return x / piv; });
     }
   };
-  StaticFor<0, W>::run(column);
-  if (t == 0 && first_zero && *info == 0) *info = first_zero;
+  StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(v, jc, 0, nc); });
+  store_rows(v, k0, nc);
 
-  // ---- store the panel ----
-  for (int r = 0; r < nrounds; ++r) {
-    const int r0 = r * SR;
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * NT;
-      if (q >= r0 && q < r0 + SR && q < mm) {
-#pragma unroll
-        for (int c = 0; c < W; c += 2)
-          reinterpret_cast<double2*>(stage)[((q - r0) * W + c) / 2] = make_double2(v[s][c], v[s][c + 1]);
-      }
-    }
-    __syncthreads();
-    store_round(r0, k0, nc);
-    __syncthreads();
-  }
-
-  if (n2 > 0) {
-    // ---- sibling update: columns cs .. cs + n2 ----
+  if (LEAF_SIBLING(R) && n2 > 0) {
+    // ---- sibling update: columns cs .. cs + n2 - 1 ----
     const int cs = k0 + nc;
+    double x[R][W];
+    load_rows(x, cs, n2);
 #pragma unroll
     for (int s = 0; s < R; ++s)
       if (pos[s] >= 0 && pos[s] < nc) {
         const int i = pos[s];
 #pragma unroll
         for (int k = 0; k < W; ++k) s_l[i][k] = v[s][k];
-        const double* src = a + (long long)s_ph[t + s * NT] * lda + cs;
 #pragma unroll
-        for (int c = 0; c < W; ++c)
-          if (c < n2) s_u[i][c] = src[c];
+        for (int c = 0; c < W; ++c) s_u[i][c] = x[s][c];
       }
     __syncthreads();
     if (t < n2) {
-      // U12 = L11^{-1} A12, column t, in place
-      for (int i = 1; i < nc; ++i) {
-        double acc = s_u[i][t];
-        for (int k = 0; k < i; ++k) acc -= s_l[i][k] * s_u[k][t];
-        s_u[i][t] = acc;
-      }
+      // U12 = L11^{-1} A12, column t, by substitution in registers
+      double u[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) u[i] = i < nc ? s_u[i][t] : 0.0;
+      StaticFor<1, W>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (i >= nc) return;  // uniform
+        double acc = u[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc = fma(-s_l[i][k], u[k], acc);
+        u[i] = acc;
+      });
+#pragma unroll
+      for (int i = 0; i < W; ++i)
+        if (i < nc) s_u[i][t] = u[i];
     }
     __syncthreads();
-    double2 x[PER];
-    load_round(0, cs, n2, x);
-    for (int r = 0; r < nrounds; ++r) {
-      const int r0 = r * SR;
-      put_round(x);
-      __syncthreads();
-      if (r + 1 < nrounds) load_round(r0 + SR, cs, n2, x);
+    // A22 -= L21 U12, one row of U12 at a time (the scheduling barrier keeps
+    // the LDS reads of later rows from being hoisted into registers)
+    StaticFor<0, W>::run([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if (k >= nc) return;  // uniform
+      __builtin_amdgcn_sched_barrier(0);
+      double u[W];
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const int q = t + s * NT;
-        if (q >= r0 && q < r0 + SR && q < mm) {
-          double* row = stage + (q - r0) * W;
-          const bool top = pos[s] < nc;
-          const int pi = top ? pos[s] : 0;
-#pragma unroll 1
-          for (int c = 0; c < n2; ++c) {
-            double acc = row[c];
+      for (int c = 0; c < W; ++c) u[c] = s_u[k][c];
 #pragma unroll
-            for (int k = 0; k < W; ++k)
-              if (k < nc) acc = fma(-v[s][k], s_u[k][c], acc);
-            row[c] = top ? s_u[pi][c] : acc;
-          }
-        }
-      }
-      __syncthreads();
-      store_round(r0, cs, n2);
-      __syncthreads();
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int c = 0; c < W; ++c) x[s][c] = fma(-v[s][k], u[c], x[s][c]);
+    });
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const bool top = pos[s] >= 0 && pos[s] < nc;
+      const int pi = top ? pos[s] : 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c) x[s][c] = top ? s_u[pi][c] : x[s][c];
     }
+    // ---- factor the sibling's columns too (panel columns nc .. nc + n2) ----
+    StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(x, jc, nc, n2); });
+    store_rows(x, cs, n2);
   }
+  if (t == 0 && first_zero && *info == 0) *info = first_zero;
 
   // ---- the new row order ----
 #pragma unroll
   for (int s = 0; s < R; ++s)
-    if (pos[s] >= 0) perm[k0 + pos[s]] = s_ph[t + s * NT];
+    if (pos[s] >= 0) perm[k0 + pos[s]] = ph[s];
 }
 
 // widest leaf for a panel with mm rows (R * W <= 32 doubles per thread keeps
@@ -373,6 +364,7 @@ inline int leaf_width(int mm) {
 void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, int nc, int n2, int* info) {
   const int R = ceil_div(mm, LEAF_NT);
   if (nc > leaf_width(mm) || n2 > leaf_width(mm)) throw std::runtime_error("getrf_f64: leaf wider than its template");
+  if (n2 > 0 && !LEAF_SIBLING(R)) throw std::runtime_error("getrf_f64: no fused sibling update for this leaf");
   dim3 g(1), b(LEAF_NT);
   if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
@@ -491,10 +483,9 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   int n1 = (n / 2 + 7) / 8 * 8;
   if (n1 >= n) n1 = n / 2;
   const int n2 = n - n1;
-  if (n1 <= wmax && n2 <= wmax) {
-    // bottom node: the left leaf also updates its sibling's columns
+  if (n1 <= wmax && n2 <= wmax && LEAF_SIBLING(ceil_div(mm, LEAF_NT))) {
+    // bottom node: one leaf launch factors both halves
     launch_leaf(s, a, lda, perm, k0, mm, n1, n2, info);
-    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
     return;
   }
   getrf_rec(s, a, lda, perm, k0, m, n1, info, work, cnt);
