@@ -376,86 +376,98 @@ void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, i
   FROB_LAUNCH_CHECK();
 }
 
-// Internal recursion node with n1, n2 <= 64 in one launch (replaces a
-// triangular-solve launch and a GEMM launch): every workgroup solves
-// U12 = L11^{-1} A12 (quad substitution on an LDS copy of the unit lower
-// L11), then updates its 64 rows of A22 -= L21 U12.  A12 may be overwritten
-// with U12 only after every workgroup has read it: the workgroups count
-// themselves on *cnt and the last one writes U12 and resets the counter.
+// Internal recursion node with n1, n2 <= NB (16, 32 or 64) in one launch
+// (replaces a triangular-solve launch and a GEMM launch): every workgroup
+// solves U12 = L11^{-1} A12 (quad substitution on an LDS copy of the unit
+// lower L11), then updates its 64 rows of A22 -= L21 U12.  A12 may be
+// overwritten with U12 only after every workgroup has read it: the workgroups
+// count themselves on *cnt and the last one writes U12 and resets the counter.
 constexpr int NODE_MAX = 64;
+constexpr int NODE_ROWS = 64;   // rows of A22 per workgroup
+template <int NB>
 __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int lda, const int* __restrict__ perm,
                                                      int k0, int mm, int n1, int n2, int* cnt) {
-  constexpr int LD = NODE_MAX + 1;
-  __shared__ double Ls[NODE_MAX * LD];   // L11, then the block of L21
-  __shared__ double Us[NODE_MAX * LD];   // U12
-  __shared__ double rd[NODE_MAX];
+  constexpr int LD = NB + 1;
+  constexpr int TPR = 256 / NB;               // rows per pass of the NB-wide element mapping
+  constexpr int PL = NB * NB / 256;           // L11 / U12 elements per thread
+  constexpr int PB = NODE_ROWS * NB / 256;    // L21 / A22 elements per thread
+  constexpr int QB = NB / 4;                  // blocks of four rows in the solve
+  static_assert(PL >= 1 && NB % 4 == 0, "node shape");
+  __shared__ double Ls[NODE_ROWS * LD];       // L11, then the block of L21
+  __shared__ double Us[NB * LD];              // U12
+  __shared__ double rd[NB];
   __shared__ int s_last;
   const int tid = threadIdx.x;
-  const int cs = k0 + n1;                  // first column of A12 / A22
-  const int r0 = n1 + blockIdx.x * NODE_MAX;   // this workgroup's first row of L21 / A22
+  const int cs = k0 + n1;                     // first column of A12 / A22
+  const int r0 = n1 + blockIdx.x * NODE_ROWS; // this workgroup's first row of L21 / A22
+  const int er = tid / NB, ec = tid % NB;     // element (er + TPR u, ec)
+  const int c = tid >> 2, g = tid & 3;        // quad layout of the solve
   // Every global load has an in-range (clamped) address and is issued
-  // unconditionally in an unrolled batch, so the loads overlap (one memory
-  // latency instead of one per element); out-of-range values are replaced
-  // afterwards.  L21 and A22 are fetched up front and wait in registers while
-  // U12 is solved.
-  const int wr = tid >> 6, lc = tid & 63;  // a wave reads rows wr + 4u, 64 consecutive columns
-  const int c = tid >> 2, g = tid & 3;     // quad layout of the solve
-  const int ti = tid >> 4, tj = tid & 15;  // 4x4 outputs per thread in the product
-  int pl[16], pb[16], px[16], qr[4];
+  // unconditionally in one batch, so the loads overlap (one memory latency);
+  // out-of-range values are replaced afterwards.  L21 and A22 are fetched up
+  // front and wait in registers while U12 is solved.
+  // the product: thread (ti, tj) owns rows ti + 16 i (i < 4), columns tj + 16 j (j < CJ)
+  constexpr int CJ = NB / 16;
+  const int ti = tid >> 4, tj = tid & 15;
+  int pl[PL], pb[PB], px[QB], qr[4];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    pl[u] = perm[k0 + min(wr + 4 * u, n1 - 1)];
-    pb[u] = perm[k0 + min(r0 + wr + 4 * u, mm - 1)];
-    px[u] = perm[k0 + min(4 * u + g, n1 - 1)];
-  }
+  for (int u = 0; u < PL; ++u) pl[u] = perm[k0 + min(er + TPR * u, n1 - 1)];
+#pragma unroll
+  for (int u = 0; u < PB; ++u) pb[u] = perm[k0 + min(r0 + er + TPR * u, mm - 1)];
+#pragma unroll
+  for (int u = 0; u < QB; ++u) px[u] = perm[k0 + min(4 * u + g, n1 - 1)];
 #pragma unroll
   for (int i = 0; i < 4; ++i) qr[i] = perm[k0 + min(r0 + ti + 16 * i, mm - 1)];
-  double vl[16], vb[16], x[16], acc[4][4];
+  double vl[PL], vb[PB], x[QB], acc[4][CJ];
   {
-    const int cl = min(lc, n1 - 1), cx = cs + min(c, n2 - 1);
+    const int cl = k0 + min(ec, n1 - 1), cx = cs + min(c, n2 - 1);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      vl[u] = a[(long long)pl[u] * lda + k0 + cl];
-      x[u] = a[(long long)px[u] * lda + cx];
-      vb[u] = a[(long long)pb[u] * lda + k0 + cl];
-    }
+    for (int u = 0; u < PL; ++u) vl[u] = a[(long long)pl[u] * lda + cl];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) x[u] = a[(long long)px[u] * lda + cx];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) vb[u] = a[(long long)pb[u] * lda + cl];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = a[(long long)qr[i] * lda + cs + min(tj + 16 * j, n2 - 1)];
+      for (int j = 0; j < CJ; ++j) acc[i][j] = a[(long long)qr[i] * lda + cs + min(tj + 16 * j, n2 - 1)];
   }
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int r = wr + 4 * u;
-    Ls[r * LD + lc] = (r < n1 && lc < r) ? vl[u] : (r == lc ? 1.0 : 0.0);
-    x[u] = (4 * u + g < n1 && c < n2) ? x[u] : 0.0;
+  for (int u = 0; u < PL; ++u) {
+    const int r = er + TPR * u;
+    Ls[r * LD + ec] = (r < n1 && ec < r) ? vl[u] : (r == ec ? 1.0 : 0.0);
   }
-  if (tid < NODE_MAX) rd[tid] = 1.0;
+#pragma unroll
+  for (int u = 0; u < QB; ++u) x[u] = (4 * u + g < n1 && c < n2) ? x[u] : 0.0;
+  if (tid < NB) rd[tid] = 1.0;
   __syncthreads();
-  quad_lower_solve<LD>(Ls, rd, x, g, opaque_zero());
+  quad_lower_solve<LD, QB>(Ls, rd, x, g, opaque_zero());
   __syncthreads();   // every wave is done with L11
+  if (c < NB) {
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int r = wr + 4 * u;
-    Us[(4 * u + g) * LD + c] = x[u];
-    Ls[r * LD + lc] = (r0 + r < mm && lc < n1) ? vb[u] : 0.0;
+    for (int u = 0; u < QB; ++u) Us[(4 * u + g) * LD + c] = x[u];
+  }
+#pragma unroll
+  for (int u = 0; u < PB; ++u) {
+    const int r = er + TPR * u;
+    Ls[r * LD + ec] = (r0 + r < mm && ec < n1) ? vb[u] : 0.0;
   }
   __syncthreads();
   for (int k = 0; k < n1; ++k) {
-    double lv[4], uv[4];
+    double lv[4], uv[CJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i) lv[i] = Ls[(ti + 16 * i) * LD + k];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) uv[j] = Us[k * LD + tj + 16 * j];
+    for (int j = 0; j < CJ; ++j) uv[j] = Us[k * LD + tj + 16 * j];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(-lv[i], uv[j], acc[i][j]);
+      for (int j = 0; j < CJ; ++j) acc[i][j] = fma(-lv[i], uv[j], acc[i][j]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CJ; ++j) {
       const int r = r0 + ti + 16 * i, cc = tj + 16 * j;
       if (r < mm && cc < n2) a[(long long)qr[i] * lda + cs + cc] = acc[i][j];
     }
@@ -464,12 +476,23 @@ __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int
   __syncthreads();
   if (s_last) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int r = wr + 4 * u;
-      if (r < n1 && lc < n2) a[(long long)pl[u] * lda + cs + lc] = Us[r * LD + lc];
+    for (int u = 0; u < PL; ++u) {
+      const int r = er + TPR * u;
+      if (r < n1 && ec < n2) a[(long long)pl[u] * lda + cs + ec] = Us[r * LD + ec];
     }
     if (tid == 0) atomicExch(cnt, 0);
   }
+}
+
+void launch_node(hipStream_t s, double* a, int lda, const int* perm, int k0, int mm, int n1, int n2, int* cnt) {
+  const int rows = mm - n1;
+  const dim3 g(rows > 0 ? ceil_div(rows, NODE_ROWS) : 1), b(256);
+  const int w = max(n1, n2);
+  if (w <= 16) hipLaunchKernelGGL(k_lu_node_f64<16>, g, b, 0, s, a, lda, perm, k0, mm, n1, n2, cnt);
+  else if (w <= 32) hipLaunchKernelGGL(k_lu_node_f64<32>, g, b, 0, s, a, lda, perm, k0, mm, n1, n2, cnt);
+  else if (w <= NODE_MAX) hipLaunchKernelGGL(k_lu_node_f64<64>, g, b, 0, s, a, lda, perm, k0, mm, n1, n2, cnt);
+  else throw std::runtime_error("getrf_f64: node wider than the node kernel");
+  FROB_LAUNCH_CHECK();
 }
 
 // factor columns [k0, k0 + n) over logical rows [k0, m)
@@ -490,10 +513,7 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   }
   getrf_rec(s, a, lda, perm, k0, m, n1, info, work, cnt);
   if (n1 <= NODE_MAX && n2 <= NODE_MAX) {
-    const int rows = m - k0 - n1;
-    hipLaunchKernelGGL(k_lu_node_f64, dim3(rows > 0 ? ceil_div(rows, NODE_MAX) : 1), dim3(256), 0, s, a, lda, perm, k0,
-                       m - k0, n1, n2, cnt);
-    FROB_LAUNCH_CHECK();
+    launch_node(s, a, lda, perm, k0, m - k0, n1, n2, cnt);
     getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
     return;
   }

@@ -1,6 +1,6 @@
 // tri_dev.hpp -- device building block shared by the small triangular solve
-// kernels: substitution with a 64x64 lower triangle held in LDS, applied to
-// 64 right-hand sides at once by 256 threads.
+// kernels: substitution with a lower triangle of order <= 64 held in LDS,
+// applied to 64 right-hand sides at once by 256 threads.
 //
 // Thread tid works on right-hand side c = tid / 4 and owns its rows
 // i = 4 m + g (g = tid % 4, m = 0 .. 15) in registers.  Rows are processed in
@@ -52,13 +52,14 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
-// Solve L x = b in place (x holds b on entry).  L: 64 x 64 lower triangle in
-// LDS with row stride LDL; rd[i] = 1 / L(i, i).  Blocks before `bfirst` are
-// skipped (their rows of x are zero for every lane of the wave and stay zero).
-template <int LDL>
+// Solve L x = b in place (x holds b on entry).  L: (4 NBLK) x (4 NBLK) lower
+// triangle in LDS with row stride LDL (64 x 64 by default); rd[i] = 1 / L(i, i).
+// Blocks before `bfirst` are skipped (their rows of x are zero for every lane
+// of the wave and stay zero).
+template <int LDL, int NBLK>
 __device__ __forceinline__ void quad_lower_solve(const double* __restrict__ L, const double* __restrict__ rd,
-                                                 double (&x)[16], int g, int bfirst) {
-  StaticFor<0, 16>::run([&](auto bc) {
+                                                 double (&x)[NBLK], int g, int bfirst) {
+  StaticFor<0, NBLK>::run([&](auto bc) {
     constexpr int b = decltype(bc)::value;
     if (b < bfirst) return;  // uniform per wave
     double xb = x[b];
@@ -80,7 +81,7 @@ __device__ __forceinline__ void quad_lower_solve(const double* __restrict__ L, c
     const double xs[4] = {x0, x1, x2, x3};
     StaticFor<0, 4>::run([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      StaticFor<b + 1, 16>::run([&](auto mc) {
+      StaticFor<b + 1, NBLK>::run([&](auto mc) {
         constexpr int m = decltype(mc)::value;
         x[m] = fma(-L[(4 * m + g) * LDL + 4 * b + q], xs[q], x[m]);
       });
