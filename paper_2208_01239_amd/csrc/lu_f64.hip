@@ -15,6 +15,7 @@
 #include <climits>
 
 #include "common.hpp"
+#include "devutil.hpp"
 #include "internal.hpp"
 #include "tri_dev.hpp"
 
@@ -51,46 +52,6 @@ constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 // columns it loads the n2 <= W columns to the right, applies the
 // factorization to them (U12 = L11^{-1} A12 by substitution, A22 -= L21 U12
 // with L21 still in registers) and factors them as panel columns nc .. nc+n2.
-// Keys are the bit patterns of FP32 values: for the values used here (>= 0,
-// or negative for "no candidate") signed-integer order agrees with numeric
-// order wherever it matters (any value >= 0 beats any negative one), and an
-// integer max fuses with its DPP operand into one instruction.
-template <int CTRL, int RM>
-__device__ __forceinline__ int upd_dpp_i32(int old, int v) {
-  return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xF, false);
-}
-// maximum over each row of 16 lanes, left in the row's last lane
-__device__ __forceinline__ int row_max_key(int v) {
-  v = max(v, upd_dpp_i32<0x111, 0xF>(v, v));  // row_shr:1
-  v = max(v, upd_dpp_i32<0x112, 0xF>(v, v));  // row_shr:2
-  v = max(v, upd_dpp_i32<0x114, 0xF>(v, v));  // row_shr:4
-  v = max(v, upd_dpp_i32<0x118, 0xF>(v, v));  // row_shr:8
-  return v;
-}
-// maximum over the wave, the same in every lane
-__device__ __forceinline__ int wave_max_key(int v) {
-  v = row_max_key(v);
-  v = max(v, upd_dpp_i32<0x142, 0xA>(v, v));  // row_bcast:15 into rows 1, 3
-  v = max(v, upd_dpp_i32<0x143, 0xC>(v, v));  // row_bcast:31 into rows 2, 3
-  return __builtin_amdgcn_readlane(v, 63);
-}
-// Exact argmax over the lanes in `cand` of (val desc, key asc); returns the
-// winning lane.  Rare path (several lanes share the FP32 maximum).
-__device__ __forceinline__ int exact_argmax(unsigned long long cand, double val, int key) {
-  int wl = -1;
-  double bv = -1.0;
-  int bk = INT_MAX;
-  while (cand) {
-    const int l = __ffsll((long long)cand) - 1;
-    cand &= cand - 1;
-    const double lv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(val), l),
-                                       __builtin_amdgcn_readlane(__double2loint(val), l));
-    const int lk = __builtin_amdgcn_readlane(key, l);
-    if (lv > bv || (lv == bv && lk < bk)) { bv = lv; bk = lk; wl = l; }
-  }
-  return wl;
-}
-
 // the fused sibling update needs a second R x W block of registers; the
 // tallest leaves (more than 16 rows per thread) leave it to a node kernel
 constexpr bool LEAF_SIBLING(int R) { return R <= 16; }

@@ -1,19 +1,21 @@
 // lu_z64.hip -- complex (planar FP64) LU with partial pivoting for the
 // complex-arithmetic baseline (Algorithm 4).  Same design as lu_f64.hip:
-// recursive column splitting, register-resident leaf panels in one
-// 1024-thread workgroup, pivoting through the row-index array perm, staged
-// panel I/O, fused sibling update at bottom nodes.  The pivot measure is
-// |Re| + |Im| (LAPACK's izamax convention); ties go to the lowest row.
+// recursive column splitting, register-resident leaf panels in one 512-thread
+// workgroup with position-tracked rows, pivoting through the row-index array
+// perm, one launch per bottom recursion node.  A complex value takes two
+// registers, so a leaf holds half as many columns as the real one.  The pivot
+// measure is |Re| + |Im| (LAPACK's izamax convention); ties go to the lowest
+// row.
 #include "common.hpp"
 #include "devutil.hpp"
 #include "internal.hpp"
+#include "tri_dev.hpp"
 
 namespace frob {
 
 namespace {
 
-constexpr int ZLT = 1024;
-constexpr int ZSTAGE = 4096;  // doubles per plane in the LDS stage
+constexpr int ZLT = 512;   // threads of the leaf workgroup
 
 struct zc {
   double r, i;
@@ -29,280 +31,302 @@ __device__ __forceinline__ zc zrecip(zc z) {
   return zc{t / d, -1.0 / d};
 }
 
+// the fused sibling update needs a second R x W block of registers
+constexpr bool ZLEAF_SIBLING(int R) { return R <= 8; }
+
+// One workgroup factors an mm x nc complex panel (nc <= W) held in
+// registers, thread t owning panel rows q = t + s * ZLT (s < R).  The design
+// is the real leaf's (lu_f64.hip): rows never move, each carries its logical
+// position pos and a pivot step exchanges positions only; the candidate
+// search runs on FP32 images of the pivot measure |Re| + |Im| with the exact
+// FP64 comparison on ties; one barrier per column; rows are read and written
+// by their owning threads straight from HBM; with n2 > 0 the kernel factors a
+// whole bottom recursion node (the n2 columns to the right are updated with
+// U12 = L11^{-1} A12, A22 -= L21 U12 and factored as panel columns
+// nc .. nc + n2).
 template <int R, int W>
 __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, double* __restrict__ ai, int lda,
                                                      int* __restrict__ perm, int k0, int mm, int nc, int n2,
                                                      int* info) {
   constexpr int NW = ZLT / 64;
-  constexpr int SROWS = ZSTAGE / W;
-  constexpr int PER = ZSTAGE / ZLT;
-  static_assert(ZSTAGE % ZLT == 0 && ZSTAGE % W == 0, "stage shape");
-  __shared__ double sr_[ZSTAGE];
-  __shared__ double si_[ZSTAGE];
-  __shared__ int s_ph[SROWS];
   __shared__ double s_cv[2][NW];
-  __shared__ int s_ci[2][NW];
-  __shared__ int s_cph[2][NW];
-  __shared__ double s_crr[2][NW][W];
-  __shared__ double s_cri[2][NW][W];
-  __shared__ double s_jr[2][W];
-  __shared__ double s_ji[2][W];
-  __shared__ int s_jph[2];
-  __shared__ double s_ur[W][W];
-  __shared__ double s_ui[W][W];
+  __shared__ int s_ck[2][NW];
+  __shared__ double s_crr[2][NW][W], s_cri[2][NW][W];
+  __shared__ double s_lr[W][W + 1], s_li[W][W + 1];
+  __shared__ double s_ur[W][W + 1], s_ui[W][W + 1];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  double vr[R][W], vi[R][W];
-  int ph[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    ph[s] = -1;
-#pragma unroll
-    for (int c = 0; c < W; ++c) { vr[s][c] = 0.0; vi[s][c] = 0.0; }
-  }
+  const bool vbase = ((lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(ar) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(ai) & 15) == 0);
 
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
-    int pr[PER];
-    double xr[PER], xi[PER];
+  int ph[R], pos[R];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT, r = e / W;
-      pr[i] = r < nrow ? perm[k0 + r0 + r] : 0;
-    }
+  for (int s = 0; s < R; ++s) ph[s] = perm[k0 + min(t + s * ZLT, mm - 1)];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT, r = e / W, c = e % W;
-      const bool ok = r < nrow && c < nc;
-      const long long off = (long long)pr[i] * lda + k0 + c;
-      xr[i] = ok ? ar[off] : 0.0;
-      xi[i] = ok ? ai[off] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT;
-      sr_[e] = xr[i];
-      si_[e] = xi[i];
-      if (e % W == 0 && e / W < nrow) s_ph[e / W] = pr[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * ZLT;
-      if (q >= r0 && q < r0 + nrow) {
-        ph[s] = s_ph[q - r0];
-#pragma unroll
-        for (int c = 0; c < W; ++c) { vr[s][c] = sr_[(q - r0) * W + c]; vi[s][c] = si_[(q - r0) * W + c]; }
-      }
-    }
-    __syncthreads();
-  }
+  for (int s = 0; s < R; ++s) pos[s] = t + s * ZLT < mm ? t + s * ZLT : -1;
 
-  int first_zero = 0;
-#pragma unroll
-  for (int j = 0; j < W; ++j) {
-    if (j >= nc) continue;
-    const int par = j & 1;
-    double best = -1.0;
-    int bq = INT_MAX;
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * ZLT;
-      const double xv = fabs(vr[s][j]) + fabs(vi[s][j]);
-      const bool ok = q >= j && q < mm && xv > best;
-      best = ok ? xv : best;
-      bq = ok ? q : bq;
-    }
-    double wbest;
-    int wq;
-    const int wl = wave_argmax(best, bq, wbest, wq);
-    if (lane == wl) {
-      const int s = (wq - t) / ZLT;
-#pragma unroll
-      for (int ss = 0; ss < R; ++ss)
-        if (ss == s) {
-#pragma unroll
-          for (int c = 0; c < W; ++c) { s_crr[par][wv][c] = vr[ss][c]; s_cri[par][wv][c] = vi[ss][c]; }
-          s_cph[par][wv] = ph[ss];
-        }
-    }
-    if (lane == 0) { s_cv[par][wv] = wbest; s_ci[par][wv] = wq; }
-    if ((j & (ZLT - 1)) == t) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) { s_jr[par][c] = vr[j / ZLT][c]; s_ji[par][c] = vi[j / ZLT][c]; }
-      s_jph[par] = ph[j / ZLT];
-    }
-    __syncthreads();
-    double gb = -1.0;
-    int gq = INT_MAX, gw = -1;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const double cv = s_cv[par][w];
-      const int ci = s_ci[par][w];
-      const bool ok = ci != INT_MAX && (cv > gb || (cv == gb && ci < gq));
-      gb = ok ? cv : gb;
-      gq = ok ? ci : gq;
-      gw = ok ? w : gw;
-    }
-    const bool have = gw >= 0;
-    const int p = have ? gq : j;
-    double pwr[W], pwi[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      pwr[c] = have ? s_crr[par][gw][c] : s_jr[par][c];
-      pwi[c] = have ? s_cri[par][gw][c] : s_ji[par][c];
-    }
-    const int pph = have ? s_cph[par][gw] : s_jph[par];
-    if (p != j) {
-      if ((j & (ZLT - 1)) == t) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) { vr[j / ZLT][c] = pwr[c]; vi[j / ZLT][c] = pwi[c]; }
-        ph[j / ZLT] = pph;
-      }
-      if ((p & (ZLT - 1)) == t) {
-#pragma unroll
-        for (int ss = 0; ss < R; ++ss)
-          if (ss == p / ZLT) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) { vr[ss][c] = s_jr[par][c]; vi[ss][c] = s_ji[par][c]; }
-            ph[ss] = s_jph[par];
-          }
-      }
-    }
-    const zc piv{pwr[j], pwi[j]};
-    if (piv.r == 0.0 && piv.i == 0.0) {
-      if (!first_zero) first_zero = k0 + j + 1;
-    } else {
-      const zc rp = zrecip(piv);
+  // columns col0 .. col0 + ncol - 1 of this thread's rows (both planes), one
+  // batch of unconditional loads at clamped addresses
+  auto load_rows = [&](double (&xr)[R][W], double (&xi)[R][W], int col0, int ncol) {
+    if (W % 2 == 0 && vbase && ((col0 | ncol) & 1) == 0) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        const int q = t + s * ZLT;
-        const bool below = q > j && q < mm;
-        zc l = zmul(zc{vr[s][j], vi[s][j]}, rp);
-        if (!below) l = zc{0.0, 0.0};
-        if (below) { vr[s][j] = l.r; vi[s][j] = l.i; }
+        const long long o = (long long)ph[s] * lda + col0;
 #pragma unroll
-        for (int c = 0; c < W; ++c)
-          if (c > j) {
-            vr[s][c] -= l.r * pwr[c] - l.i * pwi[c];
-            vi[s][c] -= l.r * pwi[c] + l.i * pwr[c];
-          }
+        for (int c = 0; c + 1 < W; c += 2) {
+          const double2 yr = *reinterpret_cast<const double2*>(ar + o + min(c, ncol - 2));
+          const double2 yi = *reinterpret_cast<const double2*>(ai + o + min(c, ncol - 2));
+          xr[s][c] = yr.x; xr[s][c + 1] = yr.y;
+          xi[s][c] = yi.x; xi[s][c + 1] = yi.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const long long o = (long long)ph[s] * lda + col0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          xr[s][c] = ar[o + min(c, ncol - 1)];
+          xi[s][c] = ai[o + min(c, ncol - 1)];
+        }
       }
     }
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        xr[s][c] = c < ncol ? xr[s][c] : 0.0;
+        xi[s][c] = c < ncol ? xi[s][c] : 0.0;
+      }
+  };
+  auto store_rows = [&](const double (&xr)[R][W], const double (&xi)[R][W], int col0, int ncol) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      if (pos[s] < 0) continue;
+      const long long o = (long long)ph[s] * lda + col0;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c < ncol) {
+          ar[o + c] = xr[s][c];
+          ai[o + c] = xi[s][c];
+        }
+    }
+  };
+
+  double vr[R][W], vi[R][W];
+  load_rows(vr, vi, k0, nc);
+
+  int first_zero = 0;
+  // one column step: register column jj of block (xr, xi), panel column off + jj
+  auto column = [&](double (&xr)[R][W], double (&xi)[R][W], auto jc, int off, int ncols)
+                    __attribute__((always_inline)) {
+    constexpr int jj = decltype(jc)::value;
+    if (jj >= ncols) return;  // uniform
+    const int jp = off + jj;
+    constexpr int par = jj & 1;
+    auto meas = [&](int s) { return fabs(xr[s][jj]) + fabs(xi[s][jj]); };
+    auto key = [&](int s) {
+      const double m = meas(s);
+      return (pos[s] >= jp && m == m) ? __float_as_int((float)m) : -1;
+    };
+    int kmax = key(0);
+#pragma unroll
+    for (int s = 1; s < R; ++s) kmax = max(kmax, key(s));
+    double best = -1.0;
+    int bq = INT_MAX, nt = 0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const bool m = kmax >= 0 && key(s) == kmax;
+      best = m ? meas(s) : best;
+      bq = m ? pos[s] : bq;
+      nt += m ? 1 : 0;
+    }
+    if (R > 1 && __ballot(nt > 1)) {
+      best = -1.0;
+      bq = INT_MAX;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const double m = meas(s);
+        const bool ok = kmax >= 0 && key(s) == kmax && (m > best || (m == best && pos[s] < bq));
+        best = ok ? m : best;
+        bq = ok ? pos[s] : bq;
+      }
+    }
+    const int wmf = wave_max_key(kmax);
+    if (wmf >= 0) {
+      const unsigned long long tied = __ballot(kmax == wmf);
+      const int wl = (__popcll(tied) == 1) ? __ffsll((long long)tied) - 1 : exact_argmax(tied, best, bq);
+      if (lane == wl) {
+#pragma unroll
+        for (int s = 0; s < R; ++s)
+          if (pos[s] == bq) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+              s_crr[par][wv][c] = xr[s][c];
+              s_cri[par][wv][c] = xi[s][c];
+            }
+          }
+        s_cv[par][wv] = best;
+        s_ck[par][wv] = bq;
+      }
+    } else if (lane == 0) {
+      s_cv[par][wv] = -1.0;
+      s_ck[par][wv] = INT_MAX;
+    }
+    __syncthreads();
+    const double sv = lane < NW ? s_cv[par][lane] : -2.0;
+    const int sk = lane < NW ? s_ck[par][lane] : INT_MAX;
+    const int sf = __float_as_int((float)sv);
+    const int gmf = __builtin_amdgcn_readlane(row_max_key(sf), 15);
+    int p;
+    const double *prr, *pri;
+    if (gmf >= 0) {
+      const unsigned long long tied = __ballot(lane < NW && sf == gmf);
+      const int gw = (__popcll(tied) == 1) ? __ffsll((long long)tied) - 1 : exact_argmax(tied, sv, sk);
+      p = __builtin_amdgcn_readlane(sk, gw);
+      prr = s_crr[par][gw];
+      pri = s_cri[par][gw];
+    } else {
+      // every candidate is NaN: keep row jp in place (uniform slow path)
+      p = jp;
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+        if (pos[s] == jp) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            s_crr[par][0][c] = xr[s][c];
+            s_cri[par][0][c] = xi[s][c];
+          }
+        }
+      __syncthreads();
+      prr = s_crr[par][0];
+      pri = s_cri[par][0];
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) pos[s] = pos[s] == p ? jp : (pos[s] == jp ? p : pos[s]);
+    const zc piv{prr[jj], pri[jj]};
+    const bool nz = piv.r != 0.0 || piv.i != 0.0;
+    if (!nz && !first_zero) first_zero = k0 + jp + 1;
+    const zc rp = nz ? zrecip(piv) : zc{0.0, 0.0};
+    double pwr[W], pwi[W];
+#pragma unroll
+    for (int c = jj + 1; c < W; ++c) {
+      pwr[c] = prr[c];
+      pwi[c] = pri[c];
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const bool below = nz && pos[s] > jp;
+      const zc q = zmul(zc{xr[s][jj], xi[s][jj]}, rp);
+      const double lr = below ? q.r : 0.0, li = below ? q.i : 0.0;
+      xr[s][jj] = below ? q.r : xr[s][jj];
+      xi[s][jj] = below ? q.i : xi[s][jj];
+#pragma unroll
+      for (int c = jj + 1; c < W; ++c) {
+        xr[s][c] = fma(li, pwi[c], fma(-lr, pwr[c], xr[s][c]));
+        xi[s][c] = fma(-li, pwr[c], fma(-lr, pwi[c], xi[s][c]));
+      }
+    }
+  };
+  StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(vr, vi, jc, 0, nc); });
+  store_rows(vr, vi, k0, nc);
+
+  if (ZLEAF_SIBLING(R) && n2 > 0) {
+    const int cs = k0 + nc;
+    double xr[R][W], xi[R][W];
+    load_rows(xr, xi, cs, n2);
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+      if (pos[s] >= 0 && pos[s] < nc) {
+        const int i = pos[s];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          s_lr[i][k] = vr[s][k];
+          s_li[i][k] = vi[s][k];
+          s_ur[i][k] = xr[s][k];
+          s_ui[i][k] = xi[s][k];
+        }
+      }
+    __syncthreads();
+    if (t < n2) {
+      // U12 = L11^{-1} A12, column t, by substitution in registers
+      double ur[W], ui[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        ur[i] = i < nc ? s_ur[i][t] : 0.0;
+        ui[i] = i < nc ? s_ui[i][t] : 0.0;
+      }
+      StaticFor<1, W>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (i >= nc) return;  // uniform
+        double accr = ur[i], acci = ui[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+          const double lr = s_lr[i][k], li = s_li[i][k];
+          accr = fma(li, ui[k], fma(-lr, ur[k], accr));
+          acci = fma(-li, ur[k], fma(-lr, ui[k], acci));
+        }
+        ur[i] = accr;
+        ui[i] = acci;
+      });
+#pragma unroll
+      for (int i = 0; i < W; ++i)
+        if (i < nc) {
+          s_ur[i][t] = ur[i];
+          s_ui[i][t] = ui[i];
+        }
+    }
+    __syncthreads();
+    // A22 -= L21 U12, one row of U12 at a time
+    StaticFor<0, W>::run([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if (k >= nc) return;  // uniform
+      __builtin_amdgcn_sched_barrier(0);
+      double ur[W], ui[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        ur[c] = s_ur[k][c];
+        ui[c] = s_ui[k][c];
+      }
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const double lr = vr[s][k], li = vi[s][k];
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          xr[s][c] = fma(li, ui[c], fma(-lr, ur[c], xr[s][c]));
+          xi[s][c] = fma(-li, ur[c], fma(-lr, ui[c], xi[s][c]));
+        }
+      }
+    });
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const bool top = pos[s] >= 0 && pos[s] < nc;
+      const int pi = top ? pos[s] : 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        xr[s][c] = top ? s_ur[pi][c] : xr[s][c];
+        xi[s][c] = top ? s_ui[pi][c] : xi[s][c];
+      }
+    }
+    StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(xr, xi, jc, nc, n2); });
+    store_rows(xr, xi, cs, n2);
   }
   if (t == 0 && first_zero && *info == 0) *info = first_zero;
 
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * ZLT;
-      if (q >= r0 && q < r0 + nrow) {
-        s_ph[q - r0] = ph[s];
-        perm[k0 + q] = ph[s];
-#pragma unroll
-        for (int c = 0; c < W; ++c) { sr_[(q - r0) * W + c] = vr[s][c]; si_[(q - r0) * W + c] = vi[s][c]; }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT, r = e / W, c = e % W;
-      if (r < nrow && c < nc) {
-        const long long off = (long long)s_ph[r] * lda + k0 + c;
-        ar[off] = sr_[e];
-        ai[off] = si_[e];
-      }
-    }
-    __syncthreads();
-  }
-
-  if (n2 <= 0) return;
-  const int cs = k0 + nc;
-  for (int r0 = 0; r0 < mm; r0 += SROWS) {
-    const int nrow = min(SROWS, mm - r0);
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * ZLT;
-      if (q >= r0 && q < r0 + nrow) s_ph[q - r0] = ph[s];
-    }
-    __syncthreads();
-    double xr[PER], xi[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT, r = e / W, c = e % W;
-      const bool ok = r < nrow && c < n2;
-      const long long off = ok ? (long long)s_ph[r] * lda + cs + c : 0;
-      xr[i] = ok ? ar[off] : 0.0;
-      xi[i] = ok ? ai[off] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) { sr_[t + i * ZLT] = xr[i]; si_[t + i * ZLT] = xi[i]; }
-    __syncthreads();
-    if (r0 == 0 && t < 64) {
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        if (k < nc) {
-          if (t > k && t < nc) {
-            const double lr = vr[0][k], li = vi[0][k];
-#pragma unroll
-            for (int c = 0; c < W; ++c) {
-              const double ur = sr_[k * W + c], ui = si_[k * W + c];
-              sr_[t * W + c] -= lr * ur - li * ui;
-              si_[t * W + c] -= lr * ui + li * ur;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-      }
-      for (int e = t; e < W * W; e += 64) {
-        const bool ok = e / W < nc;
-        s_ur[e / W][e % W] = ok ? sr_[e] : 0.0;
-        s_ui[e / W][e % W] = ok ? si_[e] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int q = t + s * ZLT;
-      if (q >= r0 && q < r0 + nrow && q >= nc) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) {
-          double accr = sr_[(q - r0) * W + c], acci = si_[(q - r0) * W + c];
-#pragma unroll
-          for (int k = 0; k < W; ++k)
-            if (k < nc) {
-              accr -= vr[s][k] * s_ur[k][c] - vi[s][k] * s_ui[k][c];
-              acci -= vr[s][k] * s_ui[k][c] + vi[s][k] * s_ur[k][c];
-            }
-          sr_[(q - r0) * W + c] = accr;
-          si_[(q - r0) * W + c] = acci;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = t + i * ZLT, r = e / W, c = e % W;
-      if (r < nrow && c < n2) {
-        const long long off = (long long)s_ph[r] * lda + cs + c;
-        ar[off] = sr_[e];
-        ai[off] = si_[e];
-      }
-    }
-    __syncthreads();
-  }
+  for (int s = 0; s < R; ++s)
+    if (pos[s] >= 0) perm[k0 + pos[s]] = ph[s];
 }
 
+// widest leaf for a panel with mm rows (R * W <= 16 complex values per thread)
 inline int zleaf_width(int mm) {
   const int R = ceil_div(mm, ZLT);
+  if (R <= 1) return 16;
   if (R <= 2) return 8;
   if (R <= 4) return 4;
   if (R <= 8) return 2;
-  if (R <= 16) return 1;
+  if (R <= 32) return 1;
   return 0;
 }
 
@@ -310,18 +334,207 @@ void zlaunch_leaf(hipStream_t s, double* ar, double* ai, int lda, int* perm, int
                   int* info) {
   const int R = ceil_div(mm, ZLT);
   if (nc > zleaf_width(mm) || n2 > zleaf_width(mm)) throw std::runtime_error("getrf_z64: leaf wider than template");
+  if (n2 > 0 && !ZLEAF_SIBLING(R)) throw std::runtime_error("getrf_z64: no fused sibling update for this leaf");
   dim3 g(1), b(ZLT);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
+  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_z64<8, 2>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
   else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_z64<16, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
+  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_z64<32, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
   else throw std::runtime_error("getrf_z64: matrix order above 16384 is not supported");
   FROB_LAUNCH_CHECK();
 }
 
+// Solve L x = b in place for a unit lower complex triangle L of order
+// 4 NBLK in LDS (planes Lr, Li, row stride LDL); the quad layout and
+// sweeps of quad_lower_solve (tri_dev.hpp), in complex arithmetic.
+template <int LDL, int NBLK>
+__device__ __forceinline__ void zquad_unit_lower_solve(const double* __restrict__ Lr, const double* __restrict__ Li,
+                                                       double (&xr)[NBLK], double (&xi)[NBLK], int g) {
+  StaticFor<0, NBLK>::run([&](auto bc) {
+    constexpr int b = decltype(bc)::value;
+    double br = xr[b], bi = xi[b];
+    double sr[4], si[4];
+    StaticFor<0, 4>::run([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      sr[q] = quad_bcast<q>(br);
+      si[q] = quad_bcast<q>(bi);
+      if (q < 3 && g > q) {
+        const double lr = Lr[(4 * b + g) * LDL + 4 * b + q], li = Li[(4 * b + g) * LDL + 4 * b + q];
+        br = fma(li, si[q], fma(-lr, sr[q], br));
+        bi = fma(-li, sr[q], fma(-lr, si[q], bi));
+      }
+    });
+    xr[b] = br;
+    xi[b] = bi;
+    StaticFor<0, 4>::run([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      StaticFor<b + 1, NBLK>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        const double lr = Lr[(4 * m + g) * LDL + 4 * b + q], li = Li[(4 * m + g) * LDL + 4 * b + q];
+        xr[m] = fma(li, si[q], fma(-lr, sr[q], xr[m]));
+        xi[m] = fma(-li, sr[q], fma(-lr, si[q], xi[m]));
+      });
+    });
+  });
+}
+
+// Internal recursion node with n1, n2 <= NB (16 or 32) in one launch, the
+// complex counterpart of the real node kernel (lu_f64.hip): every workgroup
+// solves U12 = L11^{-1} A12 and updates its 64 rows of A22 -= L21 U12; the
+// last workgroup to finish (counted on *cnt) writes U12 and resets the count.
+constexpr int ZNODE_MAX = 32;
+template <int NB>
+__global__ __launch_bounds__(256) void k_lu_node_z64(double* __restrict__ ar, double* __restrict__ ai, int lda,
+                                                     const int* __restrict__ perm, int k0, int mm, int n1, int n2,
+                                                     int* cnt) {
+  constexpr int ROWS = 64;
+  constexpr int LD = NB + 1;
+  constexpr int TPR = 256 / NB;
+  constexpr int PL = NB * NB / 256;
+  constexpr int PB = ROWS * NB / 256;
+  constexpr int QB = NB / 4;
+  constexpr int CJ = NB / 16;
+  static_assert(PL >= 1 && NB % 16 == 0, "node shape");
+  __shared__ double Lsr[ROWS * LD], Lsi[ROWS * LD];
+  __shared__ double Usr[NB * LD], Usi[NB * LD];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int cs = k0 + n1;
+  const int r0 = n1 + blockIdx.x * ROWS;
+  const int er = tid / NB, ec = tid % NB;
+  const int c = tid >> 2, g = tid & 3;
+  const int ti = tid >> 4, tj = tid & 15;
+  // one batch of unconditional loads at clamped addresses
+  int pl[PL], pb[PB], px[QB], qr[4];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) pl[u] = perm[k0 + min(er + TPR * u, n1 - 1)];
+#pragma unroll
+  for (int u = 0; u < PB; ++u) pb[u] = perm[k0 + min(r0 + er + TPR * u, mm - 1)];
+#pragma unroll
+  for (int u = 0; u < QB; ++u) px[u] = perm[k0 + min(4 * u + g, n1 - 1)];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) qr[i] = perm[k0 + min(r0 + ti + 16 * i, mm - 1)];
+  double vlr[PL], vli[PL], vbr[PB], vbi[PB], xr[QB], xi[QB], accr[4][CJ], acci[4][CJ];
+  {
+    const int cl = k0 + min(ec, n1 - 1), cx = cs + min(c, n2 - 1);
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      vlr[u] = ar[(long long)pl[u] * lda + cl];
+      vli[u] = ai[(long long)pl[u] * lda + cl];
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      xr[u] = ar[(long long)px[u] * lda + cx];
+      xi[u] = ai[(long long)px[u] * lda + cx];
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      vbr[u] = ar[(long long)pb[u] * lda + cl];
+      vbi[u] = ai[(long long)pb[u] * lda + cl];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const long long o = (long long)qr[i] * lda + cs + min(tj + 16 * j, n2 - 1);
+        accr[i][j] = ar[o];
+        acci[i][j] = ai[o];
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int r = er + TPR * u;
+    const bool low = r < n1 && ec < r;
+    Lsr[r * LD + ec] = low ? vlr[u] : (r == ec ? 1.0 : 0.0);
+    Lsi[r * LD + ec] = low ? vli[u] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < QB; ++u) {
+    const bool ok = 4 * u + g < n1 && c < n2;
+    xr[u] = ok ? xr[u] : 0.0;
+    xi[u] = ok ? xi[u] : 0.0;
+  }
+  __syncthreads();
+  zquad_unit_lower_solve<LD, QB>(Lsr, Lsi, xr, xi, g);
+  __syncthreads();   // every wave is done with L11
+  if (c < NB) {
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      Usr[(4 * u + g) * LD + c] = xr[u];
+      Usi[(4 * u + g) * LD + c] = xi[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PB; ++u) {
+    const int r = er + TPR * u;
+    const bool ok = r0 + r < mm && ec < n1;
+    Lsr[r * LD + ec] = ok ? vbr[u] : 0.0;
+    Lsi[r * LD + ec] = ok ? vbi[u] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n1; ++k) {
+    double lr[4], li[4], ur[CJ], ui[CJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      lr[i] = Lsr[(ti + 16 * i) * LD + k];
+      li[i] = Lsi[(ti + 16 * i) * LD + k];
+    }
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      ur[j] = Usr[k * LD + tj + 16 * j];
+      ui[j] = Usi[k * LD + tj + 16 * j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        accr[i][j] = fma(li[i], ui[j], fma(-lr[i], ur[j], accr[i][j]));
+        acci[i][j] = fma(-li[i], ur[j], fma(-lr[i], ui[j], acci[i][j]));
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int r = r0 + ti + 16 * i, cc = tj + 16 * j;
+      if (r < mm && cc < n2) {
+        const long long o = (long long)qr[i] * lda + cs + cc;
+        ar[o] = accr[i][j];
+        ai[o] = acci[i][j];
+      }
+    }
+  // every read of A12 by this workgroup is complete
+  if (tid == 0) s_last = atomicAdd(cnt, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (s_last) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int r = er + TPR * u;
+      if (r < n1 && ec < n2) {
+        const long long o = (long long)pl[u] * lda + cs + ec;
+        ar[o] = Usr[r * LD + ec];
+        ai[o] = Usi[r * LD + ec];
+      }
+    }
+    if (tid == 0) atomicExch(cnt, 0);
+  }
+}
+
+void zlaunch_node(hipStream_t s, double* ar, double* ai, int lda, const int* perm, int k0, int mm, int n1, int n2,
+                  int* cnt) {
+  const int rows = mm - n1;
+  const dim3 g(rows > 0 ? ceil_div(rows, 64) : 1), b(256);
+  const int w = max(n1, n2);
+  if (w <= 16) hipLaunchKernelGGL(k_lu_node_z64<16>, g, b, 0, s, ar, ai, lda, perm, k0, mm, n1, n2, cnt);
+  else if (w <= ZNODE_MAX) hipLaunchKernelGGL(k_lu_node_z64<32>, g, b, 0, s, ar, ai, lda, perm, k0, mm, n1, n2, cnt);
+  else throw std::runtime_error("getrf_z64: node wider than the node kernel");
+  FROB_LAUNCH_CHECK();
+}
+
 void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k0, int m, int n, int* info,
-                double* work) {
+                double* work, int* cnt) {
   const int mm = m - k0;
   const int wmax = zleaf_width(mm);
   if (n <= wmax) {
@@ -331,12 +544,17 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   int n1 = (n / 2 + 3) / 4 * 4;
   if (n1 >= n) n1 = n / 2;
   const int n2 = n - n1;
-  if (n1 <= wmax && n2 <= wmax) {
+  if (n1 <= wmax && n2 <= wmax && ZLEAF_SIBLING(ceil_div(mm, ZLT))) {
+    // bottom node: one leaf launch factors both halves
     zlaunch_leaf(s, ar, ai, lda, perm, k0, mm, n1, n2, info);
-    zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work);
     return;
   }
-  zgetrf_rec(s, ar, ai, lda, perm, k0, m, n1, info, work);
+  zgetrf_rec(s, ar, ai, lda, perm, k0, m, n1, info, work, cnt);
+  if (n1 <= ZNODE_MAX && n2 <= ZNODE_MAX) {
+    zlaunch_node(s, ar, ai, lda, perm, k0, m - k0, n1, n2, cnt);
+    zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt);
+    return;
+  }
   ZOp L11{ar + k0, ai + k0, lda, perm + k0};
   ZOut A12{ar + k0 + n1, ai + k0 + n1, lda, perm + k0, nullptr};
   trsm_z64(s, false, TRI_LOWER_UNIT, OP_N, n1, n2, L11, A12, work);
@@ -344,17 +562,20 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   ZOp U12{ar + k0 + n1, ai + k0 + n1, lda, perm + k0};
   ZOut A22{ar + k0 + n1, ai + k0 + n1, lda, perm + k0 + n1, nullptr};
   gemm_z64(s, OP_N, OP_N, m - k0 - n1, n2, n1, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
-  zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work);
+  zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt);
 }
 
 }  // namespace
 
-size_t getrf_z_work_elems(int n) { return trsm_z_work_elems(n / 2 + 8); }
+size_t getrf_z_work_elems(int n) { return trsm_z_work_elems(n / 2 + 8) + 64; }
 
 void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work) {
   if (n <= 0) return;
   iota_i32(s, n, perm);
-  zgetrf_rec(s, re, im, lda, perm, 0, n, n, info, work);
+  // the node kernels' workgroup counter lives in the first 64 doubles of work
+  int* cnt = reinterpret_cast<int*>(work);
+  fill_i32(s, 1, 0, cnt);
+  zgetrf_rec(s, re, im, lda, perm, 0, n, n, info, work + 64, cnt);
 }
 
 }  // namespace frob
