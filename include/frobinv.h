@@ -79,8 +79,14 @@ typedef struct {
   int refine;           /* maximum number of Newton-Schulz steps X <- X + X (I - M X) (0 = none)           */
   int prec;             /* frob_prec_t, default FROB_PREC_F64                                               */
   double refine_tol;    /* stop refining once ||I - M X||_F / sqrt(n) <= refine_tol (<= 0: 1e-14)            */
-  int reserved[4];
+  int refine_flags;     /* FROB_REFINE_* bits, default 0                                                    */
+  int reserved[3];
 } frob_opts_t;
+
+/* refine_flags: when refinement ends at the step limit (opts.refine steps
+ * applied), do not form the residual of the returned inverse (result.resid is
+ * then NaN).  Saves the three n x n x n products that only measure it. */
+#define FROB_REFINE_SKIP_FINAL_RESID 1
 
 typedef struct {
   int info;             /* 1-based column of the failing pivot, 0 if none                                   */
@@ -89,7 +95,7 @@ typedef struct {
   int shifts_tried;     /* number of shifts drawn (Algorithm 6 re-draws when A - mu B is singular)           */
   int refine_steps;     /* Newton-Schulz steps applied                                                     */
   double resid0;        /* ||I - M X||_F / sqrt(n) of the unrefined inverse (refine > 0 only)              */
-  double resid;         /* the same for the returned inverse (refine > 0 only)                             */
+  double resid;         /* the same for the returned inverse (refine > 0 only; NaN if skipped, see above)   */
   double reserved[2];
 } frob_result_t;
 

@@ -29,12 +29,13 @@ FROB_SHIFT_ON = 2
 FROB_PREC_F64 = 0
 FROB_PREC_F32 = 1
 FROB_PREC_BF16 = 2
+FROB_REFINE_SKIP_FINAL_RESID = 1
 
 
 class frob_opts_t(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine", ctypes.c_int), ("prec", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("reserved", ctypes.c_int * 4)]
+                ("refine_flags", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class frob_result_t(ctypes.Structure):

@@ -222,6 +222,7 @@ void frob_default_opts(frob_opts_t* o) {
   o->refine = 0;
   o->prec = FROB_PREC_F64;
   o->refine_tol = 0.0;
+  o->refine_flags = 0;
 }
 
 frob_status_t frob_create(frob_handle_t* out, int device) {
@@ -328,7 +329,7 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
     if (!done) st = FROB_SINGULAR;
     if (st == FROB_OK && o.refine > 0) {
       LowPrecScope fp64(LP_NONE);   // the residual is formed in FP64
-      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, c, &r);
+      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, o.refine_flags, c, &r);
     } else if (st == FROB_OK) {
       FROB_HIP(hipStreamSynchronize(s));
     }
@@ -391,7 +392,7 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     if (h->hinfo[0]) { st = FROB_NOT_HPD; r.info = h->hinfo[0]; r.stage = 1; }
     else if (h->hinfo[1]) { st = FROB_NOT_HPD; r.info = h->hinfo[1]; r.stage = 2; }
     if (st == FROB_OK && o.refine > 0)
-      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, c, &r);
+      st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, o.refine_flags, c, &r);
     if (res) *res = r;
     return st;
   });

@@ -80,6 +80,7 @@ void read_info(frob_handle* h);
 // residual is formed in FP64, the correction product in precision `prec`.
 size_t ns_ws_bytes(int n, int steps);
 frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
-                        double* Xi, int ldx, int max_steps, double tol, int prec, Carve& c, frob_result_t* r);
+                        double* Xi, int ldx, int max_steps, double tol, int prec, int flags, Carve& c,
+                        frob_result_t* r);
 
 }  // namespace frob

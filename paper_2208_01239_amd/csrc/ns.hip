@@ -6,7 +6,8 @@
 // lower operand precision (its error is relative to the already small R).
 // Refinement stops when ||R||_F / sqrt(n) reaches the tolerance, when it no
 // longer halves (the FP64 rounding floor, about u kappa(M)), or after the
-// step limit; it does not start when ||R||_F >= 1.
+// step limit (optionally without forming the residual of the last iterate);
+// it does not start when ||R||_F >= 1.
 //
 // Both complex products are formed from three real matrix-core GEMMs with
 // Gauss's scheme (Proposition 2.2 with tau = 1):
@@ -48,7 +49,8 @@ static void gauss3m(hipStream_t s, int n, const double* Pr, int ldp, const doubl
 }
 
 frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
-                        double* Xi, int ldx, int max_steps, double tol, int prec, Carve& c, frob_result_t* r) {
+                        double* Xi, int ldx, int max_steps, double tol, int prec, int flags, Carve& c,
+                        frob_result_t* r) {
   hipStream_t s = h->stream;
   const size_t nn = (size_t)n * n;
   double* Rr = c.take<double>(nn);
@@ -63,6 +65,10 @@ frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const d
   int steps = 0;
   frob_status_t st = FROB_OK;
   for (int k = 0;; ++k) {
+    if (k > 0 && k == max_steps && (flags & FROB_REFINE_SKIP_FINAL_RESID)) {
+      r->resid = std::nan("");   // step limit reached; the closing residual is not formed
+      break;
+    }
     // R = I - M X in FP64, and its Frobenius norm
     gauss3m(s, n, A, lda, B, Xr, ldx, Xi, Rr, Ri, n, T1, T2);
     resid_form_f64(s, n, Rr, Ri, n, h->dnorm);

@@ -18,6 +18,9 @@ of the paper (Section 5) and the synthetic configurations used for measurement:
                       [[0, -t], [t, 0]].
 * ``spectrum``     -- M = U diag(sigma) V^H (or U diag(sigma) U^H) with Haar
                       U, V and sigma log-spaced to a target condition number.
+* ``spectrum_device`` -- the same recipe at large orders, drawn and assembled
+                      with torch on a device (its own random stream), with
+                      the inverse V diag(1/sigma) U^H from the same factors.
 * ``batch``        -- uneven batch: n ~ U{16..512}, kinds alternate general/HPD.
 """
 from __future__ import annotations
@@ -117,6 +120,38 @@ def spectrum(n: int, kappa: float, kind: str = "general", seed: int = 302):
         V = haar_unitary(n, rng)
         M = (U * sig) @ V.conj().T
     return np.ascontiguousarray(M.real), np.ascontiguousarray(M.imag)
+
+
+def spectrum_device(n: int, kappa: float, kind: str = "general", seed: int = 302, device: str = "cuda"):
+    """Large-order form of ``spectrum``: U, V Haar (QR of complex Gaussians
+    with the diagonal phases of R taken out), sigma_j = kappa^(-j/(n-1)),
+    drawn with a seeded torch generator on ``device`` and assembled there in
+    FP64.  Returns torch tensors (A, B, Re Minv, Im Minv) where
+    Minv = V diag(1/sigma) U^H is built from the same factors (it is the
+    inverse of the stored M to about u * kappa, relative)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar():
+        re = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+        im = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+        Q, R = torch.linalg.qr(torch.complex(re, im) / np.sqrt(2.0))
+        d = torch.diagonal(R)
+        return Q * (d / d.abs())
+
+    U = haar()
+    V = U if kind == "hpd" else haar()
+    sig = kappa ** (-torch.arange(n, device=device, dtype=torch.float64) / max(n - 1, 1))
+    Vh = V.conj().T.contiguous()
+    Uh = U.conj().T.contiguous()
+    M = (U * sig) @ Vh
+    Minv = (V * (1.0 / sig)) @ Uh
+    if kind == "hpd":
+        M = 0.5 * (M + M.conj().T)
+        Minv = 0.5 * (Minv + Minv.conj().T)
+    return (M.real.contiguous(), M.imag.contiguous(), Minv.real.contiguous(), Minv.imag.contiguous())
 
 
 def batch(count: int = 2048, seed: int = 4, n_lo: int = 16, n_hi: int = 512):

@@ -211,6 +211,16 @@ def test_refinement_reduces_error(h):
     assert relF(X1r, X1i, Rr, Ri) <= TOL
 
 
+def test_refinement_without_closing_residual(h):
+    """Skipping the residual of the last iterate changes no arithmetic of the
+    refinement: the same inverse, bit for bit, with resid reported as NaN."""
+    A, B = inputs.general(256, 91)
+    X1r, X1i, res1 = gpu_general(h, A, B, refine=1, refine_tol=1e-300)
+    X2r, X2i, res2 = gpu_general(h, A, B, refine=1, refine_tol=1e-300, final_resid=False)
+    assert res2["refine_steps"] == 1 and np.isnan(res2["resid"]) and res2["resid0"] == res1["resid0"]
+    assert np.array_equal(X1r, X2r) and np.array_equal(X1i, X2i)
+
+
 def test_determinism(h):
     A, B = inputs.general(200, 4)
     X1 = gpu_general(h, A, B)
