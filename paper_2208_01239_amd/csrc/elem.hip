@@ -49,17 +49,22 @@ __global__ void k_axpby(int m, int n, double a, const double* __restrict__ X, in
   *y = (b == 0.0) ? a * x : a * x + b * *y;
 }
 
-// R <- I - R (real and imaginary planes), sumsq += ||R||_F^2 (one atomic per block)
+// R <- I - R (real and imaginary planes), sumsq += ||R||_F^2.  A block
+// covers RESID_ROWS rows (one atomic per block: few enough that the atomics
+// on the single accumulator do not serialize the kernel).
+constexpr int RESID_ROWS = 8;
 __global__ void k_resid_form(int n, double* __restrict__ Rr, double* __restrict__ Ri, int ld, double* sumsq) {
-  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
   double acc = 0.0;
-  if (j < n) {
-    double* pr = Rr + (long long)i * ld + j;
-    double* pi = Ri + (long long)i * ld + j;
-    const double vr = (i == j ? 1.0 : 0.0) - *pr, vi = -*pi;
-    *pr = vr;
-    *pi = vi;
-    acc = vr * vr + vi * vi;
+  const int i1 = min(n, (int)(blockIdx.x + 1) * RESID_ROWS);
+  for (int i = blockIdx.x * RESID_ROWS; i < i1; ++i) {
+    double* pr = Rr + (long long)i * ld;
+    double* pi = Ri + (long long)i * ld;
+    for (int j = threadIdx.x; j < n; j += EB) {
+      const double vr = (i == j ? 1.0 : 0.0) - pr[j], vi = -pi[j];
+      pr[j] = vr;
+      pi[j] = vi;
+      acc = fma(vr, vr, fma(vi, vi, acc));
+    }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
@@ -104,7 +109,7 @@ __global__ void k_zero_upper(int n, double* a, int lda) {
 
 void resid_form_f64(hipStream_t s, int n, double* Rr, double* Ri, int ld, double* sumsq) {
   fill_f64(s, 1, 1, 0.0, sumsq, 1);
-  hipLaunchKernelGGL(k_resid_form, grid2d(n, n), dim3(EB), 0, s, n, Rr, Ri, ld, sumsq);
+  hipLaunchKernelGGL(k_resid_form, dim3(ceil_div(n, RESID_ROWS)), dim3(EB), 0, s, n, Rr, Ri, ld, sumsq);
   FROB_LAUNCH_CHECK();
 }
 

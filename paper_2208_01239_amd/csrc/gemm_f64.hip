@@ -20,7 +20,9 @@
 // flight while the current tile is multiplied.  Padding keeps the 16-lane
 // fragment reads on distinct banks.  Linear block ids are remapped so that
 // each of the 8 XCDs (hardware assigns block b to XCD b % 8) works on a
-// contiguous band of tiles, which keeps the shared A rows in that XCD's L2.
+// contiguous range of tile indices, and tile indices run through groups of
+// eight tile-rows column by column, so the tiles one XCD runs at the same
+// time form a square block whose A rows and B columns stay in its L2.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -50,6 +52,8 @@ __device__ __forceinline__ double tri_mask(double v, int tri, int r, int c) {
   }
 }
 
+constexpr int TILE_GROUP = 8;
+
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   constexpr int BK = 16;
@@ -74,8 +78,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   const int bid = blockIdx.x;
   const int t = (bid & 7) * per + (bid >> 3);
   if (t >= tiles) return;
-  const int bm0 = (t / g.tilesN) * BM;
-  const int bn0 = (t % g.tilesN) * BN;
+  // grouped order: TILE_GROUP tile-rows at a time, column-major inside the
+  // group, so that the tiles an XCD runs at once form a square block
+  const int gsz = TILE_GROUP * g.tilesN;
+  const int grp = t / gsz;
+  const int gh = min(TILE_GROUP, g.tilesM - grp * TILE_GROUP);
+  const int wt = t - grp * gsz;
+  const int bm0 = (grp * TILE_GROUP + wt % gh) * BM;
+  const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
 
   const long long z = blockIdx.z;

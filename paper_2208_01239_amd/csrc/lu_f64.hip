@@ -83,7 +83,7 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   // one batch of unconditional loads at clamped addresses (16-byte pairs
   // when rows are 16-byte aligned and the extent is even), columns beyond
   // ncol zeroed afterwards.
-  auto load_rows = [&](double (&x)[R][W], int col0, int ncol) {
+  auto load_rows = [&](double (&x)[R][W], int col0, int ncol, bool mask = true) {
     if (vbase && ((col0 | ncol) & 1) == 0) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
@@ -103,10 +103,12 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
         for (int c = 0; c < W; ++c) x[s][c] = row[min(c, ncol - 1)];
       }
     }
+    if (mask) {
 #pragma unroll
-    for (int s = 0; s < R; ++s)
+      for (int s = 0; s < R; ++s)
 #pragma unroll
-      for (int c = 0; c < W; ++c) x[s][c] = c < ncol ? x[s][c] : 0.0;
+        for (int c = 0; c < W; ++c) x[s][c] = c < ncol ? x[s][c] : 0.0;
+    }
   };
   auto store_rows = [&](const double (&x)[R][W], int col0, int ncol) {
     const bool vec = vbase && ((col0 | ncol) & 1) == 0;
@@ -126,8 +128,11 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
     }
   };
 
-  double v[R][W];
+  double v[R][W], x[R][W];
   load_rows(v, k0, nc);
+  // the sibling's columns are fetched now and stay in flight during the first
+  // half (masked when first used, so nothing waits on them before)
+  if (LEAF_SIBLING(R) && n2 > 0) load_rows(x, k0 + nc, n2, false);
 
   // ---- factor ----
   int first_zero = 0;
@@ -247,8 +252,10 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   if (LEAF_SIBLING(R) && n2 > 0) {
     // ---- sibling update: columns cs .. cs + n2 - 1 ----
     const int cs = k0 + nc;
-    double x[R][W];
-    load_rows(x, cs, n2);
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int c = 0; c < W; ++c) x[s][c] = c < n2 ? x[s][c] : 0.0;
 #pragma unroll
     for (int s = 0; s < R; ++s)
       if (pos[s] >= 0 && pos[s] < nc) {

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
 
   // columns col0 .. col0 + ncol - 1 of this thread's rows (both planes), one
   // batch of unconditional loads at clamped addresses
-  auto load_rows = [&](double (&xr)[R][W], double (&xi)[R][W], int col0, int ncol) {
+  auto load_rows = [&](double (&xr)[R][W], double (&xi)[R][W], int col0, int ncol, bool mask = true) {
     if (W % 2 == 0 && vbase && ((col0 | ncol) & 1) == 0) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
@@ -92,13 +92,15 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
         }
       }
     }
+    if (mask) {
 #pragma unroll
-    for (int s = 0; s < R; ++s)
+      for (int s = 0; s < R; ++s)
 #pragma unroll
-      for (int c = 0; c < W; ++c) {
-        xr[s][c] = c < ncol ? xr[s][c] : 0.0;
-        xi[s][c] = c < ncol ? xi[s][c] : 0.0;
-      }
+        for (int c = 0; c < W; ++c) {
+          xr[s][c] = c < ncol ? xr[s][c] : 0.0;
+          xi[s][c] = c < ncol ? xi[s][c] : 0.0;
+        }
+    }
   };
   auto store_rows = [&](const double (&xr)[R][W], const double (&xi)[R][W], int col0, int ncol) {
 #pragma unroll
@@ -114,8 +116,11 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
     }
   };
 
-  double vr[R][W], vi[R][W];
+  double vr[R][W], vi[R][W], xr[R][W], xi[R][W];
   load_rows(vr, vi, k0, nc);
+  // the sibling's columns are fetched now and stay in flight during the first
+  // half (masked when first used, so nothing waits on them before)
+  if (ZLEAF_SIBLING(R) && n2 > 0) load_rows(xr, xi, k0 + nc, n2, false);
 
   int first_zero = 0;
   // one column step: register column jj of block (xr, xi), panel column off + jj
@@ -234,8 +239,13 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
 
   if (ZLEAF_SIBLING(R) && n2 > 0) {
     const int cs = k0 + nc;
-    double xr[R][W], xi[R][W];
-    load_rows(xr, xi, cs, n2);
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        xr[s][c] = c < n2 ? xr[s][c] : 0.0;
+        xi[s][c] = c < n2 ? xi[s][c] : 0.0;
+      }
 #pragma unroll
     for (int s = 0; s < R; ++s)
       if (pos[s] >= 0 && pos[s] < nc) {
