@@ -11,7 +11,8 @@
 // (trmm-like products), the symmetric rank-k updates (lower-only), and the
 // plain products B*Y and -Y*C^{-1}.
 //
-// Tiling: 256 threads = 4 wave64s, block tile BM x BN, k-step 16.  Each wave
+// Tiling: 256 threads = 4 wave64s, block tile BM x BN, k-step 16 (128 x 128)
+// or 32 (smaller tiles).  Each wave
 // owns a (BM/WM) x (BN/WN) sub-tile built from 16x16 v_mfma_f64_16x16x4f64
 // tiles.  Operand tiles are staged through a double-buffered LDS ring in the
 // same orientation as in HBM (the fragment read indexing applies op), so a
@@ -54,9 +55,18 @@ __device__ __forceinline__ double tri_mask(double v, int tri, int r, int c) {
 
 constexpr int TILE_GROUP = 8;
 
-template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
-  constexpr int BK = 16;
+// LDS of the double-buffered operand tiles; two workgroups per CU when they fit
+constexpr int gemm_lds_bytes(int BM, int BN, int BK, bool TA, bool TB) {
+  return 2 * 8 * ((TA ? BK * (BM + 16) : BM * (BK + 2)) + (TB ? BN * (BK + 2) : BK * (BN + 16)));
+}
+constexpr int gemm_min_blocks(int BM, int BN, int BK, bool TA, bool TB) {
+  return 2 * gemm_lds_bytes(BM, BN, BK, TA, TB) <= 160 * 1024 ? 2 : 1;
+}
+
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK>
+__global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_gemm_f64(GemmF64Params g) {
+  constexpr int KP = BK / 2;       // 16-byte pairs per row of a row-band tile
+  constexpr int RP = 256 / KP;     // rows of a row-band tile per pass
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
   static_assert(WM * WN == 4, "four waves");
@@ -71,6 +81,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   // pairs per thread per tile
   constexpr int A_P = BM * BK / 512;
   constexpr int B_P = BN * BK / 512;
+  static_assert(BK == 16 || BK == 32, "k-step");
   __shared__ __attribute__((aligned(16))) double smem[2 * (A_SZ + B_SZ)];
 
   const int tiles = g.tilesM * g.tilesN;
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   if (!TA) {
 #pragma unroll
     for (int p = 0; p < A_P; ++p) {
-      const int gi = bm0 + tid / 8 + 32 * p;
+      const int gi = bm0 + tid / KP + RP * p;
       aRowOk[p] = gi < M;
       const int pr = gi < M ? (rA ? rA[gi] : gi) : 0;
       aRow[p] = Ap + (long long)pr * g.A.ld;
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   if (TB) {
 #pragma unroll
     for (int p = 0; p < B_P; ++p) {
-      const int gj = bn0 + tid / 8 + 32 * p;
+      const int gj = bn0 + tid / KP + RP * p;
       bRowOk[p] = gj < N;
       const int pr = gj < N ? (rB ? rB[gj] : gj) : 0;
       bRow[p] = Bp + (long long)pr * g.B.ld;
@@ -176,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
   };
   auto load_tiles = [&](int kt) {
     if (!TA) {
-      const int gk = kt + (tid & 7) * 2;
+      const int gk = kt + (tid % KP) * 2;
 #pragma unroll
       for (int p = 0; p < A_P; ++p) ld_pair(aRow[p], gk, kend, ra[p][0], ra[p][1]);
     } else {
@@ -197,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
         ld_pair(Bp + (long long)(rB ? ixb[p] : gk) * g.B.ld, gj, N, rb[p][0], rb[p][1]);
       }
     } else {
-      const int gk = kt + (tid & 7) * 2;
+      const int gk = kt + (tid % KP) * 2;
 #pragma unroll
       for (int p = 0; p < B_P; ++p) ld_pair(bRow[p], gk, kend, rb[p][0], rb[p][1]);
     }
@@ -212,11 +223,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
       int off, gi, gk, di, dk;
       bool ok;
       if (!TA) {
-        gi = bm0 + tid / 8 + 32 * p;
-        gk = kt + (tid & 7) * 2;
+        gi = bm0 + tid / KP + RP * p;
+        gk = kt + (tid % KP) * 2;
         di = 0; dk = 1;
         ok = aRowOk[p];
-        off = (tid / 8 + 32 * p) * A_LD + (tid & 7) * 2;
+        off = (tid / KP + RP * p) * A_LD + (tid % KP) * 2;
       } else {
         constexpr int TPR = BM / 2, RPP = 256 / TPR;
         gi = bm0 + (tid % TPR) * 2;
@@ -238,11 +249,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmF64Params g) {
       int off, gj, gk, dj, dk;
       bool ok;
       if (TB) {
-        gj = bn0 + tid / 8 + 32 * p;
-        gk = kt + (tid & 7) * 2;
+        gj = bn0 + tid / KP + RP * p;
+        gk = kt + (tid % KP) * 2;
         dj = 0; dk = 1;
         ok = bRowOk[p];
-        off = (tid / 8 + 32 * p) * B_LD + (tid & 7) * 2;
+        off = (tid / KP + RP * p) * B_LD + (tid % KP) * 2;
       } else {
         constexpr int TPR = BN / 2, RPP = 256 / TPR;
         gj = bn0 + (tid % TPR) * 2;
@@ -354,10 +365,14 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
   p.tilesN = ceil_div(p.N, BN);
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
+  // the big tile keeps a 16-deep k-step (two workgroups per CU fit in LDS);
+  // the smaller tiles, used for latency-bound products, take 32 (half as
+  // many dependent k-steps)
+  constexpr int BK = (BM * BN >= 128 * 128) ? 16 : 32;
   if (p.vecA && p.vecB)
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 

@@ -52,9 +52,15 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
-  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous bands of tiles
+  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous ranges of tile indices
   if (t >= tiles) return;
-  const int bm0 = (t / g.tilesN) * BM, bn0 = (t % g.tilesN) * BN;
+  // tile indices run through groups of eight tile-rows column by column
+  const int gsz = 8 * g.tilesN;
+  const int grp = t / gsz;
+  const int gh = min(8, g.tilesM - grp * 8);
+  const int wt = t - grp * gsz;
+  const int bm0 = (grp * 8 + wt % gh) * BM;
+  const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
   const int z = blockIdx.z;
   const TS* Ap = g.A + z * g.sA;
