@@ -2,12 +2,13 @@
 //
 // Recursive: factor A11, L21 = A21 L11^{-T} (right triangular solve), lower
 // half of A22 -= L21 L21^T (one GEMM writing only the lower triangle), factor
-// A22.  The base case keeps a diagonal block of order <= 64 in LDS and runs
-// the right-looking algorithm there in FP64 (square root and pivot test on
-// the diagonal).  The first non-positive (or NaN) pivot stops the
-// factorization and is recorded in *info (1-based).
+// A22.  The base case factors a diagonal block of order <= 64 held in the
+// registers of one workgroup (square root and pivot test on the diagonal in
+// FP64).  The first non-positive (or NaN) pivot stops the factorization and
+// is recorded in *info (1-based).
 #include "common.hpp"
 #include "internal.hpp"
+#include "tri_dev.hpp"
 
 namespace frob {
 
@@ -15,43 +16,89 @@ namespace {
 
 constexpr int CB = 64;
 
+// Base case, order n <= 64, right-looking with the matrix in registers:
+// thread (ti, tj) of a 16 x 16 grid owns the 4 x 4 block at rows 4 ti,
+// columns 4 tj (blocks above the diagonal stay idle).  Per column j every
+// thread reads column j (as updated so far) from a parity-double-buffered
+// LDS copy, forms L(:, j) with the reciprocal of the pivot's square root
+// (scaling as LAPACK's potf2 does), updates its block, and the owners of
+// column j + 1 publish it: one barrier per column.
 __global__ __launch_bounds__(256) void k_potrf_small_f64(double* a, int lda, int n, int k0, int* info) {
-  __shared__ double S[CB][CB + 1];
-  __shared__ int s_bad;
+  __shared__ double colbuf[2][CB];
   const int tid = threadIdx.x;
-  if (*info != 0) return;  // an earlier block already failed
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e / CB, k = e % CB;
-    S[i][k] = (i < n && k <= i) ? a[(long long)i * lda + k] : 0.0;
+  if (*info != 0) return;  // an earlier block already failed (uniform)
+  const int ti = tid >> 4, tj = tid & 15;
+  const bool low = ti >= tj;
+  double blk[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * ti + r, k = 4 * tj + c;
+      const bool in = i < n && k <= i;
+      blk[r][c] = in ? a[(long long)min(i, n - 1) * lda + min(k, n - 1)] : 0.0;
+    }
+  if (tj == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) colbuf[0][4 * ti + r] = blk[r][0];
   }
-  if (tid == 0) s_bad = 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double d = S[j][j];
-      if (!(d > 0.0)) s_bad = j + 1;
-      else S[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const double ljj = S[j][j];
-    for (int i = j + 1 + tid; i < n; i += 256) S[i][j] = S[i][j] / ljj;
-    __syncthreads();
-    const int rem = n - j - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = j + 1 + e / rem, k = j + 1 + e % rem;
-      if (k <= i) S[i][k] -= S[i][j] * S[k][j];
-    }
-    __syncthreads();
+  int bad = 0;
+  for (int jb = 0; jb < CB / 4 && !bad; ++jb) {
+    StaticFor<0, 4>::run([&](auto jcc) {
+      constexpr int jc = decltype(jcc)::value;
+      const int j = 4 * jb + jc;
+      if (bad || j >= n) return;  // uniform
+      const int par = j & 1;
+      const double djj = colbuf[par][j];
+      if (!(djj > 0.0)) {   // uniform: every thread read the same value
+        bad = j + 1;
+        return;
+      }
+      const double d = sqrt(djj), rd = 1.0 / d;
+      double li[4], lk[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * ti + r;
+        li[r] = i > j ? colbuf[par][i] * rd : (i == j ? d : 0.0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = 4 * tj + c;
+        lk[c] = k > j ? colbuf[par][k] * rd : 0.0;
+      }
+      if (low) {
+        if (tj == jb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * ti + r >= j) blk[r][jc] = li[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) blk[r][c] = fma(-li[r], lk[c], blk[r][c]);
+      }
+      // publish column j + 1 (its updates from columns <= j are complete)
+      constexpr int nc = (jc + 1) & 3;
+      const int jn = j + 1;
+      if (tj == jn / 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) colbuf[par ^ 1][4 * ti + r] = blk[r][nc];
+      }
+      __syncthreads();
+    });
   }
-  if (s_bad) {
-    if (tid == 0) *info = k0 + s_bad;
+  if (bad) {
+    if (tid == 0) *info = k0 + bad;
     return;
   }
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e / CB, k = e % CB;
-    if (i < n && k <= i) a[(long long)i * lda + k] = S[i][k];
-  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * ti + r, k = 4 * tj + c;
+      if (i < n && k <= i) a[(long long)i * lda + k] = blk[r][c];
+    }
 }
 
 void potrf_rec(hipStream_t s, double* a, int lda, int n, int k0, int* info, double* work) {

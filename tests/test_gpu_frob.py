@@ -217,7 +217,9 @@ def test_refinement_without_closing_residual(h):
     A, B = inputs.general(256, 91)
     X1r, X1i, res1 = gpu_general(h, A, B, refine=1, refine_tol=1e-300)
     X2r, X2i, res2 = gpu_general(h, A, B, refine=1, refine_tol=1e-300, final_resid=False)
-    assert res2["refine_steps"] == 1 and np.isnan(res2["resid"]) and res2["resid0"] == res1["resid0"]
+    # the norm is summed with atomics in no fixed order: equal up to rounding
+    assert res2["refine_steps"] == 1 and np.isnan(res2["resid"])
+    assert abs(res2["resid0"] - res1["resid0"]) <= 1e-12 * res1["resid0"]
     assert np.array_equal(X1r, X2r) and np.array_equal(X1i, X2i)
 
 
