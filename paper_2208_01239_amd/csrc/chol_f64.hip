@@ -55,17 +55,24 @@ __global__ __launch_bounds__(256) void k_potrf_small_f64(double* a, int lda, int
         bad = j + 1;
         return;
       }
+      // the column's entries are read unconditionally (one LDS round trip),
+      // then selected
+      double ci[4], ck[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ci[r] = colbuf[par][4 * ti + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ck[c] = colbuf[par][4 * tj + c];
       const double d = sqrt(djj), rd = 1.0 / d;
       double li[4], lk[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * ti + r;
-        li[r] = i > j ? colbuf[par][i] * rd : (i == j ? d : 0.0);
+        li[r] = i > j ? ci[r] * rd : (i == j ? d : 0.0);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int k = 4 * tj + c;
-        lk[c] = k > j ? colbuf[par][k] * rd : 0.0;
+        lk[c] = k > j ? ck[c] * rd : 0.0;
       }
       if (low) {
         if (tj == jb) {
