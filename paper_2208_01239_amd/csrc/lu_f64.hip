@@ -194,8 +194,11 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
       s_ck[par][wv] = INT_MAX;
     }
     __syncthreads();
-    const double sv = lane < NW ? s_cv[par][lane] : -2.0;
-    const int sk = lane < NW ? s_ck[par][lane] : INT_MAX;
+    // (read unconditionally, then selected: no divergent branch around the LDS reads)
+    const double sv0 = s_cv[par][lane & (NW - 1)];
+    const int sk0 = s_ck[par][lane & (NW - 1)];
+    const double sv = lane < NW ? sv0 : -2.0;
+    const int sk = lane < NW ? sk0 : INT_MAX;
     const int sf = __float_as_int((float)sv);
     const int gmf = __builtin_amdgcn_readlane(row_max_key(sf), 15);
     int p;
@@ -270,7 +273,9 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
       // U12 = L11^{-1} A12, column t, by substitution in registers
       double u[W];
 #pragma unroll
-      for (int i = 0; i < W; ++i) u[i] = i < nc ? s_u[i][t] : 0.0;
+      for (int i = 0; i < W; ++i) u[i] = s_u[i][t];
+#pragma unroll
+      for (int i = 0; i < W; ++i) u[i] = i < nc ? u[i] : 0.0;
       StaticFor<1, W>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         if (i >= nc) return;  // uniform
@@ -303,7 +308,10 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
       const bool top = pos[s] >= 0 && pos[s] < nc;
       const int pi = top ? pos[s] : 0;
 #pragma unroll
-      for (int c = 0; c < W; ++c) x[s][c] = top ? s_u[pi][c] : x[s][c];
+      for (int c = 0; c < W; ++c) {
+        const double uv = s_u[pi][c];
+        x[s][c] = top ? uv : x[s][c];
+      }
     }
     // ---- factor the sibling's columns too (panel columns nc .. nc + n2) ----
     StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(x, jc, nc, n2); });

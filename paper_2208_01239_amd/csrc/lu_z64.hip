@@ -180,8 +180,11 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
       s_ck[par][wv] = INT_MAX;
     }
     __syncthreads();
-    const double sv = lane < NW ? s_cv[par][lane] : -2.0;
-    const int sk = lane < NW ? s_ck[par][lane] : INT_MAX;
+    // (read unconditionally, then selected: no divergent branch around the LDS reads)
+    const double sv0 = s_cv[par][lane & (NW - 1)];
+    const int sk0 = s_ck[par][lane & (NW - 1)];
+    const double sv = lane < NW ? sv0 : -2.0;
+    const int sk = lane < NW ? sk0 : INT_MAX;
     const int sf = __float_as_int((float)sv);
     const int gmf = __builtin_amdgcn_readlane(row_max_key(sf), 15);
     int p;
@@ -264,8 +267,9 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
       double ur[W], ui[W];
 #pragma unroll
       for (int i = 0; i < W; ++i) {
-        ur[i] = i < nc ? s_ur[i][t] : 0.0;
-        ui[i] = i < nc ? s_ui[i][t] : 0.0;
+        const double vr = s_ur[i][t], vi = s_ui[i][t];
+        ur[i] = i < nc ? vr : 0.0;
+        ui[i] = i < nc ? vi : 0.0;
       }
       StaticFor<1, W>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -315,8 +319,9 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
       const int pi = top ? pos[s] : 0;
 #pragma unroll
       for (int c = 0; c < W; ++c) {
-        xr[s][c] = top ? s_ur[pi][c] : xr[s][c];
-        xi[s][c] = top ? s_ui[pi][c] : xi[s][c];
+        const double uvr = s_ur[pi][c], uvi = s_ui[pi][c];
+        xr[s][c] = top ? uvr : xr[s][c];
+        xi[s][c] = top ? uvi : xi[s][c];
       }
     }
     StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(xr, xi, jc, nc, n2); });
