@@ -67,7 +67,7 @@ frob_status_t frob_cinv_lu(frob_handle_t h, int n, const double* Mr, const doubl
     // step 1: X = P^T L U
     copy_f64(s, n, n, Mr, ldm, nullptr, Fr, n);
     copy_f64(s, n, n, Mi, ldm, nullptr, Fi, n);
-    getrf_z64(s, n, Fr, Fi, n, perm, h->dinfo, work);
+    getrf_z64(s, n, Fr, Fi, n, perm, h->dinfo, work, lookahead(h));
     ZOp LU{Fr, Fi, n, perm};
     ZOut W{Wr, Wi, n, nullptr, nullptr};
     if (form == 0) {

@@ -50,6 +50,16 @@ void* ws_reserve(frob_handle* h, size_t bytes) {
   return h->ws;
 }
 
+const LookAhead* lookahead(frob_handle* h) {
+  if (!h) return nullptr;
+  if (!h->la.s1) {
+    // default priority (the same as every other stream the library uses)
+    FROB_HIP(hipStreamCreateWithFlags(&h->la.s1, hipStreamNonBlocking));
+    for (auto& e : h->la.ev) FROB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  return &h->la;
+}
+
 size_t solver_work_elems(int n) {
   size_t w = trsm_work_elems(n);
   w = std::max(w, getrf_work_elems(n));
@@ -173,7 +183,7 @@ void frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double*
   const int ld = w.ld;
   // step 1: P1 A = L1 U1
   copy_f64(s, n, n, A, lda, nullptr, w.F, ld);
-  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0, w.tmp);
+  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0, w.tmp, lookahead(w.h));
   // step 2: Y = U1^{-1} L1^{-1} P1 B
   copy_f64(s, n, n, B, ldb, w.p1, w.Y, ld);
   DOp LU1{w.F, ld, w.p1};
@@ -188,7 +198,7 @@ void frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double*
              DOut{w.C, ld, nullptr, nullptr});
   }
   // step 4: P2 C = L2 U2   (a zero pivot here means M is singular, Lemma 2.3)
-  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1, w.tmp);
+  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1, w.tmp, lookahead(w.h));
 }
 
 void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, double* Xr, double* Xi,
@@ -261,6 +271,12 @@ frob_status_t frob_destroy(frob_handle_t h) {
   if (h->hnorm) (void)hipHostFree(h->hnorm);
   for (auto& p : h->pending) { (void)hipEventDestroy(p.e0); (void)hipEventDestroy(p.e1); }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->la.s1) {
+    (void)hipStreamSynchronize(h->la.s1);
+    for (auto e : h->la.ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(h->la.s1);
+  }
   delete h;
   return FROB_OK;
 }

@@ -6,6 +6,7 @@
 
 #include "../../include/frobinv.h"
 #include "common.hpp"
+#include "internal.hpp"
 
 // Optional per-kernel-class timing: HIP events recorded on the handle's stream
 // around selected launches, resolved after the call's final synchronization.
@@ -30,6 +31,7 @@ struct frob_handle {
   std::vector<hipEvent_t> pool;
   int batch_nb[2][2][4] = {{{16, 16, 16, 16}, {16, 16, 16, 16}}, {{16, 16, 16, 16}, {16, 16, 16, 16}}};
                                  // batched panel width [FP64/FP32][general/HPD][order class]
+  frob::LookAhead la;            // second stream and events of the look-ahead LU (created on first use)
   double prof_ms[16] = {0};
   double prof_flops[16] = {0};
   long long prof_count[16] = {0};
@@ -73,6 +75,8 @@ void prof_resolve(frob_handle* h);
 uint64_t splitmix64(uint64_t& x);
 double draw_mu(frob_handle* h);
 void* ws_reserve(frob_handle* h, size_t bytes);
+// the handle's look-ahead stream and events, created on first use (null handle: none)
+const LookAhead* lookahead(frob_handle* h);
 void read_info(frob_handle* h);
 
 // Newton-Schulz refinement X <- X + X (I - M X) with complex products done by

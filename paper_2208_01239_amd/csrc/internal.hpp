@@ -87,10 +87,24 @@ void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, double* Wre, doubl
 // logical row i of P A = L U lives in physical row perm[i].  *info (device)
 // receives the 1-based column of the first exactly-zero pivot or stays 0.
 // `work` holds getrf_work_elems(n) doubles.
+//
+// With a LookAhead (a second stream and events owned by the handle) orders
+// n >= LA_MIN are factored in panels of LA_NB columns with a look-ahead of
+// one panel: the update of the next panel's columns stays on `s`, the update
+// of the remaining columns runs on the second stream, concurrently with the
+// next panel's factorization.  The call returns with all work ordered on `s`.
+struct LookAhead {
+  hipStream_t s1 = nullptr;
+  hipEvent_t ev[8] = {};
+};
+constexpr int LA_NB = 256;
+constexpr int LA_MIN = 4 * LA_NB;
 size_t getrf_work_elems(int n);
-void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work);
+void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work,
+               const LookAhead* la = nullptr);
 size_t getrf_z_work_elems(int n);
-void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work);
+void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work,
+               const LookAhead* la = nullptr);
 // Cholesky A = L L^T (lower, in place in the lower triangle of a; the strict
 // upper triangle is not referenced).  *info receives the 1-based index of the
 // first non-positive pivot.

@@ -505,17 +505,78 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
 }
 
+// Panels of LA_NB columns with a look-ahead of one panel (see internal.hpp).
+// Row interchanges only permute `perm` among the trailing positions, so a
+// trailing update may run while a later panel pivots, provided it addresses
+// its rows through a copy of perm taken when its panel was finished (the set
+// of trailing physical rows is the same; their order does not matter to a
+// row-wise update).  Ordering:
+//   s0: panel j -> snapshot -> event F_j -> [wait R_{j-1}] update of panel
+//       j+1's columns -> panel j+1 ...
+//   s1: [wait F_j] update of the columns right of panel j+1 -> event R_j
+// The update of panel j+1's columns waits for R_{j-1}, the previous update
+// of those columns; the snapshot buffer of panel j is rewritten at panel
+// j + 2, after s0 has waited for R_j.
+void getrf_lookahead(hipStream_t s0, int n, double* a, int lda, int* perm, int* info, double* work, int* cnt,
+                     const LookAhead& la) {
+  hipStream_t s1 = la.s1;
+  double* work0 = work;
+  double* work1 = work0 + trsm_work_elems(n / 2 + 8);
+  int* snap[2];
+  snap[0] = reinterpret_cast<int*>(work1 + trsm_work_elems(LA_NB));
+  snap[1] = snap[0] + n;
+  auto evF = [&](int j) { return la.ev[j & 3]; };
+  auto evR = [&](int j) { return la.ev[4 + (j & 3)]; };
+  // columns c .. c + w - 1 of the trailing matrix, updated with panel k0 .. k0 + nb
+  auto update = [&](hipStream_t st, int k0, int nb, int c, int w, const int* trows, double* wk) {
+    DOp L11{a + k0, lda, perm + k0};
+    DOut A12{a + c, lda, perm + k0, nullptr};
+    trsm_f64(st, false, TRI_LOWER_UNIT, false, nb, w, L11, A12, wk);
+    DOp L21{a + k0, lda, trows};
+    DOp U12{a + c, lda, perm + k0};
+    DOut A22{a + c, lda, trows, nullptr};
+    gemm_f64(st, false, false, n - (k0 + nb), w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
+  };
+  const int np = ceil_div(n, LA_NB);
+  int last_r = -1;
+  for (int j = 0; j < np; ++j) {
+    const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
+    getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt);
+    const int r0 = k0 + nb;
+    if (r0 >= n) break;
+    int* sn = snap[j & 1];
+    FROB_HIP(hipMemcpyAsync(sn, perm + r0, sizeof(int) * (n - r0), hipMemcpyDeviceToDevice, s0));
+    FROB_HIP(hipEventRecord(evF(j), s0));
+    const int c1 = r0, w1 = min(LA_NB, n - c1);
+    if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
+    update(s0, k0, nb, c1, w1, perm + r0, work0);
+    const int c2 = c1 + w1, w2 = n - c2;
+    if (w2 > 0) {
+      FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
+      update(s1, k0, nb, c2, w2, sn, work1);
+      FROB_HIP(hipEventRecord(evR(j), s1));
+      last_r = j;
+    }
+  }
+  if (last_r >= 0) FROB_HIP(hipStreamWaitEvent(s0, evR(last_r), 0));
+}
+
 }  // namespace
 
-size_t getrf_work_elems(int n) { return trsm_work_elems(n / 2 + 8) + 64; }
+size_t getrf_work_elems(int n) {
+  // node counter, recursion and look-ahead scratch of s0, solve scratch of the
+  // second stream, two snapshots of n row indices
+  return 64 + trsm_work_elems(n / 2 + 8) + trsm_work_elems(LA_NB) + (size_t)n;
+}
 
-void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work) {
+void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work, const LookAhead* la) {
   if (n <= 0) return;
   iota_i32(s, n, perm);
   // the node kernels' workgroup counter lives in the first 64 doubles of work
   int* cnt = reinterpret_cast<int*>(work);
   fill_i32(s, 1, 0, cnt);
-  getrf_rec(s, a, lda, perm, 0, n, n, info, work + 64, cnt);
+  if (la && la->s1 && n >= LA_MIN) getrf_lookahead(s, n, a, lda, perm, info, work + 64, cnt, *la);
+  else getrf_rec(s, a, lda, perm, 0, n, n, info, work + 64, cnt);
 }
 
 }  // namespace frob

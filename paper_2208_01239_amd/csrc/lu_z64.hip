@@ -580,17 +580,67 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt);
 }
 
+// Panels of LA_NB columns with a look-ahead of one panel; the ordering and
+// the snapshot of the trailing rows' indices are those of the real version
+// (getrf_lookahead in lu_f64.hip).
+void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, int* perm, int* info, double* work,
+                      int* cnt, const LookAhead& la) {
+  hipStream_t s1 = la.s1;
+  double* work0 = work;
+  double* work1 = work0 + trsm_z_work_elems(n / 2 + 8);
+  int* snap[2];
+  snap[0] = reinterpret_cast<int*>(work1 + trsm_z_work_elems(LA_NB));
+  snap[1] = snap[0] + n;
+  auto evF = [&](int j) { return la.ev[j & 3]; };
+  auto evR = [&](int j) { return la.ev[4 + (j & 3)]; };
+  auto update = [&](hipStream_t st, int k0, int nb, int c, int w, const int* trows, double* wk) {
+    ZOp L11{ar + k0, ai + k0, lda, perm + k0};
+    ZOut A12{ar + c, ai + c, lda, perm + k0, nullptr};
+    trsm_z64(st, false, TRI_LOWER_UNIT, OP_N, nb, w, L11, A12, wk);
+    ZOp L21{ar + k0, ai + k0, lda, trows};
+    ZOp U12{ar + c, ai + c, lda, perm + k0};
+    ZOut A22{ar + c, ai + c, lda, trows, nullptr};
+    gemm_z64(st, OP_N, OP_N, n - (k0 + nb), w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
+  };
+  const int np = ceil_div(n, LA_NB);
+  int last_r = -1;
+  for (int j = 0; j < np; ++j) {
+    const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
+    zgetrf_rec(s0, ar, ai, lda, perm, k0, n, nb, info, work0, cnt);
+    const int r0 = k0 + nb;
+    if (r0 >= n) break;
+    int* sn = snap[j & 1];
+    FROB_HIP(hipMemcpyAsync(sn, perm + r0, sizeof(int) * (n - r0), hipMemcpyDeviceToDevice, s0));
+    FROB_HIP(hipEventRecord(evF(j), s0));
+    const int c1 = r0, w1 = min(LA_NB, n - c1);
+    if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
+    update(s0, k0, nb, c1, w1, perm + r0, work0);
+    const int c2 = c1 + w1, w2 = n - c2;
+    if (w2 > 0) {
+      FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
+      update(s1, k0, nb, c2, w2, sn, work1);
+      FROB_HIP(hipEventRecord(evR(j), s1));
+      last_r = j;
+    }
+  }
+  if (last_r >= 0) FROB_HIP(hipStreamWaitEvent(s0, evR(last_r), 0));
+}
+
 }  // namespace
 
-size_t getrf_z_work_elems(int n) { return trsm_z_work_elems(n / 2 + 8) + 64; }
+size_t getrf_z_work_elems(int n) {
+  return 64 + trsm_z_work_elems(n / 2 + 8) + trsm_z_work_elems(LA_NB) + (size_t)n;
+}
 
-void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work) {
+void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work,
+               const LookAhead* la) {
   if (n <= 0) return;
   iota_i32(s, n, perm);
   // the node kernels' workgroup counter lives in the first 64 doubles of work
   int* cnt = reinterpret_cast<int*>(work);
   fill_i32(s, 1, 0, cnt);
-  zgetrf_rec(s, re, im, lda, perm, 0, n, n, info, work + 64, cnt);
+  if (la && la->s1 && n >= LA_MIN) zgetrf_lookahead(s, n, re, im, lda, perm, info, work + 64, cnt, *la);
+  else zgetrf_rec(s, re, im, lda, perm, 0, n, n, info, work + 64, cnt);
 }
 
 }  // namespace frob

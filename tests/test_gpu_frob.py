@@ -360,6 +360,26 @@ def test_full_size_complex_lu_n4096(h):
         assert e <= TOL
 
 
+@pytest.mark.parametrize("n", [1024, 1300])
+def test_lookahead_lu_orders(h, n):
+    """Orders at which the LU runs in 256-column panels with a look-ahead on a
+    second stream (a full panel count and a ragged last panel): Frobenius
+    inversion and the complex-LU baseline against the oracle's inverse."""
+    A, B = inputs.general(n, 77)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    C = A + B @ np.linalg.solve(A, B)
+    tol = max(TOL, 16 * np.finfo(float).eps / 2 * np.linalg.cond(C))
+    Xr, Xi, _ = gpu_general(h, A, B)
+    e = relF(Xr, Xi, Rr, Ri)
+    print(f"n={n} frobenius relF={e:.2e} tol={tol:.1e}")
+    assert e <= tol
+    Zr, Zi, _ = gpu_cinv(h, __import__("paper_2208_01239_amd").frob_cinv_lu, A, B, 1)
+    ez = relF(Zr, Zi, Rr, Ri)
+    print(f"n={n} complex LU relF={ez:.2e}")
+    assert ez <= max(TOL, 16 * np.finfo(float).eps / 2 * np.linalg.cond(A + 1j * B))
+
+
 def _backward_error_cols(A, B, xr, xi, cols):
     """||M x_j - e_j|| / (||M||_F ||x_j||) over sampled columns, in numpy FP64."""
     n = A.shape[0]
