@@ -97,8 +97,8 @@ struct LookAhead {
   hipStream_t s1 = nullptr;
   hipEvent_t ev[8] = {};
 };
-constexpr int LA_NB = 256;
-constexpr int LA_MIN = 4 * LA_NB;
+constexpr int LA_NB = 64;      // of 64, 128, 256 and 512, the fastest at n = 4096
+constexpr int LA_MIN = 1024;
 size_t getrf_work_elems(int n);
 void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work,
                const LookAhead* la = nullptr);

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
 }
 
 // widest leaf for a panel with mm rows (R * W <= 32 doubles per thread keeps
-// the panel, the pivot row and the I/O staging within 256 VGPRs)
+// the panel, the prefetched sibling block and the pivot row within 256 VGPRs)
 inline int leaf_width(int mm) {
   const int R = ceil_div(mm, LEAF_NT);
   if (R <= 1) return 32;

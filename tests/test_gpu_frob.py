@@ -362,8 +362,8 @@ def test_full_size_complex_lu_n4096(h):
 
 @pytest.mark.parametrize("n", [1024, 1300])
 def test_lookahead_lu_orders(h, n):
-    """Orders at which the LU runs in 256-column panels with a look-ahead on a
-    second stream (a full panel count and a ragged last panel): Frobenius
+    """Orders at which the LU runs in panels with a look-ahead on a second
+    stream (a whole number of panels and a ragged last panel): Frobenius
     inversion and the complex-LU baseline against the oracle's inverse."""
     A, B = inputs.general(n, 77)
     Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
