@@ -614,7 +614,9 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
     FROB_HIP(hipEventRecord(evF(j), s0));
     const int c1 = r0, w1 = min(LA_NB, n - c1);
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
-    update(s0, k0, nb, c1, w1, perm + r0, work0);
+    // the next panel's update is a recursion node when it is narrow enough
+    if (nb <= ZNODE_MAX && w1 <= ZNODE_MAX) zlaunch_node(s0, ar, ai, lda, perm, k0, n - k0, nb, w1, cnt);
+    else update(s0, k0, nb, c1, w1, perm + r0, work0);
     const int c2 = c1 + w1, w2 = n - c2;
     if (w2 > 0) {
       FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
