@@ -87,6 +87,13 @@ typedef struct {
  * applied), do not form the residual of the returned inverse (result.resid is
  * then NaN).  Saves the three n x n x n products that only measure it. */
 #define FROB_REFINE_SKIP_FINAL_RESID 1
+/* refine_flags: with FP64 factorizations (opts.prec = FROB_PREC_F64), form the
+ * correction X R of each step with FP32 matrix-core operands and FP32
+ * accumulation; the residual R = I - M X stays FP64.  The correction is as
+ * small as the error of X, so its FP32 rounding adds about
+ * 6e-8 kappa(M) times that error: a step still contracts while
+ * kappa(M) << 1e7.  Ignored when opts.prec is not FROB_PREC_F64. */
+#define FROB_REFINE_F32_CORRECTION 2
 
 typedef struct {
   int info;             /* 1-based column of the failing pivot, 0 if none                                   */

@@ -14,7 +14,8 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_SKIP_FINAL_RESID,  # noqa: F401
+from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32_CORRECTION,  # noqa: F401
+                   FROB_REFINE_SKIP_FINAL_RESID,
                    FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNoConvergenceError, FrobNotHPDError, FrobSingularError,
                    frob_opts_t, frob_result_t)
 
@@ -22,7 +23,7 @@ __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_cin
            "frob_inv_adjoint", "frob_inv_batched", "frob_batched_tune", "BatchedPlan",
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
            "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
-           "FROB_REFINE_SKIP_FINAL_RESID", "load_library"]
+           "FROB_REFINE_SKIP_FINAL_RESID", "FROB_REFINE_F32_CORRECTION", "load_library"]
 
 
 def load_library():
@@ -93,7 +94,7 @@ def _mat(t, n_rows, n_cols, name):
     return ctypes.c_void_p(t.data_ptr()), int(t.stride(0))
 
 
-def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True):
+def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32_correction=False):
     o = frob_opts_t()
     _lib.load().frob_default_opts(ctypes.byref(o))
     o.shift = int(shift)
@@ -102,7 +103,8 @@ def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True):
     o.refine = int(refine)
     o.prec = int(prec)
     o.refine_tol = float(refine_tol)
-    o.refine_flags = 0 if final_resid else FROB_REFINE_SKIP_FINAL_RESID
+    o.refine_flags = (0 if final_resid else FROB_REFINE_SKIP_FINAL_RESID) | \
+        (FROB_REFINE_F32_CORRECTION if f32_correction else 0)
     return o
 
 
@@ -112,13 +114,15 @@ def _empty_like_sq(A, n):
 
 
 def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0,
-                     prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True):
+                     prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True, f32_correction=False):
     """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting).
 
     prec: operand precision of the matrix-core products (FROB_PREC_F64/F32/BF16);
     refine: maximum number of Newton-Schulz steps (residual formed in FP64);
     final_resid=False: skip the residual of the returned inverse when the step
-    limit ends refinement (result "resid" is then NaN)."""
+    limit ends refinement (result "resid" is then NaN);
+    f32_correction=True: after FP64 factorizations, form each step's
+    correction X R with FP32 matrix-core operands (the residual stays FP64)."""
     n = A.shape[0]
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
     Xi = _empty_like_sq(A, n) if Xi is None else Xi
@@ -129,14 +133,14 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
-    o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid), frob_result_t()
+    o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
     st = _lib.load().frob_inv_general(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, "frob_inv_general", r)
     return Xr, Xi, r.as_dict()
 
 
 def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_F64, refine_tol=0.0,
-                 final_resid=True):
+                 final_resid=True, f32_correction=False):
     """(A + iB)^{-1} for Hermitian positive definite A + iB (Algorithm 7)."""
     n = A.shape[0]
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
@@ -148,7 +152,7 @@ def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
-    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid), frob_result_t()
+    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
     st = _lib.load().frob_inv_hpd(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, "frob_inv_hpd", r)
     return Xr, Xi, r.as_dict()

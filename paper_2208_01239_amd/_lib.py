@@ -30,6 +30,7 @@ FROB_PREC_F64 = 0
 FROB_PREC_F32 = 1
 FROB_PREC_BF16 = 2
 FROB_REFINE_SKIP_FINAL_RESID = 1
+FROB_REFINE_F32_CORRECTION = 2
 
 
 class frob_opts_t(ctypes.Structure):

@@ -3,7 +3,8 @@
 //   R = I - M X,   X <- X + X R,     so that I - M X_new = (I - M X)^2.
 //
 // The residual and its norm are formed in FP64; the correction X R may use a
-// lower operand precision (its error is relative to the already small R).
+// lower operand precision (its error is relative to the already small R):
+// that of the factorizations, or FP32 after FP64 factorizations when asked.
 // Refinement stops when ||R||_F / sqrt(n) reaches the tolerance, when it no
 // longer halves (the FP64 rounding floor, about u kappa(M)), or after the
 // step limit (optionally without forming the residual of the last iterate);
@@ -61,6 +62,7 @@ frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const d
   double* T2 = c.take<double>(nn);
   if (!(tol > 0.0)) tol = 1e-14;
   const double rn = std::sqrt((double)n);
+  const int cprec = (prec == LP_NONE && (flags & FROB_REFINE_F32_CORRECTION)) ? LP_F32 : prec;
   double prev = 0.0;
   int steps = 0;
   frob_status_t st = FROB_OK;
@@ -87,7 +89,7 @@ frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const d
     if (k == max_steps) break;
     // X <- X + X R
     {
-      LowPrecScope lp(prec);
+      LowPrecScope lp(cprec);
       gauss3m(s, n, Xr, ldx, Xi, Rr, n, Ri, Ur, Ui, n, T1, T2);
     }
     axpby_f64(s, n, n, 1.0, Ur, n, 1.0, Xr, ldx);

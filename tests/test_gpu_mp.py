@@ -62,6 +62,32 @@ def test_mixed_precision_refined_to_fp64(h, kind, prec, kappa):
     assert res["refine_steps"] >= 1 and res["resid"] < res["resid0"]
 
 
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_f32_correction_after_fp64_factorization(h, kappa):
+    """FP64 factorizations, FP64 residual, FP32 correction X R: the correction
+    is as small as the error of X, so its FP32 rounding costs only a factor of
+    about u_32 kappa(M) per step, against (I - M X)^2 for the FP64 step."""
+    A, B, Rr, Ri = _case("general", kappa)
+    X0r, X0i, _ = _inv(h, "general", A, B)
+    e0 = relF(X0r, X0i, Rr, Ri)
+    X1r, X1i, r64 = _inv(h, "general", A, B, refine=1, refine_tol=1e-300)
+    e64 = relF(X1r, X1i, Rr, Ri)
+    X2r, X2i, r32 = _inv(h, "general", A, B, refine=1, refine_tol=1e-300, f32_correction=True)
+    e32 = relF(X2r, X2i, Rr, Ri)
+    X8r, X8i, r8 = _inv(h, "general", A, B, refine=8, f32_correction=True)
+    e8 = relF(X8r, X8i, Rr, Ri)
+    print(f"kappa {kappa:.0e}: unrefined {e0:.2e}, one FP64 step {e64:.2e}, one FP32-correction step {e32:.2e}, "
+          f"{r8['refine_steps']} FP32-correction steps {e8:.2e}")
+    # the same FP64 factorizations and residual before the first step
+    assert abs(r32["resid0"] - r64["resid0"]) <= 1e-12 * r64["resid0"]
+    assert r32["refine_steps"] == 1
+    # the flag is honoured: the correction was rounded differently
+    assert not np.array_equal(X1r, X2r)
+    # one step gains at least u_32 kappa(M) (6e-8 kappa), with a margin of 20
+    assert e32 <= max(20 * 6e-8 * kappa * e0, 10 * e64, 1e-13)
+    assert e8 <= TOL and r8["resid"] < r8["resid0"]
+
+
 def test_newton_schulz_squares_the_residual(h):
     """I - M X_{k+1} = (I - M X_k)^2, so ||R_1||_F <= ||R_0||_F^2 (up to FP64 rounding)."""
     A, B, Rr, Ri = _case("general", 1e2)
