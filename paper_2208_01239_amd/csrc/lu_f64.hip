@@ -129,10 +129,34 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   };
 
   double v[R][W], x[R][W];
-  load_rows(v, k0, nc);
-  // the sibling's columns are fetched now and stay in flight during the first
-  // half (masked when first used, so nothing waits on them before)
-  if (LEAF_SIBLING(R) && n2 > 0) load_rows(x, k0 + nc, n2, false);
+  if (LEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0) {
+    // The sibling's columns continue this thread's row segments: they are
+    // fetched now, each row's pairs right after the panel's, so both halves
+    // of a row come from the cache line its first load brought in (a row is
+    // its own line; the line fetches, not the bytes, bound this load).  They
+    // stay in flight during the first half and are masked when first used.
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const double* row = a + (long long)ph[s] * lda + k0;
+#pragma unroll
+      for (int c = 0; c < W; c += 2) {
+        const double2 y = *reinterpret_cast<const double2*>(row + c);
+        v[s][c] = y.x;
+        v[s][c + 1] = y.y;
+      }
+#pragma unroll
+      for (int c = 0; c < W; c += 2) {
+        const double2 y = *reinterpret_cast<const double2*>(row + W + min(c, n2 - 2));
+        x[s][c] = y.x;
+        x[s][c + 1] = y.y;
+      }
+    }
+  } else {
+    load_rows(v, k0, nc);
+    // the sibling's columns are fetched now and stay in flight during the
+    // first half (masked when first used, so nothing waits on them before)
+    if (LEAF_SIBLING(R) && n2 > 0) load_rows(x, k0 + nc, n2, false);
+  }
 
   // ---- factor ----
   int first_zero = 0;
