@@ -103,24 +103,59 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
     }
   };
   auto store_rows = [&](const double (&xr)[R][W], const double (&xi)[R][W], int col0, int ncol) {
+    const bool vec = W % 2 == 0 && vbase && ((col0 | ncol) & 1) == 0;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       if (pos[s] < 0) continue;
       const long long o = (long long)ph[s] * lda + col0;
+      if (vec) {
 #pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c < ncol) {
-          ar[o + c] = xr[s][c];
-          ai[o + c] = xi[s][c];
-        }
+        for (int c = 0; c + 1 < W; c += 2)
+          if (c < ncol) {
+            *reinterpret_cast<double2*>(ar + o + c) = make_double2(xr[s][c], xr[s][c + 1]);
+            *reinterpret_cast<double2*>(ai + o + c) = make_double2(xi[s][c], xi[s][c + 1]);
+          }
+      } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < ncol) {
+            ar[o + c] = xr[s][c];
+            ai[o + c] = xi[s][c];
+          }
+      }
     }
   };
 
   double vr[R][W], vi[R][W], xr[R][W], xi[R][W];
-  load_rows(vr, vi, k0, nc);
-  // the sibling's columns are fetched now and stay in flight during the first
-  // half (masked when first used, so nothing waits on them before)
-  if (ZLEAF_SIBLING(R) && n2 > 0) load_rows(xr, xi, k0 + nc, n2, false);
+  if (W % 2 == 0 && ZLEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0) {
+    // the sibling's columns continue this thread's row segments: each row's
+    // pairs are fetched right after the panel's, from the cache line the
+    // first load brought in; they stay in flight during the first half and
+    // are masked when first used
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const long long o = (long long)ph[s] * lda + k0;
+#pragma unroll
+      for (int c = 0; c + 1 < W; c += 2) {
+        const double2 yr = *reinterpret_cast<const double2*>(ar + o + c);
+        const double2 yi = *reinterpret_cast<const double2*>(ai + o + c);
+        vr[s][c] = yr.x; vr[s][c + 1] = yr.y;
+        vi[s][c] = yi.x; vi[s][c + 1] = yi.y;
+      }
+#pragma unroll
+      for (int c = 0; c + 1 < W; c += 2) {
+        const double2 yr = *reinterpret_cast<const double2*>(ar + o + W + min(c, n2 - 2));
+        const double2 yi = *reinterpret_cast<const double2*>(ai + o + W + min(c, n2 - 2));
+        xr[s][c] = yr.x; xr[s][c + 1] = yr.y;
+        xi[s][c] = yi.x; xi[s][c + 1] = yi.y;
+      }
+    }
+  } else {
+    load_rows(vr, vi, k0, nc);
+    // the sibling's columns are fetched now and stay in flight during the
+    // first half (masked when first used, so nothing waits on them before)
+    if (ZLEAF_SIBLING(R) && n2 > 0) load_rows(xr, xi, k0 + nc, n2, false);
+  }
 
   int first_zero = 0;
   // one column step: register column jj of block (xr, xi), panel column off + jj
