@@ -55,6 +55,8 @@ constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 // the fused sibling update needs a second R x W block of registers; the
 // tallest leaves (more than 16 rows per thread) leave it to a node kernel
 constexpr bool LEAF_SIBLING(int R) { return R <= 16; }
+// leaves whose panel and sibling blocks are written back together through LDS
+constexpr bool LEAF_JOINT_STORE(int W) { return W <= 8; }
 
 template <int R, int W>
 __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
@@ -66,6 +68,10 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   __shared__ __align__(16) double s_crow[2][NW][W];
   __shared__ double s_l[W][W + 1];
   __shared__ double s_u[W][W + 1];
+  // staging of the joint write-back (row pitch 2W + 2 doubles: 16-byte aligned
+  // rows, consecutive rows on different banks)
+  __shared__ __align__(16) double s_st[LEAF_JOINT_STORE(W) ? NW : 1][64][LEAF_JOINT_STORE(W) ? 2 * W + 2 : 2];
+  __shared__ int s_sph[LEAF_JOINT_STORE(W) ? NW : 1][64];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
@@ -129,7 +135,46 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   };
 
   double v[R][W], x[R][W];
-  if (LEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0) {
+  // panel and sibling block together: row segments of W + n2 columns
+  const bool joint = LEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0;
+  if (LEAF_JOINT_STORE(W) && joint) {
+    // Joint row segments read transposed: W consecutive lanes fetch one row's
+    // W + n2 contiguous columns (16 bytes each, so a load instruction touches
+    // 64 / W row segments instead of 64), staged per slot through LDS into
+    // the row-per-thread layout.  All loads are issued before the first is
+    // staged; columns past n2 are masked when first used.
+    if constexpr (LEAF_JOINT_STORE(W)) {
+      constexpr int RPI = 64 / W;
+      const int m = lane % W;
+      const int cm = k0 + min(2 * m, W + n2 - 2);
+      double y0[R][W], y1[R][W];
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const int prow = __shfl(ph[s], i * RPI + lane / W);
+          const double2 t2 = *reinterpret_cast<const double2*>(a + (long long)prow * lda + cm);
+          y0[s][i] = t2.x;
+          y1[s][i] = t2.y;
+        }
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        __builtin_amdgcn_sched_barrier(0);   // one slot at a time (register pressure)
+        __syncthreads();   // the previous slot's staged rows have been read
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+          *reinterpret_cast<double2*>(&s_st[wv][i * RPI + lane / W][2 * m]) = make_double2(y0[s][i], y1[s][i]);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < W; c += 2) {
+          const double2 p = *reinterpret_cast<const double2*>(&s_st[wv][lane][c]);
+          const double2 q = *reinterpret_cast<const double2*>(&s_st[wv][lane][W + c]);
+          v[s][c] = p.x; v[s][c + 1] = p.y;
+          x[s][c] = q.x; x[s][c + 1] = q.y;
+        }
+      }
+    }
+  } else if (joint) {
     // The sibling's columns continue this thread's row segments: they are
     // fetched now, each row's pairs right after the panel's, so both halves
     // of a row come from the cache line its first load brought in (a row is
@@ -274,7 +319,7 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
     }
   };
   StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(v, jc, 0, nc); });
-  store_rows(v, k0, nc);
+  if (!(LEAF_JOINT_STORE(W) && joint)) store_rows(v, k0, nc);
 
   if (LEAF_SIBLING(R) && n2 > 0) {
     // ---- sibling update: columns cs .. cs + n2 - 1 ----
@@ -339,7 +384,40 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
     }
     // ---- factor the sibling's columns too (panel columns nc .. nc + n2) ----
     StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(x, jc, nc, n2); });
-    store_rows(x, cs, n2);
+    if constexpr (LEAF_JOINT_STORE(W)) {
+      if (joint) {
+        // Both blocks are written back together, transposed through LDS so
+        // that W consecutive lanes write one row's W + n2 contiguous columns
+        // (16 bytes each): a store instruction then touches 64 / W row
+        // segments instead of 64, and the store rate is set by the segments
+        // touched.  Each wave stages its own 64 rows per slot s.
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          __syncthreads();   // the previous slot's staged rows have been read
+          double* rb = &s_st[wv][lane][0];
+#pragma unroll
+          for (int c = 0; c < W; c += 2) *reinterpret_cast<double2*>(rb + c) = make_double2(v[s][c], v[s][c + 1]);
+#pragma unroll
+          for (int c = 0; c < W; c += 2)
+            *reinterpret_cast<double2*>(rb + W + c) = make_double2(x[s][c], x[s][c + 1]);
+          s_sph[wv][lane] = pos[s] >= 0 ? ph[s] : -1;
+          __syncthreads();
+          constexpr int RPI = 64 / W;   // rows per store instruction
+          const int m = lane % W;       // 16-byte chunk of the row segment
+#pragma unroll
+          for (int i = 0; i < W; ++i) {
+            const int r = i * RPI + lane / W;
+            const double2 y = *reinterpret_cast<const double2*>(&s_st[wv][r][2 * m]);
+            const int prow = s_sph[wv][r];
+            if (prow >= 0 && 2 * m < W + n2) *reinterpret_cast<double2*>(a + (long long)prow * lda + k0 + 2 * m) = y;
+          }
+        }
+      } else {
+        store_rows(x, cs, n2);
+      }
+    } else {
+      store_rows(x, cs, n2);
+    }
   }
   if (t == 0 && first_zero && *info == 0) *info = first_zero;
 
