@@ -33,6 +33,8 @@ __device__ __forceinline__ zc zrecip(zc z) {
 
 // the fused sibling update needs a second R x W block of registers
 constexpr bool ZLEAF_SIBLING(int R) { return R <= 8; }
+// leaves whose panel and sibling blocks move together, transposed through LDS
+constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
 
 // One workgroup factors an mm x nc complex panel (nc <= W) held in
 // registers, thread t owning panel rows q = t + s * ZLT (s < R).  The design
@@ -54,6 +56,10 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
   __shared__ double s_crr[2][NW][W], s_cri[2][NW][W];
   __shared__ double s_lr[W][W + 1], s_li[W][W + 1];
   __shared__ double s_ur[W][W + 1], s_ui[W][W + 1];
+  // staging of the joint row segments (row pitch 2W + 2 doubles: 16-byte
+  // aligned rows, consecutive rows on different banks)
+  __shared__ __align__(16) double s_st[ZLEAF_JOINT(W) ? NW : 1][64][ZLEAF_JOINT(W) ? 2 * W + 2 : 2];
+  __shared__ int s_sph[ZLEAF_JOINT(W) ? NW : 1][64];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
@@ -127,7 +133,70 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
   };
 
   double vr[R][W], vi[R][W], xr[R][W], xi[R][W];
-  if (W % 2 == 0 && ZLEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0) {
+  // panel and sibling block together: row segments of W + n2 columns per plane
+  const bool joint = W % 2 == 0 && ZLEAF_SIBLING(R) && n2 > 0 && nc == W && vbase && ((k0 | n2) & 1) == 0;
+  // Joint segments transposed through LDS (as in the real leaf): W
+  // consecutive lanes move one row segment of a plane (16 bytes each), so an
+  // instruction touches 64 / W row segments instead of 64; the planes take
+  // turns in one staging buffer, each wave staging its own 64 rows per slot.
+  constexpr int RPI = 64 / (W > 1 ? W : 2);
+  const int m = lane % W;
+  auto stage_in = [&](const double (&y0)[W], const double (&y1)[W], double (&p)[W], double (&q)[W])
+                      __attribute__((always_inline)) {
+    __syncthreads();   // the previous contents have been read
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      *reinterpret_cast<double2*>(&s_st[wv][i * RPI + lane / W][2 * m]) = make_double2(y0[i], y1[i]);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c + 1 < W; c += 2) {
+      const double2 e = *reinterpret_cast<const double2*>(&s_st[wv][lane][c]);
+      const double2 f = *reinterpret_cast<const double2*>(&s_st[wv][lane][W + c]);
+      p[c] = e.x; p[c + 1] = e.y;
+      q[c] = f.x; q[c + 1] = f.y;
+    }
+  };
+  auto stage_out = [&](const double (&p)[W], const double (&q)[W], double* plane, int prs)
+                       __attribute__((always_inline)) {
+    __syncthreads();
+    double* rb = &s_st[wv][lane][0];
+#pragma unroll
+    for (int c = 0; c + 1 < W; c += 2) {
+      *reinterpret_cast<double2*>(rb + c) = make_double2(p[c], p[c + 1]);
+      *reinterpret_cast<double2*>(rb + W + c) = make_double2(q[c], q[c + 1]);
+    }
+    s_sph[wv][lane] = prs;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const int r = i * RPI + lane / W;
+      const double2 y = *reinterpret_cast<const double2*>(&s_st[wv][r][2 * m]);
+      const int prow = s_sph[wv][r];
+      if (prow >= 0 && 2 * m < W + n2) *reinterpret_cast<double2*>(plane + (long long)prow * lda + k0 + 2 * m) = y;
+    }
+  };
+  if (ZLEAF_JOINT(W) && joint) {
+    if constexpr (ZLEAF_JOINT(W)) {
+      const int cm = k0 + min(2 * m, W + n2 - 2);
+      double y0r[R][W], y1r[R][W], y0i[R][W], y1i[R][W];
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const long long o = (long long)__shfl(ph[s], i * RPI + lane / W) * lda + cm;
+          const double2 tr = *reinterpret_cast<const double2*>(ar + o);
+          const double2 ti = *reinterpret_cast<const double2*>(ai + o);
+          y0r[s][i] = tr.x; y1r[s][i] = tr.y;
+          y0i[s][i] = ti.x; y1i[s][i] = ti.y;
+        }
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        __builtin_amdgcn_sched_barrier(0);   // one slot at a time (register pressure)
+        stage_in(y0r[s], y1r[s], vr[s], xr[s]);
+        stage_in(y0i[s], y1i[s], vi[s], xi[s]);
+      }
+    }
+  } else if (joint) {
     // the sibling's columns continue this thread's row segments: each row's
     // pairs are fetched right after the panel's, from the cache line the
     // first load brought in; they stay in flight during the first half and
@@ -273,7 +342,7 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
     }
   };
   StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(vr, vi, jc, 0, nc); });
-  store_rows(vr, vi, k0, nc);
+  if (!(ZLEAF_JOINT(W) && joint)) store_rows(vr, vi, k0, nc);
 
   if (ZLEAF_SIBLING(R) && n2 > 0) {
     const int cs = k0 + nc;
@@ -360,7 +429,18 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
       }
     }
     StaticFor<0, W>::run([&](auto jc) __attribute__((always_inline)) { column(xr, xi, jc, nc, n2); });
-    store_rows(xr, xi, cs, n2);
+    if (ZLEAF_JOINT(W) && joint) {
+      if constexpr (ZLEAF_JOINT(W)) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const int prs = pos[s] >= 0 ? ph[s] : -1;
+          stage_out(vr[s], xr[s], ar, prs);
+          stage_out(vi[s], xi[s], ai, prs);
+        }
+      }
+    } else {
+      store_rows(xr, xi, cs, n2);
+    }
   }
   if (t == 0 && first_zero && *info == 0) *info = first_zero;
 
