@@ -228,6 +228,257 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   }
 }
 
+// FP32-operand kernel, built like the FP64 GEMM: k-step 32 through a
+// double-buffered LDS ring (one barrier per k-step), the next tile's global
+// loads (pairs along the contiguous direction, 16 or 8 bytes when aligned)
+// in flight while the current tile is multiplied, two workgroups per CU.
+// Row-band operands (A for N, B for T) sit in LDS as [rows][32 + 4] and
+// k-band operands as [32][cols + 16] floats: the fragment reads (16 rows x 4
+// k, or 4 k x 16 columns) then fall on distinct banks.
+template <typename TS, int BM, int BN, bool TA, bool TB, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_lp32(GemmLpParams<TS> g) {
+  constexpr int KP = LBK / 2;                       // pairs per row of a row-band tile
+  constexpr int RP = 256 / KP;                      // rows of a row-band tile per pass
+  constexpr int RB_LD = LBK + 4, KB_PAD = 16;
+  constexpr int A_LD = TA ? BM + KB_PAD : RB_LD;
+  constexpr int A_SZ = TA ? LBK * A_LD : BM * A_LD;
+  constexpr int B_LD = TB ? RB_LD : BN + KB_PAD;
+  constexpr int B_SZ = TB ? BN * B_LD : LBK * B_LD;
+  constexpr int A_P = BM * LBK / 512, B_P = BN * LBK / 512;   // pairs per thread per tile
+  constexpr int FM = BM / 32, FN = BN / 32;         // 16x16 tiles per wave (2x2 waves)
+  __shared__ __attribute__((aligned(16))) float smem[2 * (A_SZ + B_SZ)];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles = g.tilesM * g.tilesN;
+  const int per = (tiles + 7) / 8;
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous ranges of tile indices
+  if (t >= tiles) return;
+  const int gsz = 8 * g.tilesN;
+  const int grp = t / gsz;
+  const int gh = min(8, g.tilesM - grp * 8);
+  const int wt = t - grp * gsz;
+  const int bm0 = (grp * 8 + wt % gh) * BM;
+  const int bn0 = (wt / gh) * BN;
+  if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
+  const int z = blockIdx.z;
+  const TS* Ap = g.A + z * g.sA;
+  const TS* Bp = g.B + z * g.sB;
+  TS* Cp = g.C + z * g.sC;
+  const int M = g.M, N = g.N, K = g.K;
+
+  // row-band rows are fixed across k: pointers looked up once
+  const TS* aRow[TA ? 1 : A_P];
+  int aOk[TA ? 1 : A_P];
+  const TS* bRow[TB ? B_P : 1];
+  int bOk[TB ? B_P : 1];
+  if (!TA) {
+#pragma unroll
+    for (int p = 0; p < A_P; ++p) {
+      const int gi = bm0 + tid / KP + RP * p;
+      aOk[p] = gi < M;
+      const int gc = min(gi, M - 1);
+      aRow[p] = Ap + (long long)(g.rA ? g.rA[gc] : gc) * g.lda;
+    }
+  }
+  if (TB) {
+#pragma unroll
+    for (int p = 0; p < B_P; ++p) {
+      const int gj = bn0 + tid / KP + RP * p;
+      bOk[p] = gj < N;
+      const int gc = min(gj, N - 1);
+      bRow[p] = Bp + (long long)(g.rB ? g.rB[gc] : gc) * g.ldb;
+    }
+  }
+  // k-band row indices are fetched one k-step ahead of their data, from a
+  // readable stand-in when there is no index array (the value is then unused)
+  constexpr int KA = TA ? A_P : 1, KB = TB ? 1 : B_P;
+  const int* rAs = g.rA ? g.rA : reinterpret_cast<const int*>(Ap);
+  const int* rBs = g.rB ? g.rB : reinterpret_cast<const int*>(Bp);
+  int ixa[KA], ixb[KB];
+  auto load_index = [&](int k0) {
+    if (TA) {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KA; ++p) ixa[p] = rAs[min(k0 + tid / TPR + RPP * p, K - 1)];
+    }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+#pragma unroll
+      for (int p = 0; p < KB; ++p) ixb[p] = rBs[min(k0 + tid / TPR + RPP * p, K - 1)];
+    }
+  };
+  // a pair at (c, c + 1) of a row whose extent is lim, at a clamped address
+  auto ld_pair = [&](const TS* row, int c, int lim, float& x, float& y) {
+    if (VEC) {
+      if constexpr (sizeof(TS) == 8) {
+        const double2 v = *reinterpret_cast<const double2*>(row + min(c, (lim - 1) & ~1));
+        x = (float)v.x; y = (float)v.y;
+      } else {
+        const float2 v = *reinterpret_cast<const float2*>(row + min(c, (lim - 1) & ~1));
+        x = v.x; y = v.y;
+      }
+    } else {
+      x = (float)row[min(c, lim - 1)];
+      y = (float)row[min(c + 1, lim - 1)];
+    }
+  };
+  float ra[A_P][2], rb[B_P][2];
+  auto load_tiles = [&](int k0) {
+    if (!TA) {
+      const int gk = k0 + (tid % KP) * 2;
+#pragma unroll
+      for (int p = 0; p < A_P; ++p) ld_pair(aRow[p], gk, K, ra[p][0], ra[p][1]);
+    } else {
+      constexpr int TPR = BM / 2, RPP = 256 / TPR;
+      const int gi = bm0 + (tid % TPR) * 2;
+#pragma unroll
+      for (int p = 0; p < A_P; ++p) {
+        const int gk = min(k0 + tid / TPR + RPP * p, K - 1);
+        ld_pair(Ap + (long long)(g.rA ? ixa[p] : gk) * g.lda, gi, M, ra[p][0], ra[p][1]);
+      }
+    }
+    if (!TB) {
+      constexpr int TPR = BN / 2, RPP = 256 / TPR;
+      const int gj = bn0 + (tid % TPR) * 2;
+#pragma unroll
+      for (int p = 0; p < B_P; ++p) {
+        const int gk = min(k0 + tid / TPR + RPP * p, K - 1);
+        ld_pair(Bp + (long long)(g.rB ? ixb[p] : gk) * g.ldb, gj, N, rb[p][0], rb[p][1]);
+      }
+    } else {
+      const int gk = k0 + (tid % KP) * 2;
+#pragma unroll
+      for (int p = 0; p < B_P; ++p) ld_pair(bRow[p], gk, K, rb[p][0], rb[p][1]);
+    }
+  };
+  // mask the loaded tile of k-step k0 and write it to LDS stage `st`
+  auto store_tiles = [&](int st, int k0) {
+    float* As = smem + st * (A_SZ + B_SZ);
+    float* Bs = As + A_SZ;
+#pragma unroll
+    for (int p = 0; p < A_P; ++p) {
+      if (!TA) {
+        const int r = tid / KP + RP * p, gk = k0 + (tid % KP) * 2;
+        const bool ok = aOk[p];
+        *reinterpret_cast<float2*>(&As[r * A_LD + (tid % KP) * 2]) =
+            make_float2((ok && gk < K) ? ra[p][0] : 0.f, (ok && gk + 1 < K) ? ra[p][1] : 0.f);
+      } else {
+        constexpr int TPR = BM / 2, RPP = 256 / TPR;
+        const int kr = tid / TPR + RPP * p, gi = bm0 + (tid % TPR) * 2;
+        const bool ok = k0 + kr < K;
+        *reinterpret_cast<float2*>(&As[kr * A_LD + (tid % TPR) * 2]) =
+            make_float2((ok && gi < M) ? ra[p][0] : 0.f, (ok && gi + 1 < M) ? ra[p][1] : 0.f);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < B_P; ++p) {
+      if (TB) {
+        const int r = tid / KP + RP * p, gk = k0 + (tid % KP) * 2;
+        const bool ok = bOk[p];
+        *reinterpret_cast<float2*>(&Bs[r * B_LD + (tid % KP) * 2]) =
+            make_float2((ok && gk < K) ? rb[p][0] : 0.f, (ok && gk + 1 < K) ? rb[p][1] : 0.f);
+      } else {
+        constexpr int TPR = BN / 2, RPP = 256 / TPR;
+        const int kr = tid / TPR + RPP * p, gj = bn0 + (tid % TPR) * 2;
+        const bool ok = k0 + kr < K;
+        *reinterpret_cast<float2*>(&Bs[kr * B_LD + (tid % TPR) * 2]) =
+            make_float2((ok && gj < N) ? rb[p][0] : 0.f, (ok && gj + 1 < N) ? rb[p][1] : 0.f);
+      }
+    }
+  };
+
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (K + LBK - 1) / LBK;
+  if (nk > 0) {
+    load_index(0);
+    load_tiles(0);
+    if (nk > 1) load_index(LBK);
+    store_tiles(0, 0);
+    __syncthreads();
+  }
+  for (int it = 0; it < nk; ++it) {
+    const int st = it & 1;
+    if (it + 1 < nk) {
+      load_tiles((it + 1) * LBK);
+      if (it + 2 < nk) load_index((it + 2) * LBK);
+    }
+    const float* As = smem + st * (A_SZ + B_SZ);
+    const float* Bs = As + A_SZ;
+#pragma unroll
+    for (int kk = 0; kk < LBK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      float fa[FM], fb[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int i = wm0 + a * 16 + (lane & 15);
+        fa[a] = TA ? As[k * A_LD + i] : As[i * A_LD + k];
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int j = wn0 + b * 16 + (lane & 15);
+        fb[b] = TB ? Bs[j * B_LD + k] : Bs[k * B_LD + j];
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (it + 1 < nk) store_tiles(st ^ 1, (it + 1) * LBK);
+    __syncthreads();
+  }
+
+  // epilogue: accumulator v of tile (a, b) is D[4 (l / 16) + v][l % 16]
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    long long ro[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ic = min(bm0 + wm0 + a * 16 + 4 * (lane >> 4) + v, M - 1);
+      ro[v] = (long long)(g.rC ? g.rC[ic] : ic) * g.ldc;
+    }
+    TS cold[4][FN];
+    if (g.beta != 0.0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) cold[v][b] = Cp[ro[v] + min(bn0 + wn0 + b * 16 + (lane & 15), N - 1)];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = bm0 + wm0 + a * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int j = bn0 + wn0 + b * 16 + (lane & 15);
+        if (i < M && j < N && (!g.lowerOnly || i >= j)) {
+          double val = g.alpha * (double)acc[a][b][v];
+          if (g.beta != 0.0) val += g.beta * (double)cold[v][b];
+          Cp[ro[v] + j] = (TS)val;
+        }
+      }
+    }
+  }
+}
+
+template <typename TS, int BM, int BN, bool TA, bool TB>
+void launch_lp32(GemmLpParams<TS> p, int batch, hipStream_t s, bool vec) {
+  p.tilesM = ceil_div(p.M, BM);
+  p.tilesN = ceil_div(p.N, BN);
+  const int tiles = p.tilesM * p.tilesN;
+  const int grid = 8 * ((tiles + 7) / 8);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  FROB_LAUNCH_CHECK();
+}
+
 template <typename TS, int MODE, int BM, int BN, bool TA, bool TB>
 void launch_lp(GemmLpParams<TS> p, int batch, hipStream_t s) {
   p.tilesM = ceil_div(p.M, BM);
@@ -238,9 +489,21 @@ void launch_lp(GemmLpParams<TS> p, int batch, hipStream_t s) {
   FROB_LAUNCH_CHECK();
 }
 
+template <typename TS>
+bool pairs_ok(const TS* p, int ld, long long st, int extent) {
+  return (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(TS))) == 0 && ld % 2 == 0 && st % 2 == 0 && extent % 2 == 0;
+}
+
 template <typename TS, int MODE, bool TA, bool TB>
 void pick_lp(const GemmLpParams<TS>& p, int batch, hipStream_t s) {
   const long long big = (long long)ceil_div(p.M, 128) * ceil_div(p.N, 128) * batch;
+  if (MODE == LP_F32) {
+    // pairs along each operand's contiguous direction, aligned to their size
+    const bool vec = pairs_ok(p.A, p.lda, p.sA, TA ? p.M : p.K) && pairs_ok(p.B, p.ldb, p.sB, TB ? p.K : p.N);
+    if (big >= 160) launch_lp32<TS, 128, 128, TA, TB>(p, batch, s, vec);
+    else launch_lp32<TS, 64, 64, TA, TB>(p, batch, s, vec);
+    return;
+  }
   if (big >= 160) launch_lp<TS, MODE, 128, 128, TA, TB>(p, batch, s);
   else launch_lp<TS, MODE, 64, 64, TA, TB>(p, batch, s);
 }
