@@ -127,9 +127,10 @@ def bench_adjoint(fi, inputs, h, torch, np, log):
 def bench_mp_large(fi, inputs, h, torch, np, log, n):
     """Mixed precision at order n (8192): M = U diag(sigma) V^H (HPD: V = U)
     with kappa in {1e2, 1e4, 1e6}, drawn on the device.  For FP64, FP32 and
-    BF16 matrix-core operands: the error of X against V diag(1/sigma) U^H
-    without refinement, and the time, step count, residual and error with
-    up to eight Newton-Schulz steps (FP64 residual)."""
+    BF16 matrix-core operands, and FP64 with an FP32 Newton-Schulz
+    correction: the error of X against V diag(1/sigma) U^H without
+    refinement, and the time, step count, residual and error with up to
+    eight Newton-Schulz steps (FP64 residual)."""
     out = {}
     Xr = torch.empty((n, n), dtype=torch.float64, device="cuda")
     Xi = torch.empty_like(Xr)
@@ -142,7 +143,8 @@ def bench_mp_large(fi, inputs, h, torch, np, log, n):
         for kexp in (2, 4, 6):
             log(f"[bench] mp n={n} {kind} kappa=1e{kexp}: generating")
             dA, dB, Rr, Ri = inputs.spectrum_device(n, 10.0 ** kexp, kind=kind, seed=302 + kexp)
-            for pname, prec in (("f64", fi.FROB_PREC_F64), ("f32", fi.FROB_PREC_F32), ("bf16", fi.FROB_PREC_BF16)):
+            for pname, prec, f32c in (("f64", fi.FROB_PREC_F64, False), ("f64_f32corr", fi.FROB_PREC_F64, True),
+                                      ("f32", fi.FROB_PREC_F32, False), ("bf16", fi.FROB_PREC_BF16, False)):
                 key = f"mp{n}_{kind}_k1e{kexp}_{pname}"
                 entry = {}
                 try:
@@ -151,7 +153,7 @@ def bench_mp_large(fi, inputs, h, torch, np, log, n):
                     res = {}
 
                     def run():
-                        res.update(fn(h, dA, dB, Xr, Xi, prec=prec, refine=8)[2])
+                        res.update(fn(h, dA, dB, Xr, Xi, prec=prec, refine=8, f32_correction=f32c)[2])
                     run()
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
