@@ -60,7 +60,8 @@ constexpr bool LEAF_JOINT_STORE(int W) { return W <= 8; }
 
 template <int R, int W>
 __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
-                                                         int k0, int mm, int nc, int n2, int* info) {
+                                                         int k0, int mm, int nc, int n2, int* info,
+                                                         int* __restrict__ snap, int sfrom) {
   constexpr int NT = LEAF_NT, NW = NT / 64;
   static_assert(W % 2 == 0 && NW <= 16, "leaf shape");
   __shared__ double s_cv[2][NW];
@@ -424,7 +425,11 @@ __global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a,
   // ---- the new row order ----
 #pragma unroll
   for (int s = 0; s < R; ++s)
-    if (pos[s] >= 0) perm[k0 + pos[s]] = ph[s];
+    if (pos[s] >= 0) {
+      perm[k0 + pos[s]] = ph[s];
+      // copy of the trailing row order from position sfrom on (look-ahead)
+      if (snap && k0 + pos[s] >= sfrom) snap[k0 + pos[s] - sfrom] = ph[s];
+    }
 }
 
 // widest leaf for a panel with mm rows (R * W <= 32 doubles per thread keeps
@@ -439,17 +444,18 @@ inline int leaf_width(int mm) {
   return 0;
 }
 
-void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, int nc, int n2, int* info) {
+void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, int nc, int n2, int* info,
+                 int* snap = nullptr, int sfrom = 0) {
   const int R = ceil_div(mm, LEAF_NT);
   if (nc > leaf_width(mm) || n2 > leaf_width(mm)) throw std::runtime_error("getrf_f64: leaf wider than its template");
   if (n2 > 0 && !LEAF_SIBLING(R)) throw std::runtime_error("getrf_f64: no fused sibling update for this leaf");
   dim3 g(1), b(LEAF_NT);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_f64<8, 4>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_f64<16, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_f64<32, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info);
+  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_f64<8, 4>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_f64<16, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_f64<32, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else throw std::runtime_error("getrf_f64: matrix order above 16384 is not supported");
   FROB_LAUNCH_CHECK();
 }
@@ -574,11 +580,14 @@ void launch_node(hipStream_t s, double* a, int lda, const int* perm, int k0, int
 }
 
 // factor columns [k0, k0 + n) over logical rows [k0, m)
-void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int n, int* info, double* work, int* cnt) {
+// snap (optional): the leaf that ends the recursion, the last to write perm,
+// also writes perm[sfrom .. m) to snap[0 ..)
+void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int n, int* info, double* work, int* cnt,
+               int* snap = nullptr, int sfrom = 0) {
   const int mm = m - k0;
   const int wmax = leaf_width(mm);
   if (n <= wmax) {
-    launch_leaf(s, a, lda, perm, k0, mm, n, 0, info);
+    launch_leaf(s, a, lda, perm, k0, mm, n, 0, info, snap, sfrom);
     return;
   }
   int n1 = (n / 2 + 7) / 8 * 8;
@@ -586,13 +595,13 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   const int n2 = n - n1;
   if (n1 <= wmax && n2 <= wmax && LEAF_SIBLING(ceil_div(mm, LEAF_NT))) {
     // bottom node: one leaf launch factors both halves
-    launch_leaf(s, a, lda, perm, k0, mm, n1, n2, info);
+    launch_leaf(s, a, lda, perm, k0, mm, n1, n2, info, snap, sfrom);
     return;
   }
   getrf_rec(s, a, lda, perm, k0, m, n1, info, work, cnt);
   if (n1 <= NODE_MAX && n2 <= NODE_MAX) {
     launch_node(s, a, lda, perm, k0, m - k0, n1, n2, cnt);
-    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
+    getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
     return;
   }
   // U12 = L11^{-1} A12 (unit lower), rows through perm
@@ -604,7 +613,7 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   DOp U12{a + k0 + n1, lda, perm + k0};
   DOut A22{a + k0 + n1, lda, perm + k0 + n1, nullptr};
   gemm_f64(s, false, false, m - k0 - n1, n2, n1, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
-  getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt);
+  getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
 }
 
 // Panels of LA_NB columns with a look-ahead of one panel (see internal.hpp).
@@ -612,9 +621,10 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
 // trailing update may run while a later panel pivots, provided it addresses
 // its rows through a copy of perm taken when its panel was finished (the set
 // of trailing physical rows is the same; their order does not matter to a
-// row-wise update).  Ordering:
-//   s0: panel j -> snapshot -> event F_j -> [wait R_{j-1}] update of panel
-//       j+1's columns -> panel j+1 ...
+// row-wise update); the panel's last leaf writes that copy beside perm.
+// Ordering:
+//   s0: panel j (with the snapshot) -> event F_j -> [wait R_{j-1}] update of
+//       panel j+1's columns -> panel j+1 ...
 //   s1: [wait F_j] update of the columns right of panel j+1 -> event R_j
 // The update of panel j+1's columns waits for R_{j-1}, the previous update
 // of those columns; the snapshot buffer of panel j is rewritten at panel
@@ -643,11 +653,11 @@ void getrf_lookahead(hipStream_t s0, int n, double* a, int lda, int* perm, int* 
   int last_r = -1;
   for (int j = 0; j < np; ++j) {
     const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
-    getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt);
     const int r0 = k0 + nb;
-    if (r0 >= n) break;
     int* sn = snap[j & 1];
-    FROB_HIP(hipMemcpyAsync(sn, perm + r0, sizeof(int) * (n - r0), hipMemcpyDeviceToDevice, s0));
+    // the panel's last leaf also writes the snapshot perm[r0 .. n)
+    getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
+    if (r0 >= n) break;
     FROB_HIP(hipEventRecord(evF(j), s0));
     const int c1 = r0, w1 = min(LA_NB, n - c1);
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));

@@ -49,7 +49,7 @@ constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
 template <int R, int W>
 __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, double* __restrict__ ai, int lda,
                                                      int* __restrict__ perm, int k0, int mm, int nc, int n2,
-                                                     int* info) {
+                                                     int* info, int* __restrict__ snap, int sfrom) {
   constexpr int NW = ZLT / 64;
   __shared__ double s_cv[2][NW];
   __shared__ int s_ck[2][NW];
@@ -446,7 +446,11 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
 
 #pragma unroll
   for (int s = 0; s < R; ++s)
-    if (pos[s] >= 0) perm[k0 + pos[s]] = ph[s];
+    if (pos[s] >= 0) {
+      perm[k0 + pos[s]] = ph[s];
+      // copy of the trailing row order from position sfrom on (look-ahead)
+      if (snap && k0 + pos[s] >= sfrom) snap[k0 + pos[s] - sfrom] = ph[s];
+    }
 }
 
 // widest leaf for a panel with mm rows (R * W <= 16 complex values per thread)
@@ -461,17 +465,17 @@ inline int zleaf_width(int mm) {
 }
 
 void zlaunch_leaf(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k0, int mm, int nc, int n2,
-                  int* info) {
+                  int* info, int* snap = nullptr, int sfrom = 0) {
   const int R = ceil_div(mm, ZLT);
   if (nc > zleaf_width(mm) || n2 > zleaf_width(mm)) throw std::runtime_error("getrf_z64: leaf wider than template");
   if (n2 > 0 && !ZLEAF_SIBLING(R)) throw std::runtime_error("getrf_z64: no fused sibling update for this leaf");
   dim3 g(1), b(ZLT);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_z64<8, 2>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_z64<16, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
-  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_z64<32, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info);
+  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_z64<8, 2>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_z64<16, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_z64<32, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else throw std::runtime_error("getrf_z64: matrix order above 16384 is not supported");
   FROB_LAUNCH_CHECK();
 }
@@ -663,12 +667,14 @@ void zlaunch_node(hipStream_t s, double* ar, double* ai, int lda, const int* per
   FROB_LAUNCH_CHECK();
 }
 
+// snap (optional): the leaf that ends the recursion also writes
+// perm[sfrom .. m) to snap[0 ..)
 void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k0, int m, int n, int* info,
-                double* work, int* cnt) {
+                double* work, int* cnt, int* snap = nullptr, int sfrom = 0) {
   const int mm = m - k0;
   const int wmax = zleaf_width(mm);
   if (n <= wmax) {
-    zlaunch_leaf(s, ar, ai, lda, perm, k0, mm, n, 0, info);
+    zlaunch_leaf(s, ar, ai, lda, perm, k0, mm, n, 0, info, snap, sfrom);
     return;
   }
   int n1 = (n / 2 + 3) / 4 * 4;
@@ -676,13 +682,13 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   const int n2 = n - n1;
   if (n1 <= wmax && n2 <= wmax && ZLEAF_SIBLING(ceil_div(mm, ZLT))) {
     // bottom node: one leaf launch factors both halves
-    zlaunch_leaf(s, ar, ai, lda, perm, k0, mm, n1, n2, info);
+    zlaunch_leaf(s, ar, ai, lda, perm, k0, mm, n1, n2, info, snap, sfrom);
     return;
   }
   zgetrf_rec(s, ar, ai, lda, perm, k0, m, n1, info, work, cnt);
   if (n1 <= ZNODE_MAX && n2 <= ZNODE_MAX) {
     zlaunch_node(s, ar, ai, lda, perm, k0, m - k0, n1, n2, cnt);
-    zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt);
+    zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
     return;
   }
   ZOp L11{ar + k0, ai + k0, lda, perm + k0};
@@ -692,7 +698,7 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   ZOp U12{ar + k0 + n1, ai + k0 + n1, lda, perm + k0};
   ZOut A22{ar + k0 + n1, ai + k0 + n1, lda, perm + k0 + n1, nullptr};
   gemm_z64(s, OP_N, OP_N, m - k0 - n1, n2, n1, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
-  zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt);
+  zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
 }
 
 // Panels of LA_NB columns with a look-ahead of one panel; the ordering and
@@ -721,11 +727,11 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
   int last_r = -1;
   for (int j = 0; j < np; ++j) {
     const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
-    zgetrf_rec(s0, ar, ai, lda, perm, k0, n, nb, info, work0, cnt);
     const int r0 = k0 + nb;
-    if (r0 >= n) break;
     int* sn = snap[j & 1];
-    FROB_HIP(hipMemcpyAsync(sn, perm + r0, sizeof(int) * (n - r0), hipMemcpyDeviceToDevice, s0));
+    // the panel's last leaf also writes the snapshot perm[r0 .. n)
+    zgetrf_rec(s0, ar, ai, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
+    if (r0 >= n) break;
     FROB_HIP(hipEventRecord(evF(j), s0));
     const int c1 = r0, w1 = min(LA_NB, n - c1);
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
