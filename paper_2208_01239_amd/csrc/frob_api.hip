@@ -153,14 +153,15 @@ bool bad_dims(int n, int lda) { return n < 1 || n > FROB_MAX_N || lda < n; }
 struct GenWs {
   double *F, *Y, *C, *W, *tmp;
   int *p1, *p2;
-  int ld;
+  int ld;    // Y, W
+  int ldF;   // F and C: n x 2n, room for the columns carried through their LU
   frob_handle* h;
 };
 
 size_t gen_ws_bytes(int n) {
   Carve c(nullptr);
   const size_t nn = (size_t)n * n;
-  c.take<double>(nn); c.take<double>(nn); c.take<double>(nn); c.take<double>(nn);
+  c.take<double>(2 * nn); c.take<double>(nn); c.take<double>(2 * nn); c.take<double>(nn);
   c.take<double>(solver_work_elems(n));
   c.take<int>(n); c.take<int>(n);
   return c.off;
@@ -169,47 +170,68 @@ size_t gen_ws_bytes(int n) {
 GenWs gen_ws_carve(Carve& c, int n) {
   GenWs w;
   const size_t nn = (size_t)n * n;
-  w.F = c.take<double>(nn); w.Y = c.take<double>(nn); w.C = c.take<double>(nn); w.W = c.take<double>(nn);
+  w.F = c.take<double>(2 * nn); w.Y = c.take<double>(nn); w.C = c.take<double>(2 * nn); w.W = c.take<double>(nn);
   w.tmp = c.take<double>(solver_work_elems(n));
   w.p1 = c.take<int>(n); w.p2 = c.take<int>(n);
   w.ld = n;
+  w.ldF = 2 * n;
   w.h = nullptr;
   return w;
 }
 
 // Steps 1-4 of Algorithm 5 (shared with Algorithm 3): LU of A, Y = A^{-1} B,
 // C = A + B Y, LU of C.
-void frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, GenWs& w, int* dinfo) {
-  const int ld = w.ld;
-  // step 1: P1 A = L1 U1
-  copy_f64(s, n, n, A, lda, nullptr, w.F, ld);
-  getrf_f64(s, n, w.F, ld, w.p1, dinfo + 0, w.tmp, lookahead(w.h));
-  // step 2: Y = U1^{-1} L1^{-1} P1 B
-  copy_f64(s, n, n, B, ldb, w.p1, w.Y, ld);
-  DOp LU1{w.F, ld, w.p1};
+// With the look-ahead LU, B rides along the LU of A as extra columns (they
+// take L1^{-1} P1 on the second stream, off the panel chain), and with
+// `cinv` the identity rides along the LU of C, leaving L2^{-1} P2 for
+// C^{-1} = U2^{-1} L2^{-1} P2.  Returns whether it did.
+bool frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, GenWs& w, int* dinfo,
+                   bool cinv) {
+  const int ld = w.ld, lf = w.ldF;
+  const LookAhead* la = lookahead(w.h);
+  const bool carry = getrf_lookahead_on(n, la);
+  DOp LU1{w.F, lf, w.p1};
   DOut Yo{w.Y, ld, nullptr, nullptr};
-  trsm_f64(s, false, TRI_LOWER_UNIT, false, n, n, LU1, Yo, w.tmp);
+  // step 1: P1 A = L1 U1;  step 2: Y = U1^{-1} L1^{-1} P1 B
+  copy_f64(s, n, n, A, lda, nullptr, w.F, lf);
+  if (carry) {
+    copy_f64(s, n, n, B, ldb, nullptr, w.F + n, lf);
+    getrf_f64(s, n, w.F, lf, w.p1, dinfo + 0, w.tmp, la, n);
+    copy_f64(s, n, n, w.F + n, lf, w.p1, w.Y, ld);   // L1^{-1} P1 B in logical row order
+  } else {
+    getrf_f64(s, n, w.F, lf, w.p1, dinfo + 0, w.tmp, la);
+    copy_f64(s, n, n, B, ldb, w.p1, w.Y, ld);
+    trsm_f64(s, false, TRI_LOWER_UNIT, false, n, n, LU1, Yo, w.tmp);
+  }
   trsm_f64(s, false, TRI_UPPER, false, n, n, LU1, Yo, w.tmp);
   // step 3: C = A + B Y
-  copy_f64(s, n, n, A, lda, nullptr, w.C, ld);
+  copy_f64(s, n, n, A, lda, nullptr, w.C, lf);
   {
     ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
     gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
-             DOut{w.C, ld, nullptr, nullptr});
+             DOut{w.C, lf, nullptr, nullptr});
   }
   // step 4: P2 C = L2 U2   (a zero pivot here means M is singular, Lemma 2.3)
-  getrf_f64(s, n, w.C, ld, w.p2, dinfo + 1, w.tmp, lookahead(w.h));
+  const bool carry2 = carry && cinv;
+  if (carry2) identity_f64(s, n, w.C + n, lf);
+  getrf_f64(s, n, w.C, lf, w.p2, dinfo + 1, w.tmp, la, carry2 ? n : 0);
+  return carry2;
 }
 
 void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, double* Xr, double* Xi,
                   int ldx, GenWs& w, int* dinfo) {
   const int ld = w.ld;
-  frob_lu_front(s, n, A, lda, B, ldb, w, dinfo);
+  const bool carried = frob_lu_front(s, n, A, lda, B, ldb, w, dinfo, true);
   // step 5, first block row: Re X = C^{-1} = U2^{-1} L2^{-1} P2
-  DOp LU2{w.C, ld, w.p2};
-  trtri_f64(s, TRI_UPPER, false, n, LU2, w.W, ld, w.tmp);
-  trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp);
-  permute_cols_f64(s, n, n, w.W, ld, w.p2, Xr, ldx);
+  DOp LU2{w.C, w.ldF, w.p2};
+  if (carried) {
+    copy_f64(s, n, n, w.C + n, w.ldF, w.p2, Xr, ldx);   // L2^{-1} P2 in logical row order
+    trsm_f64(s, false, TRI_UPPER, false, n, n, LU2, DOut{Xr, ldx, nullptr, nullptr}, w.tmp);
+  } else {
+    trtri_f64(s, TRI_UPPER, false, n, LU2, w.W, ld, w.tmp);
+    trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp);
+    permute_cols_f64(s, n, n, w.W, ld, w.p2, Xr, ldx);
+  }
   // step 5, second block row: Im X = -Y C^{-1}
   {
     ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
@@ -446,7 +468,7 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
     // right-hand side c' = c - mu d, d' = mu c + d; the solution is unchanged.
     auto pass = [&](const double* Au, int ldA, const double* Bu, int ldB, double mu) {
       fill_i32(s, INFO_SLOTS, 0, h->dinfo);
-      frob_lu_front(s, n, Au, ldA, Bu, ldB, w, h->dinfo);
+      frob_lu_front(s, n, Au, ldA, Bu, ldB, w, h->dinfo, false);
       // step 5: L2 U2 [x1 y1] = P2 [c d]
       copy_f64(s, n, nrhs, cv, ldc, w.p2, Z, q);
       copy_f64(s, n, nrhs, dv, ldc, w.p2, Z + nrhs, q);
@@ -454,7 +476,7 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
         // rows were gathered by p2 in both halves; rotate them in place
         rotate_f64(s, n, nrhs, mu, Z, q, Z + nrhs, q, Z, q, Z + nrhs, q);
       }
-      DOp LU2{w.C, w.ld, w.p2};
+      DOp LU2{w.C, w.ldF, w.p2};
       trsm_f64(s, false, TRI_LOWER_UNIT, false, n, q, LU2, DOut{Z, q, nullptr, nullptr}, w.tmp);
       trsm_f64(s, false, TRI_UPPER, false, n, q, LU2, DOut{Z, q, nullptr, nullptr}, w.tmp);
       // step 6: [x2 y2] = A^{-1} B [y1 x1] = Y [y1 x1]

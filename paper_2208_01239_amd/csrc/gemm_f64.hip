@@ -63,8 +63,10 @@ constexpr int gemm_min_blocks(int BM, int BN, int BK, bool TA, bool TB) {
   return 2 * gemm_lds_bytes(BM, BN, BK, TA, TB) <= 160 * 1024 ? 2 : 1;
 }
 
+// One output tile t (an index in the XCD-contiguous, grouped order) of the
+// product; smem holds gemm_lds_bytes(BM, BN, BK, TA, TB) bytes.
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK>
-__global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_gemm_f64(GemmF64Params g) {
+__device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, double* __restrict__ smem) {
   constexpr int KP = BK / 2;       // 16-byte pairs per row of a row-band tile
   constexpr int RP = 256 / KP;     // rows of a row-band tile per pass
   constexpr int FM = BM / WM / 16;
@@ -82,13 +84,8 @@ __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_ge
   constexpr int A_P = BM * BK / 512;
   constexpr int B_P = BN * BK / 512;
   static_assert(BK == 16 || BK == 32, "k-step");
-  __shared__ __attribute__((aligned(16))) double smem[2 * (A_SZ + B_SZ)];
+  static_assert(2 * (A_SZ + B_SZ) * 8 == gemm_lds_bytes(BM, BN, BK, TA, TB), "LDS size");
 
-  const int tiles = g.tilesM * g.tilesN;
-  const int per = (tiles + 7) / 8;
-  const int bid = blockIdx.x;
-  const int t = (bid & 7) * per + (bid >> 3);
-  if (t >= tiles) return;
   // grouped order: TILE_GROUP tile-rows at a time, column-major inside the
   // group, so that the tiles an XCD runs at once form a square block
   const int gsz = TILE_GROUP * g.tilesN;
@@ -358,6 +355,33 @@ __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_ge
   }
 }
 
+// Block b works on XCD b % 8 (hardware round-robin), in that XCD's
+// contiguous range of tile indices.  The usual grid gives every block one
+// tile.  PERSIST: a capped grid (GridCapScope) whose blocks take several
+// tiles, in steps of the number of blocks per XCD, and leave compute units
+// free for concurrent work.
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PERSIST>
+__global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_gemm_f64(GemmF64Params g) {
+  __shared__ __attribute__((aligned(16))) double smem[gemm_lds_bytes(BM, BN, BK, TA, TB) / 8];
+  const int tiles = g.tilesM * g.tilesN;
+  const int per = (tiles + 7) / 8;
+  const int bid = blockIdx.x;
+  if (!PERSIST) {
+    const int t = (bid & 7) * per + (bid >> 3);
+    if (t >= tiles) return;
+    gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
+  } else {
+    const int step = gridDim.x >> 3;
+    for (int li = bid >> 3; li < per; li += step) {
+      const int t = (bid & 7) * per + li;
+      if (t >= tiles) break;
+      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
+      // a next tile reuses the LDS ring: the tile's last k-step ended with a
+      // barrier after its last LDS read, and the epilogue reads no LDS
+    }
+  }
+}
+
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>
 static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
   GemmF64Params p = p0;
@@ -365,14 +389,30 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
   p.tilesN = ceil_div(p.N, BN);
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
+  // capped grids for the untransposed products (the factorizations' updates)
+  const int cap = (!TA && !TB && grid_cap() > 0) ? std::max(8, grid_cap() & ~7) : 0;
   // the big tile keeps a 16-deep k-step (two workgroups per CU fit in LDS);
   // the smaller tiles, used for latency-bound products, take 32 (half as
   // many dependent k-steps)
   constexpr int BK = (BM * BN >= 128 * 128) ? 16 : 32;
-  if (p.vecA && p.vecB)
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  const bool vec = p.vecA && p.vecB;
+  if constexpr (!TA && !TB) {
+    if (cap > 0 && cap < grid) {
+      if (vec)
+        hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, true>), dim3(cap, 1, batch), dim3(256), 0, s,
+                           p);
+      else
+        hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK, true>), dim3(cap, 1, batch), dim3(256), 0,
+                           s, p);
+      FROB_LAUNCH_CHECK();
+      return;
+    }
+  }
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK, false>), dim3(grid, 1, batch), dim3(256), 0, s,
+                       p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -407,10 +447,14 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 namespace {
 thread_local int t_lp_mode = LP_NONE;
+thread_local int t_grid_cap = 0;
 }
 int lp_mode() { return t_lp_mode; }
 LowPrecScope::LowPrecScope(int mode) : prev(t_lp_mode) { t_lp_mode = mode; }
 LowPrecScope::~LowPrecScope() { t_lp_mode = prev; }
+int grid_cap() { return t_grid_cap; }
+GridCapScope::GridCapScope(int blocks) : prev(t_grid_cap) { t_grid_cap = blocks; }
+GridCapScope::~GridCapScope() { t_grid_cap = prev; }
 
 void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, DOp A, int triA, DOp B,
                       int triB, double beta, DOut C, bool lowerOnly, int batch, long long sA, long long sB,

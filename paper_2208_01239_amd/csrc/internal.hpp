@@ -43,6 +43,16 @@ struct LowPrecScope {
   explicit LowPrecScope(int mode);
   ~LowPrecScope();
 };
+// While a GridCapScope is alive on the calling host thread, gemm_f64 launches
+// at most that many workgroups (rounded down to a multiple of 8), each taking
+// several tiles: the look-ahead's trailing updates then leave compute units
+// free for the panel chain on the other stream.  0 = no cap.
+int grid_cap();
+struct GridCapScope {
+  int prev;
+  explicit GridCapScope(int blocks);
+  ~GridCapScope();
+};
 
 // Planar complex GEMM, C = alpha op(A) op(B) + beta C with real alpha/beta and
 // op in {N, T, C (conjugate transpose)}; four real MFMA products per tile.
@@ -88,6 +98,11 @@ void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, double* Wre, doubl
 // receives the 1-based column of the first exactly-zero pivot or stays 0.
 // `work` holds getrf_work_elems(n) doubles.
 //
+// With q > 0 the q columns right of the matrix (a + n, same rows and lda) take
+// the row interchanges and the elimination without a pivot search: they end
+// holding L^{-1} P times their input, rows addressed through perm.  With the
+// look-ahead they are updated with the trailing columns on the second stream.
+//
 // With a LookAhead (a second stream and events owned by the handle) orders
 // n >= LA_MIN are factored in panels of LA_NB columns with a look-ahead of
 // one panel: the update of the next panel's columns stays on `s`, the update
@@ -102,9 +117,14 @@ struct LookAhead {
 // n = 4096 (about 2 % apart), 128 to 512 slower.
 constexpr int LA_NB = 32;
 constexpr int LA_MIN = 1024;
+// Workgroups of a trailing update on the second stream: fewer than the chip
+// holds, so the panel chain's single-workgroup leaves find a free compute unit.
+constexpr int LA_GRID_CAP = 224;
 size_t getrf_work_elems(int n);
 void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work,
-               const LookAhead* la = nullptr);
+               const LookAhead* la = nullptr, int q = 0);
+// whether getrf_f64 factors order n with the look-ahead
+bool getrf_lookahead_on(int n, const LookAhead* la);
 size_t getrf_z_work_elems(int n);
 void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work,
                const LookAhead* la = nullptr);

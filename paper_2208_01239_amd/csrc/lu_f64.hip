@@ -12,6 +12,7 @@
 // is a swap of two integers and the stored multipliers of earlier columns
 // follow automatically.  An exactly-zero pivot column is recorded in *info
 // (1-based, first occurrence) and factoring continues, as LAPACK does.
+#include <algorithm>
 #include <climits>
 
 #include "common.hpp"
@@ -629,8 +630,9 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
 // The update of panel j+1's columns waits for R_{j-1}, the previous update
 // of those columns; the snapshot buffer of panel j is rewritten at panel
 // j + 2, after s0 has waited for R_j.
-void getrf_lookahead(hipStream_t s0, int n, double* a, int lda, int* perm, int* info, double* work, int* cnt,
+void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm, int* info, double* work, int* cnt,
                      const LookAhead& la) {
+  const int nt = n + q;   // the q columns right of the matrix take every update and no pivot search
   hipStream_t s1 = la.s1;
   double* work0 = work;
   double* work1 = work0 + trsm_work_elems(n / 2 + 8);
@@ -657,16 +659,24 @@ void getrf_lookahead(hipStream_t s0, int n, double* a, int lda, int* perm, int* 
     int* sn = snap[j & 1];
     // the panel's last leaf also writes the snapshot perm[r0 .. n)
     getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
-    if (r0 >= n) break;
+    if (r0 >= n) {
+      // the last panel's rows of the extra columns: U12 = L11^{-1} A12 only
+      if (q > 0) {
+        if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
+        update(s0, k0, nb, n, q, perm + r0, work0);
+      }
+      break;
+    }
     FROB_HIP(hipEventRecord(evF(j), s0));
     const int c1 = r0, w1 = min(LA_NB, n - c1);
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
     // the next panel's update is a recursion node (solve and update in one launch)
     if (nb <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, k0, n - k0, nb, w1, cnt);
     else update(s0, k0, nb, c1, w1, perm + r0, work0);
-    const int c2 = c1 + w1, w2 = n - c2;
+    const int c2 = c1 + w1, w2 = nt - c2;
     if (w2 > 0) {
       FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
+      GridCapScope cap(LA_GRID_CAP);   // leave compute units to the panel chain
       update(s1, k0, nb, c2, w2, sn, work1);
       FROB_HIP(hipEventRecord(evR(j), s1));
       last_r = j;
@@ -679,18 +689,27 @@ void getrf_lookahead(hipStream_t s0, int n, double* a, int lda, int* perm, int* 
 
 size_t getrf_work_elems(int n) {
   // node counter, recursion and look-ahead scratch of s0, solve scratch of the
-  // second stream, two snapshots of n row indices
-  return 64 + trsm_work_elems(n / 2 + 8) + trsm_work_elems(LA_NB) + (size_t)n;
+  // second stream, two snapshots of n row indices; or the solve of extra
+  // columns without the look-ahead
+  return 64 + std::max(trsm_work_elems(n / 2 + 8) + trsm_work_elems(LA_NB) + (size_t)n, trsm_work_elems(n));
 }
 
-void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work, const LookAhead* la) {
+bool getrf_lookahead_on(int n, const LookAhead* la) { return la && la->s1 && n >= LA_MIN; }
+
+void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work, const LookAhead* la,
+               int q) {
   if (n <= 0) return;
   iota_i32(s, n, perm);
   // the node kernels' workgroup counter lives in the first 64 doubles of work
   int* cnt = reinterpret_cast<int*>(work);
   fill_i32(s, 1, 0, cnt);
-  if (la && la->s1 && n >= LA_MIN) getrf_lookahead(s, n, a, lda, perm, info, work + 64, cnt, *la);
-  else getrf_rec(s, a, lda, perm, 0, n, n, info, work + 64, cnt);
+  if (getrf_lookahead_on(n, la)) {
+    getrf_lookahead(s, n, q, a, lda, perm, info, work + 64, cnt, *la);
+  } else {
+    getrf_rec(s, a, lda, perm, 0, n, n, info, work + 64, cnt);
+    if (q > 0)
+      trsm_f64(s, false, TRI_LOWER_UNIT, false, n, q, DOp{a, lda, perm}, DOut{a + n, lda, perm, nullptr}, work + 64);
+  }
 }
 
 }  // namespace frob
