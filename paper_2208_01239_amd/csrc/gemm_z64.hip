@@ -10,6 +10,8 @@
 // v_mfma_f64_16x16x4f64 products on the two planes:
 //   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
 // with the imaginary fragment of a conjugated operand negated once per k-step.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -39,8 +41,14 @@ __device__ __forceinline__ void ztri_mask(double& re, double& im, int tri, int r
   }
 }
 
+// LDS of the double-buffered planar operand tiles, in doubles
+constexpr int zgemm_lds_doubles(int BM, int BN, int BK, bool TA, bool TB) {
+  return 2 * 2 * ((TA ? BK * (BM + 16) : BM * (BK + 2)) + (TB ? BN * (BK + 2) : BK * (BN + 16)));
+}
+
+// One output tile t (an index in the XCD-contiguous, grouped order).
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
-__global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
+__device__ __forceinline__ void gemm_z64_tile(const GemmZ64Params& g, int t, double* __restrict__ smem) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
@@ -56,13 +64,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   // pairs per thread per tile
   constexpr int A_P = BM * BK / 512;
   constexpr int B_P = BN * BK / 512;
-  __shared__ __attribute__((aligned(16))) double smem[2 * 2 * (A_SZ + B_SZ)];  // [stage][re A, im A, re B, im B]
+  // smem: [stage][re A, im A, re B, im B]
+  static_assert(2 * 2 * (A_SZ + B_SZ) == zgemm_lds_doubles(BM, BN, BK, TA, TB), "LDS size");
 
-  const int tiles = g.tilesM * g.tilesN;
-  const int per = (tiles + 7) / 8;
-  const int bid = blockIdx.x;
-  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous ranges of tile indices
-  if (t >= tiles) return;
   // tile indices run through groups of eight tile-rows column by column
   const int gsz = 8 * g.tilesN;
   const int grp = t / gsz;
@@ -356,6 +360,30 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   }
 }
 
+// Block b works on XCD b % 8 in that XCD's contiguous range of tile indices,
+// one tile per block; PERSIST: a capped grid (GridCapScope, as in the real
+// GEMM) whose blocks take several tiles.
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
+  __shared__ __attribute__((aligned(16))) double smem[zgemm_lds_doubles(BM, BN, 16, TA, TB)];
+  const int tiles = g.tilesM * g.tilesN;
+  const int per = (tiles + 7) / 8;
+  const int bid = blockIdx.x;
+  if (!PERSIST) {
+    const int t = (bid & 7) * per + (bid >> 3);
+    if (t >= tiles) return;
+    gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, smem);
+  } else {
+    const int step = gridDim.x >> 3;
+    for (int li = bid >> 3; li < per; li += step) {
+      const int t = (bid & 7) * per + li;
+      if (t >= tiles) break;
+      gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, smem);
+      // the tile's last k-step ended with a barrier; the epilogue reads no LDS
+    }
+  }
+}
+
 template <int BM, int BN, int WM, int WN, bool TA, bool TB>
 static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
   GemmZ64Params p = p0;
@@ -363,10 +391,23 @@ static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
   p.tilesN = ceil_div(p.N, BN);
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
-  if (p.vecA && p.vecB)
-    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  const bool vec = p.vecA && p.vecB;
+  if constexpr (!TA && !TB) {
+    const int cap = grid_cap() > 0 ? std::max(8, grid_cap() & ~7) : 0;
+    if (cap > 0 && cap < grid) {
+      if (vec)
+        hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true, true>), dim3(cap, 1, batch), dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false, true>), dim3(cap, 1, batch), dim3(256), 0, s,
+                           p);
+      FROB_LAUNCH_CHECK();
+      return;
+    }
+  }
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 

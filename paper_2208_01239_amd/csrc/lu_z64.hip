@@ -6,6 +6,8 @@
 // registers, so a leaf holds half as many columns as the real one.  The pivot
 // measure is |Re| + |Im| (LAPACK's izamax convention); ties go to the lowest
 // row.
+#include <algorithm>
+
 #include "common.hpp"
 #include "devutil.hpp"
 #include "internal.hpp"
@@ -741,6 +743,7 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
     const int c2 = c1 + w1, w2 = n - c2;
     if (w2 > 0) {
       FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
+      GridCapScope cap(LA_GRID_CAP);   // leave compute units to the panel chain
       update(s1, k0, nb, c2, w2, sn, work1);
       FROB_HIP(hipEventRecord(evR(j), s1));
       last_r = j;
@@ -762,7 +765,7 @@ void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm,
   // the node kernels' workgroup counter lives in the first 64 doubles of work
   int* cnt = reinterpret_cast<int*>(work);
   fill_i32(s, 1, 0, cnt);
-  if (la && la->s1 && n >= LA_MIN) zgetrf_lookahead(s, n, re, im, lda, perm, info, work + 64, cnt, *la);
+  if (getrf_lookahead_on(n, la)) zgetrf_lookahead(s, n, re, im, lda, perm, info, work + 64, cnt, *la);
   else zgetrf_rec(s, re, im, lda, perm, 0, n, n, info, work + 64, cnt);
 }
 

@@ -172,7 +172,7 @@ def test_singular_moore_penrose_example(h):
             gpu_general(h, A, B, shift=shift)
 
 
-@pytest.mark.parametrize("n,p", [(1, 1), (70, 1), (129, 3), (300, 70)])
+@pytest.mark.parametrize("n,p", [(1, 1), (70, 1), (129, 3), (300, 70), (1100, 5)])
 def test_solve(h, n, p):
     import paper_2208_01239_amd as fi
     A, B = inputs.general(n, 3000 + n)
@@ -374,10 +374,11 @@ def test_lookahead_lu_orders(h, n):
     e = relF(Xr, Xi, Rr, Ri)
     print(f"n={n} frobenius relF={e:.2e} tol={tol:.1e}")
     assert e <= tol
-    Zr, Zi, _ = gpu_cinv(h, __import__("paper_2208_01239_amd").frob_cinv_lu, A, B, 1)
-    ez = relF(Zr, Zi, Rr, Ri)
-    print(f"n={n} complex LU relF={ez:.2e}")
-    assert ez <= max(TOL, 16 * np.finfo(float).eps / 2 * np.linalg.cond(A + 1j * B))
+    for form in (1, 0):
+        Zr, Zi, _ = gpu_cinv(h, __import__("paper_2208_01239_amd").frob_cinv_lu, A, B, form)
+        ez = relF(Zr, Zi, Rr, Ri)
+        print(f"n={n} complex LU form {form} relF={ez:.2e}")
+        assert ez <= max(TOL, 16 * np.finfo(float).eps / 2 * np.linalg.cond(A + 1j * B))
 
 
 def _backward_error_cols(A, B, xr, xi, cols):
