@@ -469,6 +469,7 @@ void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, i
 // count themselves on *cnt and the last one writes U12 and resets the counter.
 constexpr int NODE_MAX = 64;
 constexpr int NODE_ROWS = 64;   // rows of A22 per workgroup
+constexpr int NODE_RI = NODE_ROWS / 16;   // rows per thread in the product
 template <int NB>
 __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int lda, const int* __restrict__ perm,
                                                      int k0, int mm, int n1, int n2, int* cnt) {
@@ -491,10 +492,10 @@ __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int
   // unconditionally in one batch, so the loads overlap (one memory latency);
   // out-of-range values are replaced afterwards.  L21 and A22 are fetched up
   // front and wait in registers while U12 is solved.
-  // the product: thread (ti, tj) owns rows ti + 16 i (i < 4), columns tj + 16 j (j < CJ)
+  // the product: thread (ti, tj) owns rows ti + 16 i (i < NODE_RI), columns tj + 16 j (j < CJ)
   constexpr int CJ = NB / 16;
   const int ti = tid >> 4, tj = tid & 15;
-  int pl[PL], pb[PB], px[QB], qr[4];
+  int pl[PL], pb[PB], px[QB], qr[NODE_RI];
 #pragma unroll
   for (int u = 0; u < PL; ++u) pl[u] = perm[k0 + min(er + TPR * u, n1 - 1)];
 #pragma unroll
@@ -502,8 +503,8 @@ __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int
 #pragma unroll
   for (int u = 0; u < QB; ++u) px[u] = perm[k0 + min(4 * u + g, n1 - 1)];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) qr[i] = perm[k0 + min(r0 + ti + 16 * i, mm - 1)];
-  double vl[PL], vb[PB], x[QB], acc[4][CJ];
+  for (int i = 0; i < NODE_RI; ++i) qr[i] = perm[k0 + min(r0 + ti + 16 * i, mm - 1)];
+  double vl[PL], vb[PB], x[QB], acc[NODE_RI][CJ];
   {
     const int cl = k0 + min(ec, n1 - 1), cx = cs + min(c, n2 - 1);
 #pragma unroll
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int
 #pragma unroll
     for (int u = 0; u < PB; ++u) vb[u] = a[(long long)pb[u] * lda + cl];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NODE_RI; ++i)
 #pragma unroll
       for (int j = 0; j < CJ; ++j) acc[i][j] = a[(long long)qr[i] * lda + cs + min(tj + 16 * j, n2 - 1)];
   }
@@ -539,18 +540,18 @@ __global__ __launch_bounds__(256) void k_lu_node_f64(double* __restrict__ a, int
   }
   __syncthreads();
   for (int k = 0; k < n1; ++k) {
-    double lv[4], uv[CJ];
+    double lv[NODE_RI], uv[CJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) lv[i] = Ls[(ti + 16 * i) * LD + k];
+    for (int i = 0; i < NODE_RI; ++i) lv[i] = Ls[(ti + 16 * i) * LD + k];
 #pragma unroll
     for (int j = 0; j < CJ; ++j) uv[j] = Us[k * LD + tj + 16 * j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NODE_RI; ++i)
 #pragma unroll
       for (int j = 0; j < CJ; ++j) acc[i][j] = fma(-lv[i], uv[j], acc[i][j]);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NODE_RI; ++i)
 #pragma unroll
     for (int j = 0; j < CJ; ++j) {
       const int r = r0 + ti + 16 * i, cc = tj + 16 * j;
