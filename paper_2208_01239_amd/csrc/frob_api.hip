@@ -181,15 +181,15 @@ GenWs gen_ws_carve(Carve& c, int n) {
 
 // Steps 1-4 of Algorithm 5 (shared with Algorithm 3): LU of A, Y = A^{-1} B,
 // C = A + B Y, LU of C.
-// With the look-ahead LU, B rides along the LU of A as extra columns (they
-// take L1^{-1} P1 on the second stream, off the panel chain), and with
-// `cinv` the identity rides along the LU of C, leaving L2^{-1} P2 for
-// C^{-1} = U2^{-1} L2^{-1} P2.  Returns whether it did.
+// With the look-ahead LU (orders up to LA_CARRY_MAX), B rides along the LU
+// of A as extra columns (they take L1^{-1} P1 on the second stream, off the
+// panel chain), and with `cinv` the identity rides along the LU of C, leaving
+// L2^{-1} P2 for C^{-1} = U2^{-1} L2^{-1} P2.  Returns whether it did.
 bool frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double* B, int ldb, GenWs& w, int* dinfo,
                    bool cinv) {
   const int ld = w.ld, lf = w.ldF;
   const LookAhead* la = lookahead(w.h);
-  const bool carry = getrf_lookahead_on(n, la);
+  const bool carry = getrf_lookahead_on(n, la) && n <= LA_CARRY_MAX;
   DOp LU1{w.F, lf, w.p1};
   DOut Yo{w.Y, ld, nullptr, nullptr};
   // step 1: P1 A = L1 U1;  step 2: Y = U1^{-1} L1^{-1} P1 B

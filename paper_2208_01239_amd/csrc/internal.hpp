@@ -120,6 +120,10 @@ constexpr int LA_MIN = 1024;
 // Workgroups of a trailing update on the second stream: fewer than the chip
 // holds, so the panel chain's single-workgroup leaves find a free compute unit.
 constexpr int LA_GRID_CAP = 224;
+// Largest order whose Frobenius LUs carry B / the identity as extra columns:
+// the second stream's extra updates (n^3 flops each) fit beside the panel
+// chain at n = 2048 and 4096 (faster) but not at 8192 (slower).
+constexpr int LA_CARRY_MAX = 4096;
 size_t getrf_work_elems(int n);
 void getrf_f64(hipStream_t s, int n, double* a, int lda, int* perm, int* info, double* work,
                const LookAhead* la = nullptr, int q = 0);
