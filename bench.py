@@ -15,7 +15,9 @@ refinement with an FP64 residual) on the same matrices; the batched line
 (2048 matrices, orders uniform in [16, 512], half general and half HPD, one
 persistent launch, FP64 and FP32) beside a per-matrix complex-LU loop on a
 sample of it; and the adjoint (256 HPD matrices of order 256, dM = -X^H G X^H
-by three-multiplication complex products, FP32 and FP64).  The dominant kernel (the n x n x n FP64 matrix-core
+by three-multiplication complex products, FP32 and FP64); Frobenius against
+complex-LU inversion at n = 8192 (same recipe, errors on the oracle's sampled
+columns).  The dominant kernel (the n x n x n FP64 matrix-core
 GEMM) is timed with HIP events on the library's stream during the timed steps
 and reported against the FP64 matrix peak.  The CPU baseline is the FP64
 oracle of the test suite timed on this host on a smaller matrix of the same
@@ -47,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=1536)
     ap.add_argument("--no-mp-large", action="store_true", help="skip the n = 8192 mixed-precision leg")
     ap.add_argument("--mp-n", type=int, default=8192)
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 8192 Frobenius / complex-LU comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -168,6 +171,66 @@ def bench_mp_large(fi, inputs, h, torch, np, log, n):
             del dA, dB, Rr, Ri
             torch.cuda.empty_cache()
     return out
+
+
+def bench_large_order(fi, inputs, h, torch, np, log, n):
+    """Frobenius against complex-LU inversion at order n (8192), same recipe
+    as the headline matrix (A, B iid N(0, 1), seed 0): plain FP64, then one and
+    two Newton-Schulz steps (FP32 and FP64 correction) until the error on the
+    oracle's sampled columns (tests/golden/n<n>_general_samples.npz, when
+    present) is <= 1e-10; the complex-LU baseline in getri and printed form.
+    Two timed runs after one warm-up each."""
+    A, B = inputs.general(n, 0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    Xr = torch.empty_like(dA)
+    Xi = torch.empty_like(dA)
+    gold = os.path.join(ROOT, "tests", "golden", f"n{n}_general_samples.npz")
+    g = np.load(gold, allow_pickle=False) if os.path.exists(gold) else None
+
+    def relf():
+        if g is None:
+            return None
+        gc = g["cols"]
+        gr, gi = Xr[:, gc].cpu().numpy(), Xi[:, gc].cpu().numpy()
+        return float(np.sqrt(np.sum((gr - g["xr"]) ** 2 + (gi - g["xi"]) ** 2) / np.sum(g["xr"] ** 2 + g["xi"] ** 2)))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 2 * 1e3
+
+    out = {"n": n, "gold_samples": g is not None}
+    log(f"[bench] n={n}: frobenius plain")
+    out["frobenius_plain_ms"] = timed(lambda: fi.frob_inv_general(h, dA, dB, Xr, Xi))
+    out["frobenius_plain_relF"] = relf()
+    best = None
+    if out["frobenius_plain_relF"] is not None and out["frobenius_plain_relF"] <= 1e-10:
+        best = ("plain", out["frobenius_plain_ms"])
+    for r in (1, 2):
+        if best is not None:
+            break
+        for f32c in (True, False):
+            tag = f"frobenius_refine{r}{'_f32corr' if f32c else ''}"
+            log(f"[bench] n={n}: {tag}")
+            ms = timed(lambda: fi.frob_inv_general(h, dA, dB, Xr, Xi, refine=r, final_resid=False,
+                                                   f32_correction=f32c))
+            e = relf()
+            out[tag + "_ms"], out[tag + "_relF"] = ms, e
+            if e is not None and e <= 1e-10 and (best is None or ms < best[1]):
+                best = (tag, ms)
+    for form in (1, 0):
+        log(f"[bench] n={n}: complex LU form {form}")
+        out[f"complex_lu_form{form}_ms"] = timed(lambda: fi.frob_cinv_lu(h, dA, dB, Xr, Xi, form=form))
+        out[f"complex_lu_form{form}_relF"] = relf()
+    if best is not None:
+        out["frobenius_at_1e-10"] = {"config": best[0], "ms": best[1]}
+    del dA, dB, Xr, Xi
+    torch.cuda.empty_cache()
+    return {f"n{n}_frobenius_vs_complex_lu": out}
 
 
 def main():
@@ -324,9 +387,12 @@ def main():
         del dAh, dBh
         extra.update(bench_batched(fi, inputs, h, torch, np, log))
         extra.update(bench_adjoint(fi, inputs, h, torch, np, log))
-        if not args.no_mp_large:
+        if not args.no_mp_large or not args.no_large:
             del Xr, Xi
             torch.cuda.empty_cache()
+        if not args.no_large:
+            extra.update(bench_large_order(fi, inputs, h, torch, np, log, 8192))
+        if not args.no_mp_large:
             extra.update(bench_mp_large(fi, inputs, h, torch, np, log, args.mp_n))
 
     cpu = None

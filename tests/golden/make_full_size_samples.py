@@ -9,7 +9,11 @@ exactly these columns).  The spectral condition numbers of M, A and
 C = A + B A^{-1} B are recorded as metadata for the tolerance derivation (they
 are properties of the input, computed with LAPACK).
 
-Usage: python tests/golden/make_full_size_samples.py [n]
+Usage: python tests/golden/make_full_size_samples.py [n] [--general-only]
+
+--general-only writes the general matrix's columns alone, without the
+condition numbers (used for n = 8192, where they would take far longer than
+the inversion).
 """
 import os
 import sys
@@ -26,7 +30,7 @@ from paper_2208_01239_amd import inputs  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def main(n=4096):
+def main(n=4096, general_only=False):
     rng = np.random.default_rng(2208)
     cols = np.sort(rng.choice(n, size=8, replace=False))
     # general matrix: oracle complex LU (Algorithm 4)
@@ -35,6 +39,10 @@ def main(n=4096):
     Xr, Xi, info, _, _ = oracle.cinv_lu(A, B)
     assert info == 0
     print(f"general n={n}: oracle Algorithm 4 in {time.time() - t:.1f} s", flush=True)
+    if general_only:
+        np.savez_compressed(os.path.join(HERE, f"n{n}_general_samples.npz"), cols=cols, xr=Xr[:, cols],
+                            xi=Xi[:, cols], a00=A[0, :4], b00=B[0, :4])
+        return
     kM = float(np.linalg.cond(A + 1j * B))
     kA = float(np.linalg.cond(A))
     C = A + B @ np.linalg.solve(A, B)
@@ -54,4 +62,5 @@ def main(n=4096):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 4096)
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    main(int(args[0]) if args else 4096, general_only="--general-only" in sys.argv)
