@@ -49,6 +49,24 @@ __global__ void k_axpby(int m, int n, double a, const double* __restrict__ X, in
   *y = (b == 0.0) ? a * x : a * x + b * *y;
 }
 
+// Z = a X + b Y
+__global__ void k_lincomb(int m, int n, double a, const double* __restrict__ X, int ldx, double b,
+                          const double* __restrict__ Y, int ldy, double* __restrict__ Z, int ldz) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  Z[(long long)i * ldz + j] = a * X[(long long)i * ldx + j] + b * Y[(long long)i * ldy + j];
+}
+
+// Xr += P - Q, Xi += P + Q
+__global__ void k_acc_rot(int m, int n, const double* __restrict__ P, int ldp, const double* __restrict__ Q, int ldq,
+                          double* __restrict__ Xr, double* __restrict__ Xi, int ldx) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  const double p = P[(long long)i * ldp + j], q = Q[(long long)i * ldq + j];
+  Xr[(long long)i * ldx + j] += p - q;
+  Xi[(long long)i * ldx + j] += p + q;
+}
+
 // R <- I - R (real and imaginary planes), sumsq += ||R||_F^2.  A block
 // covers RESID_ROWS rows (one atomic per block: few enough that the atomics
 // on the single accumulator do not serialize the kernel).
@@ -146,6 +164,20 @@ void identity_f64(hipStream_t s, int n, double* dst, int ldd) {
 void axpby_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, double* Y, int ldy) {
   if (m <= 0 || n <= 0) return;
   hipLaunchKernelGGL(k_axpby, grid2d(m, n), dim3(EB), 0, s, m, n, a, X, ldx, b, Y, ldy);
+  FROB_LAUNCH_CHECK();
+}
+
+void lincomb_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, const double* Y, int ldy,
+                 double* Z, int ldz) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_lincomb, grid2d(m, n), dim3(EB), 0, s, m, n, a, X, ldx, b, Y, ldy, Z, ldz);
+  FROB_LAUNCH_CHECK();
+}
+
+void acc_rot_f64(hipStream_t s, int m, int n, const double* P, int ldp, const double* Q, int ldq, double* Xr,
+                 double* Xi, int ldx) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_acc_rot, grid2d(m, n), dim3(EB), 0, s, m, n, P, ldp, Q, ldq, Xr, Xi, ldx);
   FROB_LAUNCH_CHECK();
 }
 

@@ -150,6 +150,12 @@ void fill_f64(hipStream_t s, int m, int n, double v, double* dst, int ldd);
 void identity_f64(hipStream_t s, int n, double* dst, int ldd);
 // Y = a X + b Y  (m x n)
 void axpby_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, double* Y, int ldy);
+// Z = a X + b Y
+void lincomb_f64(hipStream_t s, int m, int n, double a, const double* X, int ldx, double b, const double* Y, int ldy,
+                 double* Z, int ldz);
+// Xr += P - Q, Xi += P + Q
+void acc_rot_f64(hipStream_t s, int m, int n, const double* P, int ldp, const double* Q, int ldq, double* Xr,
+                 double* Xi, int ldx);
 // (X1, X2) = (A - mu B, mu A + B): shift in; used in-place-safe on distinct buffers
 void rotate_f64(hipStream_t s, int m, int n, double mu, const double* A, int lda, const double* B, int ldb,
                 double* X1, int ld1, double* X2, int ld2);

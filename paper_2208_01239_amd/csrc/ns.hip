@@ -34,10 +34,8 @@ static void gauss3m(hipStream_t s, int n, const double* Pr, int ldp, const doubl
                     const double* Si, double* Zr, double* Zi, int ldz, double* T1, double* T2) {
   const int ld = n;
   // T1 = P_r - P_i, T2 = S_r + S_i
-  copy_f64(s, n, n, Pr, ldp, nullptr, T1, ld);
-  axpby_f64(s, n, n, -1.0, Pi, ldp, 1.0, T1, ld);
-  copy_f64(s, n, n, Sr, lds, nullptr, T2, ld);
-  axpby_f64(s, n, n, 1.0, Si, lds, 1.0, T2, ld);
+  lincomb_f64(s, n, n, 1.0, Pr, ldp, -1.0, Pi, ldp, T1, ld);
+  lincomb_f64(s, n, n, 1.0, Sr, lds, 1.0, Si, lds, T2, ld);
   // Zi = M2 = P_r S_i ; Zr = M3 = P_i S_r
   gemm_f64(s, false, false, n, n, n, 1.0, DOp{Pr, ldp, nullptr}, TRI_NONE, DOp{Si, lds, nullptr}, TRI_NONE, 0.0,
            DOut{Zi, ldz, nullptr, nullptr});
@@ -87,13 +85,21 @@ frob_status_t ns_refine(frob_handle* h, int n, const double* A, int lda, const d
     if (rho <= tol) break;                              // converged
     if (k > 0 && rho > 0.5 * prev) break;               // no longer contracting: rounding floor reached
     if (k == max_steps) break;
-    // X <- X + X R
+    // X <- X + X R, the three products of Gauss's scheme accumulated into X:
+    // M2 = Xr Ri, M3 = Xi Rr, then X += (M3 - M2, M3 + M2), then
+    // Re X += M1 = (Xr - Xi)(Rr + Ri) (its factors taken before X changes)
     {
       LowPrecScope lp(cprec);
-      gauss3m(s, n, Xr, ldx, Xi, Rr, n, Ri, Ur, Ui, n, T1, T2);
+      lincomb_f64(s, n, n, 1.0, Xr, ldx, -1.0, Xi, ldx, T1, n);
+      lincomb_f64(s, n, n, 1.0, Rr, n, 1.0, Ri, n, T2, n);
+      gemm_f64(s, false, false, n, n, n, 1.0, DOp{Xr, ldx, nullptr}, TRI_NONE, DOp{Ri, n, nullptr}, TRI_NONE, 0.0,
+               DOut{Ui, n, nullptr, nullptr});
+      gemm_f64(s, false, false, n, n, n, 1.0, DOp{Xi, ldx, nullptr}, TRI_NONE, DOp{Rr, n, nullptr}, TRI_NONE, 0.0,
+               DOut{Ur, n, nullptr, nullptr});
+      acc_rot_f64(s, n, n, Ur, n, Ui, n, Xr, Xi, ldx);
+      gemm_f64(s, false, false, n, n, n, 1.0, DOp{T1, n, nullptr}, TRI_NONE, DOp{T2, n, nullptr}, TRI_NONE, 1.0,
+               DOut{Xr, ldx, nullptr, nullptr});
     }
-    axpby_f64(s, n, n, 1.0, Ur, n, 1.0, Xr, ldx);
-    axpby_f64(s, n, n, 1.0, Ui, n, 1.0, Xi, ldx);
     prev = rho;
     ++steps;
   }
