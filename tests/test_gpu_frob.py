@@ -327,6 +327,45 @@ def test_full_size_general_n4096(h):
     torch.cuda.empty_cache()
 
 
+def test_full_size_general_n8192(h):
+    """n = 8192, the same recipe (A, B iid N(0,1), seed 0): sampled columns
+    against the oracle's Algorithm 4 (stored; generated without condition
+    numbers).  One Newton-Schulz step (FP32 and FP64 correction) and the
+    complex-LU baseline (both forms) are held to the 1e-10 bar; the plain
+    FP64 result only to 1e-7 (its error, about u kappa(C), was not bounded
+    from kappa(C) here)."""
+    g = _golden("n8192_general_samples.npz")
+    n = 8192
+    A, B = inputs.general(n, 0)
+    assert np.array_equal(A[0, :4], g["a00"]) and np.array_equal(B[0, :4], g["b00"])
+    import paper_2208_01239_amd as fi
+    import torch
+    cols = g["cols"]
+    dA, dB = to_dev(A), to_dev(B)
+    Xr = torch.empty_like(dA)
+    Xi = torch.empty_like(dA)
+
+    def err():
+        return relF(Xr[:, cols].cpu().numpy(), Xi[:, cols].cpu().numpy(), g["xr"], g["xi"])
+    fi.frob_inv_general(h, dA, dB, Xr, Xi)
+    e0 = err()
+    fi.frob_inv_general(h, dA, dB, Xr, Xi, refine=1, f32_correction=True)
+    e32 = err()
+    fi.frob_inv_general(h, dA, dB, Xr, Xi, refine=1)
+    e64 = err()
+    ez = []
+    for form in (1, 0):
+        fi.frob_cinv_lu(h, dA, dB, Xr, Xi, form=form)
+        ez.append(err())
+    print(f"n=8192 general: relF plain={e0:.2e}, one step FP32 / FP64 correction {e32:.2e} / {e64:.2e}; "
+          f"complex LU forms 1 / 0 {ez[0]:.2e} / {ez[1]:.2e}")
+    assert e0 <= 1e-7
+    assert e32 <= TOL and e64 <= TOL
+    assert max(ez) <= TOL
+    del dA, dB, Xr, Xi
+    torch.cuda.empty_cache()
+
+
 def test_full_size_hpd_n4096(h):
     """n = 4096 HPD (Z Z^H + n I, seed 1): Algorithm 7 on the GPU against the
     oracle's Algorithm 8 on sampled columns, at 1e-10."""
