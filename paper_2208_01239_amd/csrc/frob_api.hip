@@ -385,26 +385,41 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     Carve sz(nullptr);
-    for (int k = 0; k < 4; ++k) sz.take<double>(nn);
+    for (int k = 0; k < 5; ++k) sz.take<double>(nn);
     sz.take<double>(solver_work_elems(n));
+    sz.take<double>(trsm_work_elems(n));
     sz.take<char>(ns_ws_bytes(n, o.refine));
     Carve c((char*)ws_reserve(h, sz.off));
-    double* F = c.take<double>(nn);   // R1^T (lower), later W = R2^{-T}
+    double* F = c.take<double>(nn);   // R1^T (lower)
+    double* Wm = c.take<double>(nn);  // W = R2^{-T} (F stays readable for the concurrent solve)
     double* X1 = c.take<double>(nn);
     double* Y = c.take<double>(nn);
     double* Cm = c.take<double>(nn);  // C, then R2^T
     double* tmp = c.take<double>(solver_work_elems(n));
+    double* tmp1 = c.take<double>(trsm_work_elems(n));   // the second stream's solve
     const int ld = n;
     fill_i32(s, INFO_SLOTS, 0, h->dinfo);
     std::unique_ptr<LowPrecScope> lp(new LowPrecScope(o.prec));
     // step 1: A = R1^T R1 (stored as the lower factor L1 = R1^T)
     copy_f64(s, n, n, A, lda, nullptr, F, ld);
     potrf_f64(s, n, F, ld, h->dinfo + 0, tmp);
-    // steps 2-3: R1^T X1 = B (forward), R1 Y = X1 (backward)
+    // step 2: R1^T X1 = B (forward)
     copy_f64(s, n, n, B, ldb, nullptr, X1, ld);
     trsm_f64(s, false, TRI_LOWER, false, n, n, DOp{F, ld, nullptr}, DOut{X1, ld, nullptr, nullptr}, tmp);
     copy_f64(s, n, n, X1, ld, nullptr, Y, ld);
-    trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr}, tmp);
+    // step 3: R1 Y = X1 (backward).  Y is needed only by step 9, so from
+    // n = LA_MIN this solve runs on the second stream beside steps 4-8 (a
+    // latency-bound Cholesky chain), its products on a capped grid.
+    const LookAhead* la = n >= LA_MIN ? lookahead(h) : nullptr;
+    if (la) {
+      FROB_HIP(hipEventRecord(la->ev[0], s));
+      FROB_HIP(hipStreamWaitEvent(la->s1, la->ev[0], 0));
+      GridCapScope cap(LA_GRID_CAP);
+      trsm_f64(la->s1, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr}, tmp1);
+      FROB_HIP(hipEventRecord(la->ev[4], la->s1));
+    } else {
+      trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr}, tmp);
+    }
     // steps 4-5: C = A - X1^T X1 (B skew gives B A^{-1} B = -X1^T X1), lower triangle
     copy_f64(s, n, n, A, lda, nullptr, Cm, ld);
     gemm_f64(s, true, false, n, n, n, -1.0, DOp{X1, ld, nullptr}, TRI_NONE, DOp{X1, ld, nullptr}, TRI_NONE, 1.0,
@@ -412,11 +427,12 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     // step 6: C = R2^T R2
     potrf_f64(s, n, Cm, ld, h->dinfo + 1, tmp);
     // steps 7-8: Re X = C^{-1} = R2^{-1} R2^{-T} = W^T W with W = (R2^T)^{-1} lower
-    trtri_f64(s, TRI_LOWER, false, n, DOp{Cm, ld, nullptr}, F, ld, tmp);
-    gemm_f64(s, true, false, n, n, n, 1.0, DOp{F, ld, nullptr}, TRI_UPPER, DOp{F, ld, nullptr}, TRI_LOWER, 0.0,
+    trtri_f64(s, TRI_LOWER, false, n, DOp{Cm, ld, nullptr}, Wm, ld, tmp);
+    gemm_f64(s, true, false, n, n, n, 1.0, DOp{Wm, ld, nullptr}, TRI_UPPER, DOp{Wm, ld, nullptr}, TRI_LOWER, 0.0,
              DOut{Xr, ldx, nullptr, nullptr}, true);
     mirror_lower_f64(s, n, Xr, ldx, 1.0);
     // step 9: Im X = -Y C^{-1}
+    if (la) FROB_HIP(hipStreamWaitEvent(s, la->ev[4], 0));
     {
       ProfScope ps(h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
       gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,

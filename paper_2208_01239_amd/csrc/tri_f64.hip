@@ -235,58 +235,70 @@ void dinv_f64(hipStream_t s, int tri, bool trans, int n, DOp T, int nb, double* 
 }
 
 // ------------------------------------------------------------------------
-// Blocked triangular solve.  The inverses of the 128x128 diagonal blocks of
-// op(T) are formed first (dinv_f64); the recursion then needs only GEMMs: a
-// leaf is X_b = inv(T_bb) B_b computed in place by one GEMM whose block row
-// (or block column) covers the whole leaf, and each inner node updates the
-// other half's right-hand side with one GEMM.
+// Blocked triangular solve.  The inverses of the diagonal blocks of op(T) are
+// formed first (dinv_f64); the recursion then needs only GEMMs: a leaf is
+// X_b = inv(T_bb) B_b, and each inner node updates the other half's
+// right-hand side with one GEMM.  Leaves of DNB = 128 are computed in place
+// by one GEMM whose block row (or block column) covers the whole leaf.  Left
+// solves with no row indirection on B and nr <= nt take leaves of DNB_OUT =
+// 512 instead, computed out of place into a scratch block and copied back: a
+// quarter of the leaf launches and of the small inner-node GEMMs.
 // ------------------------------------------------------------------------
 namespace {
 constexpr int DNB = 128;
+constexpr int DNB_OUT = 512;
 
 void trsm_rec(hipStream_t s, bool right, bool lower, bool trans, int r0, int nt, int nr, DOp T, DOut B, const double* D,
-              int ldd) {
-  if (nt <= DNB) {
+              int ldd, int dnb, double* sx) {
+  if (nt <= dnb) {
     DOp Di{D + (long long)r0 * ldd + r0, ldd, nullptr};
     const int triD = lower ? TRI_LOWER : TRI_UPPER;
-    if (!right)
+    if (sx) {
+      // left solve, out of place: sx = inv(T_bb) B_b (nt x nr, ld nr), then B_b = sx
+      gemm_f64(s, false, false, nt, nr, nt, 1.0, Di, triD, as_op(B), TRI_NONE, 0.0, DOut{sx, nr, nullptr, nullptr});
+      copy_f64(s, nt, nr, sx, nr, nullptr, B.p, B.ld);
+    } else if (!right) {
       gemm_f64(s, false, false, nt, nr, nt, 1.0, Di, triD, as_op(B), TRI_NONE, 0.0, B, false, 1, 0, 0, 0,
                GEMM_NEED_FULL_M);
-    else
+    } else {
       gemm_f64(s, false, false, nr, nt, nt, 1.0, as_op(B), TRI_NONE, Di, triD, 0.0, B, false, 1, 0, 0, 0,
                GEMM_NEED_FULL_N);
+    }
     return;
   }
-  const int nblk = ceil_div(nt, DNB);
-  const int n1 = (nblk / 2) * DNB, n2 = nt - n1;
+  const int nblk = ceil_div(nt, dnb);
+  const int n1 = (nblk / 2) * dnb, n2 = nt - n1;
   DOp T21 = dopsub(T, trans, r0 + n1, r0), T12 = dopsub(T, trans, r0, r0 + n1);
   if (!right) {
     DOut B1 = osub(B, 0, 0), B2 = osub(B, n1, 0);
     if (lower) {
-      trsm_rec(s, false, lower, trans, r0, n1, nr, T, B1, D, ldd);
+      trsm_rec(s, false, lower, trans, r0, n1, nr, T, B1, D, ldd, dnb, sx);
       gemm_f64(s, trans, false, n2, nr, n1, -1.0, T21, TRI_NONE, as_op(B1), TRI_NONE, 1.0, B2);
-      trsm_rec(s, false, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd);
+      trsm_rec(s, false, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd, dnb, sx);
     } else {
-      trsm_rec(s, false, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd);
+      trsm_rec(s, false, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd, dnb, sx);
       gemm_f64(s, trans, false, n1, nr, n2, -1.0, T12, TRI_NONE, as_op(B2), TRI_NONE, 1.0, B1);
-      trsm_rec(s, false, lower, trans, r0, n1, nr, T, B1, D, ldd);
+      trsm_rec(s, false, lower, trans, r0, n1, nr, T, B1, D, ldd, dnb, sx);
     }
   } else {
     DOut B1 = osub(B, 0, 0), B2 = osub(B, 0, n1);
     if (lower) {
-      trsm_rec(s, true, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd);
+      trsm_rec(s, true, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd, dnb, sx);
       gemm_f64(s, false, trans, nr, n1, n2, -1.0, as_op(B2), TRI_NONE, T21, TRI_NONE, 1.0, B1);
-      trsm_rec(s, true, lower, trans, r0, n1, nr, T, B1, D, ldd);
+      trsm_rec(s, true, lower, trans, r0, n1, nr, T, B1, D, ldd, dnb, sx);
     } else {
-      trsm_rec(s, true, lower, trans, r0, n1, nr, T, B1, D, ldd);
+      trsm_rec(s, true, lower, trans, r0, n1, nr, T, B1, D, ldd, dnb, sx);
       gemm_f64(s, false, trans, nr, n2, n1, -1.0, as_op(B1), TRI_NONE, T12, TRI_NONE, 1.0, B2);
-      trsm_rec(s, true, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd);
+      trsm_rec(s, true, lower, trans, r0 + n1, n2, nr, T, B2, D, ldd, dnb, sx);
     }
   }
 }
 }  // namespace
 
-size_t trsm_work_elems(int nt) { return (size_t)nt * nt + (size_t)nt * (DNB / 4) + 4096; }
+// D (nt x nt), the doubling scratch of dinv_f64 and the out-of-place leaf block
+size_t trsm_work_elems(int nt) {
+  return (size_t)nt * nt + (size_t)nt * (DNB_OUT / 4) + (size_t)DNB_OUT * nt + 4096;
+}
 
 void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DOp T, DOut B, double* work) {
   if (nt <= 0 || nr <= 0) return;
@@ -295,10 +307,13 @@ void trsm_f64(hipStream_t s, bool right, int tri, bool trans, int nt, int nr, DO
     return;
   }
   if (B.cols) throw std::runtime_error("trsm_f64: column scatter not supported");
+  const bool out = !right && !B.rows && nr <= nt && nt > DNB;
+  const int dnb = out ? DNB_OUT : DNB;
   double* D = work;
   double* tmp = work + (size_t)nt * nt;
-  dinv_f64(s, tri, trans, nt, T, DNB, D, nt, tmp);
-  trsm_rec(s, right, host_lower(tri), trans, 0, nt, nr, T, B, D, nt);
+  double* sx = out ? tmp + (size_t)nt * (DNB_OUT / 4) + 4096 : nullptr;
+  dinv_f64(s, tri, trans, nt, T, dnb, D, nt, tmp);
+  trsm_rec(s, right, host_lower(tri), trans, 0, nt, nr, T, B, D, nt, dnb, sx);
 }
 
 size_t trtri_tmp_elems(int n) {
