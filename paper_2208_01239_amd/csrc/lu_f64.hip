@@ -58,12 +58,14 @@ constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 constexpr bool LEAF_SIBLING(int R) { return R <= 16; }
 // leaves whose panel and sibling blocks are written back together through LDS
 constexpr bool LEAF_JOINT_STORE(int W) { return W <= 8; }
+// panels of 2049 .. 4096 rows: 1024-thread leaves (R = 4, W = 4) instead of 512 (R = 8)
+constexpr bool LEAF_WIDE_T = true;
 
-template <int R, int W>
-__global__ __launch_bounds__(LEAF_NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm,
-                                                         int k0, int mm, int nc, int n2, int* info,
-                                                         int* __restrict__ snap, int sfrom) {
-  constexpr int NT = LEAF_NT, NW = NT / 64;
+template <int R, int W, int NT = LEAF_NT>
+__global__ __launch_bounds__(NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm, int k0,
+                                                    int mm, int nc, int n2, int* info, int* __restrict__ snap,
+                                                    int sfrom) {
+  constexpr int NW = NT / 64;
   static_assert(W % 2 == 0 && NW <= 16, "leaf shape");
   __shared__ double s_cv[2][NW];
   __shared__ int s_ck[2][NW];
@@ -454,6 +456,10 @@ void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, i
   if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 8 && LEAF_WIDE_T)
+    // 1024 threads of four rows each: half the per-column work of a thread
+    hipLaunchKernelGGL((k_lu_leaf_f64<4, 4, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2, info,
+                       snap, sfrom);
   else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_f64<8, 4>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_f64<16, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_f64<32, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);

@@ -37,6 +37,8 @@ __device__ __forceinline__ zc zrecip(zc z) {
 constexpr bool ZLEAF_SIBLING(int R) { return R <= 8; }
 // leaves whose panel and sibling blocks move together, transposed through LDS
 constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
+// panels of 2049 .. 4096 rows: 1024-thread leaves (R = 4, W = 2) instead of 512 (R = 8)
+constexpr bool ZLEAF_WIDE_T = true;
 
 // One workgroup factors an mm x nc complex panel (nc <= W) held in
 // registers, thread t owning panel rows q = t + s * ZLT (s < R).  The design
@@ -48,11 +50,11 @@ constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
 // whole bottom recursion node (the n2 columns to the right are updated with
 // U12 = L11^{-1} A12, A22 -= L21 U12 and factored as panel columns
 // nc .. nc + n2).
-template <int R, int W>
-__global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, double* __restrict__ ai, int lda,
-                                                     int* __restrict__ perm, int k0, int mm, int nc, int n2,
-                                                     int* info, int* __restrict__ snap, int sfrom) {
-  constexpr int NW = ZLT / 64;
+template <int R, int W, int NT = ZLT>
+__global__ __launch_bounds__(NT) void k_lu_leaf_z64(double* __restrict__ ar, double* __restrict__ ai, int lda,
+                                                    int* __restrict__ perm, int k0, int mm, int nc, int n2, int* info,
+                                                    int* __restrict__ snap, int sfrom) {
+  constexpr int NW = NT / 64;
   __shared__ double s_cv[2][NW];
   __shared__ int s_ck[2][NW];
   __shared__ double s_crr[2][NW][W], s_cri[2][NW][W];
@@ -70,9 +72,9 @@ __global__ __launch_bounds__(ZLT) void k_lu_leaf_z64(double* __restrict__ ar, do
 
   int ph[R], pos[R];
 #pragma unroll
-  for (int s = 0; s < R; ++s) ph[s] = perm[k0 + min(t + s * ZLT, mm - 1)];
+  for (int s = 0; s < R; ++s) ph[s] = perm[k0 + min(t + s * NT, mm - 1)];
 #pragma unroll
-  for (int s = 0; s < R; ++s) pos[s] = t + s * ZLT < mm ? t + s * ZLT : -1;
+  for (int s = 0; s < R; ++s) pos[s] = t + s * NT < mm ? t + s * NT : -1;
 
   // columns col0 .. col0 + ncol - 1 of this thread's rows (both planes), one
   // batch of unconditional loads at clamped addresses
@@ -475,6 +477,10 @@ void zlaunch_leaf(hipStream_t s, double* ar, double* ai, int lda, int* perm, int
   if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 8 && ZLEAF_WIDE_T)
+    // 1024 threads of four rows each: half the per-column work of a thread
+    hipLaunchKernelGGL((k_lu_leaf_z64<4, 2, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
+                       info, snap, sfrom);
   else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_z64<8, 2>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_z64<16, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_z64<32, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
