@@ -58,7 +58,8 @@ constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 constexpr bool LEAF_SIBLING(int R) { return R <= 16; }
 // leaves whose panel and sibling blocks are written back together through LDS
 constexpr bool LEAF_JOINT_STORE(int W) { return W <= 8; }
-// panels of 2049 .. 4096 rows: 1024-thread leaves (R = 4, W = 4) instead of 512 (R = 8)
+// panels of 513 .. 4096 rows: 1024-thread leaves with half the rows per
+// thread of the 512-thread ones (same widths)
 constexpr bool LEAF_WIDE_T = true;
 
 template <int R, int W, int NT = LEAF_NT>
@@ -454,7 +455,13 @@ void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, i
   if (n2 > 0 && !LEAF_SIBLING(R)) throw std::runtime_error("getrf_f64: no fused sibling update for this leaf");
   dim3 g(1), b(LEAF_NT);
   if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 2 && LEAF_WIDE_T)
+    hipLaunchKernelGGL((k_lu_leaf_f64<1, 16, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2,
+                       info, snap, sfrom);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 4 && LEAF_WIDE_T)
+    hipLaunchKernelGGL((k_lu_leaf_f64<2, 8, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2,
+                       info, snap, sfrom);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 8 && LEAF_WIDE_T)
     // 1024 threads of four rows each: half the per-column work of a thread

@@ -37,7 +37,8 @@ __device__ __forceinline__ zc zrecip(zc z) {
 constexpr bool ZLEAF_SIBLING(int R) { return R <= 8; }
 // leaves whose panel and sibling blocks move together, transposed through LDS
 constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
-// panels of 2049 .. 4096 rows: 1024-thread leaves (R = 4, W = 2) instead of 512 (R = 8)
+// panels of 513 .. 4096 rows: 1024-thread leaves with half the rows per
+// thread of the 512-thread ones (same widths)
 constexpr bool ZLEAF_WIDE_T = true;
 
 // One workgroup factors an mm x nc complex panel (nc <= W) held in
@@ -475,7 +476,13 @@ void zlaunch_leaf(hipStream_t s, double* ar, double* ai, int lda, int* perm, int
   if (n2 > 0 && !ZLEAF_SIBLING(R)) throw std::runtime_error("getrf_z64: no fused sibling update for this leaf");
   dim3 g(1), b(ZLT);
   if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 2 && ZLEAF_WIDE_T)
+    hipLaunchKernelGGL((k_lu_leaf_z64<1, 8, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
+                       info, snap, sfrom);
   else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  else if (R <= 4 && ZLEAF_WIDE_T)
+    hipLaunchKernelGGL((k_lu_leaf_z64<2, 4, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
+                       info, snap, sfrom);
   else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   else if (R <= 8 && ZLEAF_WIDE_T)
     // 1024 threads of four rows each: half the per-column work of a thread
