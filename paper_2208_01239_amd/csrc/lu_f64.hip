@@ -3,9 +3,10 @@
 // Recursive column splitting: factor the left half, solve U12 = L11^{-1} A12,
 // update A22 -= L21 U12 with one matrix-core GEMM, factor the right half.  The
 // recursion stops at a "leaf" panel narrow enough to live in the registers of
-// one 512-thread workgroup (rows-per-thread x columns <= 64 doubles per
-// thread), where the pivot search is a DPP max-reduction per wave followed by
-// an 8-slot reduction, with the lowest row index winning ties.
+// one workgroup of 512 or 1024 threads (rows-per-thread x columns <= 32
+// doubles per thread and block), where the pivot search is a DPP
+// max-reduction per wave followed by a reduction over the waves' slots, with
+// the lowest row index winning ties.
 //
 // Pivoting never moves data: rows are addressed through the index array perm
 // (logical row i of P A lives in physical row perm[i]), so a row interchange
@@ -24,10 +25,10 @@ namespace frob {
 
 namespace {
 
-constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
+constexpr int LEAF_NT = 512;        // threads of the leaf workgroup (twice that for 513 .. 4096 rows)
 
-// One workgroup factors an mm x nc panel (nc <= W) held in registers.  Thread
-// t owns panel rows q = t + s * LEAF_NT (s < R).  Rows never move: each row
+// One workgroup of NT threads factors an mm x nc panel (nc <= W) held in
+// registers.  Thread t owns panel rows q = t + s * NT (s < R).  Rows never move: each row
 // carries its current logical position pos (GEPP's row interchanges act on
 // these integers only), so a pivot step exchanges no data between threads.
 // Per column j:
@@ -58,9 +59,6 @@ constexpr int LEAF_NT = 512;        // threads of the leaf workgroup
 constexpr bool LEAF_SIBLING(int R) { return R <= 16; }
 // leaves whose panel and sibling blocks are written back together through LDS
 constexpr bool LEAF_JOINT_STORE(int W) { return W <= 8; }
-// panels of 513 .. 4096 rows: 1024-thread leaves with half the rows per
-// thread of the 512-thread ones (same widths)
-constexpr bool LEAF_WIDE_T = true;
 
 template <int R, int W, int NT = LEAF_NT>
 __global__ __launch_bounds__(NT) void k_lu_leaf_f64(double* __restrict__ a, int lda, int* __restrict__ perm, int k0,
@@ -453,24 +451,18 @@ void launch_leaf(hipStream_t s, double* a, int lda, int* perm, int k0, int mm, i
   const int R = ceil_div(mm, LEAF_NT);
   if (nc > leaf_width(mm) || n2 > leaf_width(mm)) throw std::runtime_error("getrf_f64: leaf wider than its template");
   if (n2 > 0 && !LEAF_SIBLING(R)) throw std::runtime_error("getrf_f64: no fused sibling update for this leaf");
-  dim3 g(1), b(LEAF_NT);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_f64<1, 32>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 2 && LEAF_WIDE_T)
-    hipLaunchKernelGGL((k_lu_leaf_f64<1, 16, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2,
-                       info, snap, sfrom);
-  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_f64<2, 16>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 4 && LEAF_WIDE_T)
-    hipLaunchKernelGGL((k_lu_leaf_f64<2, 8, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2,
-                       info, snap, sfrom);
-  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_f64<4, 8>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 8 && LEAF_WIDE_T)
-    // 1024 threads of four rows each: half the per-column work of a thread
-    hipLaunchKernelGGL((k_lu_leaf_f64<4, 4, 2 * LEAF_NT>), g, dim3(2 * LEAF_NT), 0, s, a, lda, perm, k0, mm, nc, n2, info,
-                       snap, sfrom);
-  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_f64<8, 4>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_f64<16, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_f64<32, 2>), g, b, 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  // 1024 threads for 513 .. 4096 rows (half the rows per thread of a 512-thread
+  // leaf of the same width), 512 otherwise
+  void (*kern)(double*, int, int*, int, int, int, int, int*, int*, int);
+  int threads = 2 * LEAF_NT;
+  if (R <= 1) { kern = k_lu_leaf_f64<1, 32>; threads = LEAF_NT; }
+  else if (R <= 2) kern = k_lu_leaf_f64<1, 16, 2 * LEAF_NT>;
+  else if (R <= 4) kern = k_lu_leaf_f64<2, 8, 2 * LEAF_NT>;
+  else if (R <= 8) kern = k_lu_leaf_f64<4, 4, 2 * LEAF_NT>;
+  else if (R <= 16) { kern = k_lu_leaf_f64<16, 2>; threads = LEAF_NT; }
+  else if (R <= 32) { kern = k_lu_leaf_f64<32, 2>; threads = LEAF_NT; }
   else throw std::runtime_error("getrf_f64: matrix order above 16384 is not supported");
+  hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, s, a, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   FROB_LAUNCH_CHECK();
 }
 

@@ -1,7 +1,7 @@
 // lu_z64.hip -- complex (planar FP64) LU with partial pivoting for the
 // complex-arithmetic baseline (Algorithm 4).  Same design as lu_f64.hip:
-// recursive column splitting, register-resident leaf panels in one 512-thread
-// workgroup with position-tracked rows, pivoting through the row-index array
+// recursive column splitting, register-resident leaf panels in one workgroup
+// (512 or 1024 threads) with position-tracked rows, pivoting through the row-index array
 // perm, one launch per bottom recursion node.  A complex value takes two
 // registers, so a leaf holds half as many columns as the real one.  The pivot
 // measure is |Re| + |Im| (LAPACK's izamax convention); ties go to the lowest
@@ -17,7 +17,7 @@ namespace frob {
 
 namespace {
 
-constexpr int ZLT = 512;   // threads of the leaf workgroup
+constexpr int ZLT = 512;   // threads of the leaf workgroup (twice that for 513 .. 4096 rows)
 
 struct zc {
   double r, i;
@@ -37,12 +37,9 @@ __device__ __forceinline__ zc zrecip(zc z) {
 constexpr bool ZLEAF_SIBLING(int R) { return R <= 8; }
 // leaves whose panel and sibling blocks move together, transposed through LDS
 constexpr bool ZLEAF_JOINT(int W) { return W % 2 == 0 && W <= 8; }
-// panels of 513 .. 4096 rows: 1024-thread leaves with half the rows per
-// thread of the 512-thread ones (same widths)
-constexpr bool ZLEAF_WIDE_T = true;
 
 // One workgroup factors an mm x nc complex panel (nc <= W) held in
-// registers, thread t owning panel rows q = t + s * ZLT (s < R).  The design
+// registers, thread t of NT owning panel rows q = t + s * NT (s < R).  The design
 // is the real leaf's (lu_f64.hip): rows never move, each carries its logical
 // position pos and a pivot step exchanges positions only; the candidate
 // search runs on FP32 images of the pivot measure |Re| + |Im| with the exact
@@ -474,24 +471,18 @@ void zlaunch_leaf(hipStream_t s, double* ar, double* ai, int lda, int* perm, int
   const int R = ceil_div(mm, ZLT);
   if (nc > zleaf_width(mm) || n2 > zleaf_width(mm)) throw std::runtime_error("getrf_z64: leaf wider than template");
   if (n2 > 0 && !ZLEAF_SIBLING(R)) throw std::runtime_error("getrf_z64: no fused sibling update for this leaf");
-  dim3 g(1), b(ZLT);
-  if (R <= 1) hipLaunchKernelGGL((k_lu_leaf_z64<1, 16>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 2 && ZLEAF_WIDE_T)
-    hipLaunchKernelGGL((k_lu_leaf_z64<1, 8, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
-                       info, snap, sfrom);
-  else if (R <= 2) hipLaunchKernelGGL((k_lu_leaf_z64<2, 8>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 4 && ZLEAF_WIDE_T)
-    hipLaunchKernelGGL((k_lu_leaf_z64<2, 4, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
-                       info, snap, sfrom);
-  else if (R <= 4) hipLaunchKernelGGL((k_lu_leaf_z64<4, 4>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 8 && ZLEAF_WIDE_T)
-    // 1024 threads of four rows each: half the per-column work of a thread
-    hipLaunchKernelGGL((k_lu_leaf_z64<4, 2, 2 * ZLT>), g, dim3(2 * ZLT), 0, s, ar, ai, lda, perm, k0, mm, nc, n2,
-                       info, snap, sfrom);
-  else if (R <= 8) hipLaunchKernelGGL((k_lu_leaf_z64<8, 2>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 16) hipLaunchKernelGGL((k_lu_leaf_z64<16, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
-  else if (R <= 32) hipLaunchKernelGGL((k_lu_leaf_z64<32, 1>), g, b, 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
+  // 1024 threads for 513 .. 4096 rows (half the rows per thread of a 512-thread
+  // leaf of the same width), 512 otherwise
+  void (*kern)(double*, double*, int, int*, int, int, int, int, int*, int*, int);
+  int threads = 2 * ZLT;
+  if (R <= 1) { kern = k_lu_leaf_z64<1, 16>; threads = ZLT; }
+  else if (R <= 2) kern = k_lu_leaf_z64<1, 8, 2 * ZLT>;
+  else if (R <= 4) kern = k_lu_leaf_z64<2, 4, 2 * ZLT>;
+  else if (R <= 8) kern = k_lu_leaf_z64<4, 2, 2 * ZLT>;
+  else if (R <= 16) { kern = k_lu_leaf_z64<16, 1>; threads = ZLT; }
+  else if (R <= 32) { kern = k_lu_leaf_z64<32, 1>; threads = ZLT; }
   else throw std::runtime_error("getrf_z64: matrix order above 16384 is not supported");
+  hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, s, ar, ai, lda, perm, k0, mm, nc, n2, info, snap, sfrom);
   FROB_LAUNCH_CHECK();
 }
 
