@@ -112,10 +112,13 @@ struct LookAhead {
   hipStream_t s1 = nullptr;
   hipEvent_t ev[8] = {};
 };
-// Panel width: the next panel's update is then one recursion-node launch in
-// the real and the complex LU; 32 and 64 are the fastest widths measured at
-// n = 4096 (about 2 % apart), 128 to 512 slower.
-constexpr int LA_NB = 32;
+// Panel widths (real, complex): the next panel's update is then one
+// recursion-node launch (real nodes up to 64 columns, complex up to 32).
+// Measured at n = 4096: real 64 / 48 / 32 -> 42.1 / 44.3 / 42.5 ms per
+// Frobenius inversion, complex 32 / 64 -> 39.8 / 44.0 ms per complex LU
+// inversion; 128 to 512 were slower still.
+constexpr int LA_NB = 64;
+constexpr int ZLA_NB = 32;
 constexpr int LA_MIN = 1024;
 // Workgroups of a trailing update on the second stream: fewer than the chip
 // holds, so the panel chain's single-workgroup leaves find a free compute unit.

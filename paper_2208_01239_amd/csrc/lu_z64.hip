@@ -707,7 +707,7 @@ void zgetrf_rec(hipStream_t s, double* ar, double* ai, int lda, int* perm, int k
   zgetrf_rec(s, ar, ai, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
 }
 
-// Panels of LA_NB columns with a look-ahead of one panel; the ordering and
+// Panels of ZLA_NB columns with a look-ahead of one panel; the ordering and
 // the snapshot of the trailing rows' indices are those of the real version
 // (getrf_lookahead in lu_f64.hip).
 void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, int* perm, int* info, double* work,
@@ -716,7 +716,7 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
   double* work0 = work;
   double* work1 = work0 + trsm_z_work_elems(n / 2 + 8);
   int* snap[2];
-  snap[0] = reinterpret_cast<int*>(work1 + trsm_z_work_elems(LA_NB));
+  snap[0] = reinterpret_cast<int*>(work1 + trsm_z_work_elems(ZLA_NB));
   snap[1] = snap[0] + n;
   auto evF = [&](int j) { return la.ev[j & 3]; };
   auto evR = [&](int j) { return la.ev[4 + (j & 3)]; };
@@ -729,17 +729,17 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
     ZOut A22{ar + c, ai + c, lda, trows, nullptr};
     gemm_z64(st, OP_N, OP_N, n - (k0 + nb), w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
   };
-  const int np = ceil_div(n, LA_NB);
+  const int np = ceil_div(n, ZLA_NB);
   int last_r = -1;
   for (int j = 0; j < np; ++j) {
-    const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
+    const int k0 = j * ZLA_NB, nb = min(ZLA_NB, n - k0);
     const int r0 = k0 + nb;
     int* sn = snap[j & 1];
     // the panel's last leaf also writes the snapshot perm[r0 .. n)
     zgetrf_rec(s0, ar, ai, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
     if (r0 >= n) break;
     FROB_HIP(hipEventRecord(evF(j), s0));
-    const int c1 = r0, w1 = min(LA_NB, n - c1);
+    const int c1 = r0, w1 = min(ZLA_NB, n - c1);
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
     // the next panel's update is a recursion node when it is narrow enough
     if (nb <= ZNODE_MAX && w1 <= ZNODE_MAX) zlaunch_node(s0, ar, ai, lda, perm, k0, n - k0, nb, w1, cnt);
@@ -759,7 +759,7 @@ void zgetrf_lookahead(hipStream_t s0, int n, double* ar, double* ai, int lda, in
 }  // namespace
 
 size_t getrf_z_work_elems(int n) {
-  return 64 + trsm_z_work_elems(n / 2 + 8) + trsm_z_work_elems(LA_NB) + (size_t)n;
+  return 64 + trsm_z_work_elems(n / 2 + 8) + trsm_z_work_elems(ZLA_NB) + (size_t)n;
 }
 
 void getrf_z64(hipStream_t s, int n, double* re, double* im, int lda, int* perm, int* info, double* work,
