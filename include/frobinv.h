@@ -15,7 +15,10 @@
  *  - Ownership: the caller owns every input and output buffer.  Inputs are
  *    read-only; outputs must not alias inputs or each other.  The handle owns a
  *    grow-only device workspace and a pinned host word for status read-back,
- *    released by frob_destroy.
+ *    released by frob_destroy.  A workspace that a launch captured into a HIP
+ *    graph references is never freed before frob_destroy: when a later call
+ *    outgrows it, it is set aside and a new one is allocated, so the graph
+ *    stays valid until the handle is destroyed.
  *  - Ordering: all device work is enqueued on the handle's stream (see
  *    frob_set_stream).  Each call ends with one synchronization of that stream
  *    to read the factorization status, so outputs are ready on return.
@@ -42,12 +45,14 @@ typedef enum {
                                is invertible iff M is); with the shift disabled, also a singular real part A */
   FROB_NOT_HPD = 2,         /* a Cholesky factorization met a non-positive pivot (Lemma 4.5 says A and C are
                                positive definite whenever M is Hermitian positive definite) */
-  FROB_NO_CONVERGENCE = 3,  /* Newton-Schulz refinement cannot start: ||I - M X||_F >= 1 for the unrefined
-                               inverse (X is returned unrefined) */
+  FROB_NO_CONVERGENCE = 3,  /* Newton-Schulz refinement cannot converge from the unrefined inverse: the
+                               estimate of ||I - M X||_2 is >= 1, or ||I - M X||_F grew (X is returned unrefined) */
   FROB_E_ARG = -1,          /* invalid argument (null pointer, n out of range, leading dimension too small) */
   FROB_E_ALLOC = -2,        /* device or pinned-host allocation failed */
   FROB_E_HIP = -3,          /* a HIP runtime call failed */
-  FROB_E_INTERNAL = -4
+  FROB_E_INTERNAL = -4,
+  FROB_E_CAPTURE = -5       /* the call needs a larger workspace while the handle's stream is being captured
+                               into a HIP graph: run it once outside the capture first */
 } frob_status_t;
 
 /* What to do about the real part A (Section 4.2, Algorithm 6, "almost sure
@@ -103,7 +108,9 @@ typedef struct {
   int refine_steps;     /* Newton-Schulz steps applied                                                     */
   double resid0;        /* ||I - M X||_F / sqrt(n) of the unrefined inverse (refine > 0 only)              */
   double resid;         /* the same for the returned inverse (refine > 0 only; NaN if skipped, see above)   */
-  double reserved[2];
+  double norm2_est;     /* power-iteration estimate (a lower bound) of ||I - M X||_2 for the unrefined inverse,
+                           formed only when ||I - M X||_F >= 1; 0 otherwise                                */
+  double reserved[1];
 } frob_result_t;
 
 /* Fill *opts with the defaults (FROB_SHIFT_AUTO, mu drawn, no refinement). */
@@ -154,6 +161,25 @@ frob_status_t frob_solve(frob_handle_t handle, int n, int nrhs, const double *A,
                          const double *c, const double *d, int ldc, double *x, double *y, int ldxy,
                          const frob_opts_t *opts, frob_result_t *res);
 
+/* Newton-Schulz refinement of a caller-supplied approximate inverse X of
+ * M = A + iB, in place (the refinement the precision line applies after a
+ * low-precision inversion; not in the paper):
+ *   R = I - M X (FP64, Gauss's three-multiplication products, Proposition 2.2),
+ *   X <- X + X R   (so that I - M X_new = R^2),
+ * for at most opts->refine steps (>= 1), the correction's operands in
+ * opts->prec (FROB_PREC_F64, F32 or BF16, or FP32 with
+ * FROB_REFINE_F32_CORRECTION), until ||R||_F / sqrt(n) <= opts->refine_tol
+ * or the FP64 rounding floor.  The iteration converges iff the spectral
+ * radius of R_0 is below one.  A start with ||R_0||_F >= 1 is accepted when a
+ * power-iteration estimate of ||R_0||_2 is below one, tentatively: if
+ * ||R||_F grows before dropping below one, X is restored.  Returns
+ * FROB_NO_CONVERGENCE (X unchanged) when the estimate is >= 1 or the norm grew.
+ *   A, B   : n x n (leading dimensions lda, ldb), the matrix M
+ *   Xr, Xi : n x n (leading dimension ldx), input and output
+ *   res    : resid0, resid, norm2_est, refine_steps (may be NULL) */
+frob_status_t frob_refine(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
+                          double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
 /* Baseline: inversion with LU decomposition in complex arithmetic
  * (Algorithm 4), planar storage, four real matrix-core products per complex
  * tile product.  form 0: as printed (U X1 = I, X2 L = X1, X^{-1} = X2 P);
@@ -199,7 +225,9 @@ frob_status_t frob_inv_adjoint(frob_handle_t handle, int batch, int n, int stora
  * Asynchronous on the handle's stream: no host synchronization, no allocation
  * once the workspace has grown to fit (a first call of the same shape), and
  * no memset (queue reset by a kernel), so a call can be captured in a HIP
- * graph and replayed.  The panel width per (kind, order class) comes from
+ * graph and replayed.  Captured before a first eager call of its shape, it
+ * returns FROB_E_CAPTURE; the workspace it captured outlives later growth of
+ * the handle's workspace (see Ownership).  The panel width per (kind, order class) comes from
  * frob_batched_tune (default 16). */
 frob_status_t frob_inv_batched(frob_handle_t handle, int count, int nmax, const int *n_dev, const int *kind_dev,
                                const void *const *A_dev, const void *const *B_dev, void *const *Xr_dev,

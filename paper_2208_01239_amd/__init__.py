@@ -19,7 +19,7 @@ from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32
                    FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNoConvergenceError, FrobNotHPDError, FrobSingularError,
                    frob_opts_t, frob_result_t)
 
-__all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_cinv_lu", "frob_cinv_chol",
+__all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_refine", "frob_cinv_lu", "frob_cinv_chol",
            "frob_inv_adjoint", "frob_inv_batched", "frob_batched_tune", "BatchedPlan",
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
            "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
@@ -156,6 +156,26 @@ def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_
     st = _lib.load().frob_inv_hpd(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, "frob_inv_hpd", r)
     return Xr, Xi, r.as_dict()
+
+
+def frob_refine(h: Handle, A, B, Xr, Xi, *, refine=4, prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True,
+                f32_correction=False):
+    """Newton-Schulz refinement, in place, of an approximate inverse Xr + i Xi of A + iB.
+
+    Raises FrobNoConvergenceError (X left unchanged) when ||I - M X||_2 is
+    estimated >= 1 or the residual grows.  Returns the result dict."""
+    n = A.shape[0]
+    pa, lda = _mat(A, n, n, "A")
+    pb, ldb = _mat(B, n, n, "B")
+    pr, ldx = _mat(Xr, n, n, "Xr")
+    pi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldx != ldxi:
+        raise ValueError("Xr and Xi must share a leading dimension")
+    h.bind_stream()
+    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
+    st = _lib.load().frob_refine(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, "frob_refine", r)
+    return r.as_dict()
 
 
 def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0):

@@ -22,6 +22,7 @@ FROB_E_ARG = -1
 FROB_E_ALLOC = -2
 FROB_E_HIP = -3
 FROB_E_INTERNAL = -4
+FROB_E_CAPTURE = -5
 
 FROB_SHIFT_OFF = 0
 FROB_SHIFT_AUTO = 1
@@ -42,12 +43,13 @@ class frob_opts_t(ctypes.Structure):
 class frob_result_t(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int), ("stage", ctypes.c_int), ("mu_used", ctypes.c_double),
                 ("shifts_tried", ctypes.c_int), ("refine_steps", ctypes.c_int),
-                ("resid0", ctypes.c_double), ("resid", ctypes.c_double), ("reserved", ctypes.c_double * 2)]
+                ("resid0", ctypes.c_double), ("resid", ctypes.c_double), ("norm2_est", ctypes.c_double),
+                ("reserved", ctypes.c_double * 1)]
 
     def as_dict(self):
         return {"info": self.info, "stage": self.stage, "mu_used": self.mu_used,
                 "shifts_tried": self.shifts_tried, "refine_steps": self.refine_steps,
-                "resid0": self.resid0, "resid": self.resid}
+                "resid0": self.resid0, "resid": self.resid, "norm2_est": self.norm2_est}
 
 
 _vp = ctypes.c_void_p
@@ -66,6 +68,7 @@ SIGNATURES = {
     "frob_inv_general": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_inv_hpd": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_refine": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_inv_adjoint": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -116,7 +119,7 @@ class FrobNotHPDError(FrobError):
 
 
 class FrobNoConvergenceError(FrobError):
-    """Newton-Schulz refinement could not start (||I - M X||_F >= 1); X is unrefined."""
+    """Newton-Schulz refinement cannot converge (||I - M X||_2 estimated >= 1, or the residual grew); X is unrefined."""
 
 
 def check(status: int, where: str, result: frob_result_t | None = None):

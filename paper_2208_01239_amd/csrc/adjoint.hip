@@ -142,6 +142,8 @@ extern "C" frob_status_t frob_inv_adjoint(frob_handle_t h, int batch, int n, int
     return FROB_OK;
   } catch (const std::bad_alloc&) {
     return FROB_E_ALLOC;
+  } catch (const CaptureGrowth&) {
+    return FROB_E_CAPTURE;
   } catch (const HipError&) {
     return FROB_E_HIP;
   } catch (...) {

@@ -1,0 +1,597 @@
+// batched_dev.hpp -- the workgroup-level building blocks of the batched
+// inversion (one workgroup of BT threads inverts one matrix at a time) and the
+// body of the persistent kernel.
+//
+// The code is written against a handful of primitives that the including file
+// supplies before including this header, inside namespace frob::bat:
+//   BB_FN                      qualifier of the out-of-line building blocks
+//   BB_IN                      qualifier of the small inline helpers
+//   int  bb_tid()              thread index within the workgroup
+//   void bb_sync()             workgroup barrier (with workgroup memory fence)
+//   template <class V> V bb_shfl_xor(V v, int mask)   lane exchange in a wave of 64
+//   int  bb_first(int v)       the value held by the wave's first lane
+//   d4   bb_mfma(double a, double b, d4 c)   16x16x4 FP64 matrix-core product
+//   f4   bb_mfma(float a, float b, f4 c)     16x16x4 FP32 matrix-core product
+//   int  bb_atomic_add(int* p, int v)        atomic fetch-and-add
+// and the vector types frob::d4 / frob::f4.  batched.hip maps them to the
+// gfx950 intrinsics; the test suite maps them to a cooperative CPU emulation of
+// one or more workgroups that checks every barrier is reached by every thread
+// in the same order (tests/emu/batched_emu.cpp).
+#pragma once
+
+#include <climits>
+#include <cmath>
+
+namespace frob {
+namespace bat {
+
+constexpr int BT = 256;          // threads per workgroup
+constexpr int BNMAX = 512;       // largest order handled in-workgroup
+constexpr int PNB = 32;          // largest LU panel width
+constexpr int XNB = 16;          // diagonal blocks solved by register substitution (triangular solves, Cholesky)
+constexpr int GT = 64;           // GEMM output tile
+constexpr int GP = GT + 4;       // LDS pitch of a GEMM tile row
+// GEMM k-step: 32 in FP32, 16 in FP64 (keeps the FP64 panel plus tiles under 160 KiB of LDS)
+template <typename T>
+struct GKof { static constexpr int v = sizeof(T) == 8 ? 16 : 32; };
+
+BB_IN int imin(int a, int b) { return a < b ? a : b; }
+BB_IN int imax(int a, int b) { return a > b ? a : b; }
+
+// Output layout of the 16x16x4 products: lane l holds column l % 16 of four
+// rows.  Input layout: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc;
+  BB_IN static acc op(double a, double b, acc c) { return bb_mfma(a, b, c); }
+  BB_IN static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc;
+  BB_IN static acc op(float a, float b, acc c) { return bb_mfma(a, b, c); }
+  BB_IN static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T>
+struct Smem {
+  T ga[GKof<T>::v * GP];     // GEMM A tile, k-major
+  T gb[GKof<T>::v * GP];     // GEMM B tile, k-major
+  T panel[BNMAX * PNB];      // LU panel / Cholesky diagonal block / triangular diagonal block
+  T red_v[BT / 64];
+  int red_i[BT / 64];
+  int bcast[4];
+};
+
+// Scalar arguments of the out-of-line building blocks arrive in vector
+// registers; re-reading them through the first lane makes every loop bound and
+// branch condition derived from them uniform to the compiler (they are uniform
+// in value), so barrier-containing regions are never entered with a partial or
+// empty exec mask.
+BB_IN int uni(int v) { return bb_first(v); }
+BB_IN bool uni(bool v) { return bb_first((int)v) != 0; }
+
+// ---------------------------------------------------------------- GEMM
+// C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K (A stored K x M if ta)
+template <typename T>
+BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B, int ldb,
+                   bool tb, T beta, T* C, int ldc) {
+  M = uni(M); N = uni(N); K = uni(K); lda = uni(lda); ldb = uni(ldb); ldc = uni(ldc); ta = uni(ta); tb = uni(tb);
+  typedef typename Mfma<T>::acc acc_t;
+  constexpr int GK = GKof<T>::v;
+  const int tid = bb_tid(), lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int tilesN = (N + GT - 1) / GT;
+  const int tiles = ((M + GT - 1) / GT) * tilesN;
+  constexpr int E = GT * GK / BT;   // elements per thread per operand tile
+  for (int t = 0; t < tiles; ++t) {
+    const int tm = (t / tilesN) * GT, tn = (t % tilesN) * GT;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    T ra[E], rb[E];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = tid + BT * u;
+        int i, k;
+        if (!ta) { i = e / GK; k = e % GK; } else { k = e / GT; i = e % GT; }
+        const int gi = imin(tm + i, M - 1), gk = imin(k0 + k, K - 1);
+        ra[u] = ta ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk];
+      }
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = tid + BT * u;
+        int k, j;
+        if (!tb) { k = e / GT; j = e % GT; } else { j = e / GK; k = e % GK; }
+        const int gk = imin(k0 + k, K - 1), gj = imin(tn + j, N - 1);
+        rb[u] = tb ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj];
+      }
+    };
+    auto store = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = tid + BT * u;
+        int i, k;
+        if (!ta) { i = e / GK; k = e % GK; } else { k = e / GT; i = e % GT; }
+        sm.ga[k * GP + i] = (tm + i < M && k0 + k < K) ? ra[u] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = tid + BT * u;
+        int k, j;
+        if (!tb) { k = e / GT; j = e % GT; } else { j = e / GK; k = e % GK; }
+        sm.gb[k * GP + j] = (tn + j < N && k0 + k < K) ? rb[u] : T(0);
+      }
+    };
+    const int nk = (K + GK - 1) / GK;
+    if (nk > 0) load(0);
+    for (int it = 0; it < nk; ++it) {
+      store(it * GK);
+      bb_sync();
+      if (it + 1 < nk) load((it + 1) * GK);
+#pragma unroll
+      for (int kk = 0; kk < GK; kk += 4) {
+        T fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fa[a] = sm.ga[(kk + (lane >> 4)) * GP + wm + 16 * a + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) fb[b] = sm.gb[(kk + (lane >> 4)) * GP + wn + 16 * b + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(fa[a], fb[b], acc[a][b]);
+      }
+      bb_sync();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tm + wm + 16 * a + Mfma<T>::row(lane, v);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int j = tn + wn + 16 * b + (lane & 15);
+          if (i < M && j < N) {
+            T* cp = C + (long long)i * ldc + j;
+            T val = alpha * acc[a][b][v];
+            if (beta != T(0)) val += beta * *cp;
+            *cp = val;
+          }
+        }
+      }
+  }
+  bb_sync();
+}
+
+// ------------------------------------------------------- triangular solves
+// op(L) X = B in place (B is n x nrhs).  L is lower triangular (unit or not);
+// op(L) = L (forward) or L^T (backward).
+template <typename T>
+BB_FN void wg_trsm_left(Smem<T>& sm, int n, int nrhs, const T* L, int ldl, bool unit, bool trans, T* B, int ldb,
+                        int nb) {
+  n = uni(n); nrhs = uni(nrhs); ldl = uni(ldl); ldb = uni(ldb); unit = uni(unit); trans = uni(trans);
+  const int tid = bb_tid();
+  nb = imin(uni(nb), XNB);
+  const int nblk = (n + nb - 1) / nb;
+  for (int s = 0; s < nblk; ++s) {
+    const int blk = trans ? nblk - 1 - s : s;
+    const int k0 = blk * nb, kb = imin(nb, n - k0);
+    // diagonal block of op(L) into LDS: D(i, k) = op(L)(k0 + i, k0 + k)
+    T* D = sm.panel;
+    for (int e = tid; e < kb * kb; e += BT) {
+      const int i = e / kb, k = e % kb;
+      const int r = trans ? k : i, c = trans ? i : k;      // stored coordinates within the block
+      D[i * PNB + k] = (c <= r) ? L[(long long)(k0 + r) * ldl + k0 + c] : T(0);
+    }
+    bb_sync();
+    // substitution: one thread per right-hand side column (register indices
+    // are compile-time; rows at and beyond kb are masked)
+    for (int j = tid; j < nrhs; j += BT) {
+      T x[XNB];
+#pragma unroll
+      for (int i = 0; i < XNB; ++i) x[i] = B[(long long)(k0 + imin(i, kb - 1)) * ldb + j];
+      if (!trans) {
+#pragma unroll
+        for (int i = 0; i < XNB; ++i)
+          if (i < kb) {
+            T v = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= D[i * PNB + k] * x[k];
+            x[i] = unit ? v : v / D[i * PNB + i];
+          }
+      } else {
+#pragma unroll
+        for (int i = XNB - 1; i >= 0; --i)
+          if (i < kb) {
+            T v = x[i];
+#pragma unroll
+            for (int k = i + 1; k < XNB; ++k)
+              if (k < kb) v -= D[i * PNB + k] * x[k];
+            x[i] = unit ? v : v / D[i * PNB + i];
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < XNB; ++i)
+        if (i < kb) B[(long long)(k0 + i) * ldb + j] = x[i];
+    }
+    bb_sync();
+    // update the rest: forward B[k0+kb:] -= L[k0+kb:, blk] X_blk;  backward B[:k0] -= L[blk, :k0]^T X_blk
+    if (!trans) {
+      const int m = n - k0 - kb;
+      if (m > 0)
+        wg_gemm<T>(sm, m, nrhs, kb, T(-1), L + (long long)(k0 + kb) * ldl + k0, ldl, false,
+                   B + (long long)k0 * ldb, ldb, false, T(1), B + (long long)(k0 + kb) * ldb, ldb);
+    } else {
+      if (k0 > 0)
+        wg_gemm<T>(sm, k0, nrhs, kb, T(-1), L + (long long)k0 * ldl, ldl, true, B + (long long)k0 * ldb, ldb,
+                   false, T(1), B, ldb);
+    }
+  }
+}
+
+// U X = B in place with U upper triangular (non-unit), backward blocks
+template <typename T>
+BB_FN void wg_trsm_upper(Smem<T>& sm, int n, int nrhs, const T* U, int ldu, T* B, int ldb, int nb) {
+  n = uni(n); nrhs = uni(nrhs); ldu = uni(ldu); ldb = uni(ldb);
+  const int tid = bb_tid();
+  nb = imin(uni(nb), XNB);
+  const int nblk = (n + nb - 1) / nb;
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int k0 = blk * nb, kb = imin(nb, n - k0);
+    T* D = sm.panel;
+    for (int e = tid; e < kb * kb; e += BT) {
+      const int i = e / kb, k = e % kb;
+      D[i * PNB + k] = (k >= i) ? U[(long long)(k0 + i) * ldu + k0 + k] : T(0);
+    }
+    bb_sync();
+    for (int j = tid; j < nrhs; j += BT) {
+      T x[XNB];
+#pragma unroll
+      for (int i = 0; i < XNB; ++i) x[i] = B[(long long)(k0 + imin(i, kb - 1)) * ldb + j];
+#pragma unroll
+      for (int i = XNB - 1; i >= 0; --i)
+        if (i < kb) {
+          T v = x[i];
+#pragma unroll
+          for (int k = i + 1; k < XNB; ++k)
+            if (k < kb) v -= D[i * PNB + k] * x[k];
+          x[i] = v / D[i * PNB + i];
+        }
+#pragma unroll
+      for (int i = 0; i < XNB; ++i)
+        if (i < kb) B[(long long)(k0 + i) * ldb + j] = x[i];
+    }
+    bb_sync();
+    if (k0 > 0)
+      wg_gemm<T>(sm, k0, nrhs, kb, T(-1), U + k0, ldu, false, B + (long long)k0 * ldb, ldb, false, T(1), B, ldb);
+  }
+}
+
+// ------------------------------------------------------------ reductions
+// (value, index) with the largest value; lowest index on ties; returns to all threads
+template <typename T>
+BB_IN int wg_argmax(Smem<T>& sm, T v, int idx) {
+  const int lane = bb_tid() & 63, wave = bb_tid() >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const T ov = bb_shfl_xor(v, off);
+    const int oi = bb_shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  if (lane == 0) { sm.red_v[wave] = v; sm.red_i[wave] = idx; }
+  bb_sync();
+  T bv = sm.red_v[0];
+  int bi = sm.red_i[0];
+#pragma unroll
+  for (int w = 1; w < BT / 64; ++w) {
+    const T ov = sm.red_v[w];
+    const int oi = sm.red_i[w];
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  bb_sync();
+  return bi;
+}
+
+// ------------------------------------------------------------- LU (GEPP)
+// P A = L U in place, piv[k] = row exchanged with k (LAPACK ipiv, 0-based).
+// Returns the first zero pivot column + 1, or 0.  nb >= 1 (the caller clamps).
+template <typename T>
+BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* piv, int nb) {
+  n = uni(n); lda = uni(lda); nb = uni(nb);
+  const int tid = bb_tid();
+  int info = 0;
+  for (int k0 = 0; k0 < n; k0 += nb) {
+    const int kb = imin(nb, n - k0), m = n - k0;
+    // panel (rows k0.., columns k0..k0+kb) into LDS: P[r][c]
+    T* P = sm.panel;
+    for (int e = tid; e < m * kb; e += BT) {
+      const int r = e / kb, c = e % kb;
+      P[r * PNB + c] = A[(long long)(k0 + r) * lda + k0 + c];
+    }
+    bb_sync();
+    for (int j = 0; j < kb; ++j) {
+      T best = T(-1);
+      int bi = INT_MAX;
+      for (int r = j + tid; r < m; r += BT) {
+        const T a = std::fabs(P[r * PNB + j]);
+        if (a > best) { best = a; bi = r; }
+      }
+      const int p = wg_argmax<T>(sm, best, bi);
+      const int pr = (p == INT_MAX) ? j : p;      // an all-NaN column keeps row j
+      if (tid == 0) piv[k0 + j] = k0 + pr;
+      if (pr != j)
+        for (int c = tid; c < kb; c += BT) {
+          const T t = P[j * PNB + c];
+          P[j * PNB + c] = P[pr * PNB + c];
+          P[pr * PNB + c] = t;
+        }
+      bb_sync();
+      const T d = P[j * PNB + j];
+      if (d == T(0)) {
+        if (!info) info = k0 + j + 1;
+      } else {
+        const T rd = T(1) / d;
+        for (int r = j + 1 + tid; r < m; r += BT) {
+          const T l = P[r * PNB + j] * rd;
+          P[r * PNB + j] = l;
+          for (int c = j + 1; c < kb; ++c) P[r * PNB + c] -= l * P[j * PNB + c];
+        }
+      }
+      bb_sync();
+    }
+    for (int e = tid; e < m * kb; e += BT) {
+      const int r = e / kb, c = e % kb;
+      A[(long long)(k0 + r) * lda + k0 + c] = P[r * PNB + c];
+    }
+    // the panel's interchanges on the columns left and right of it
+    for (int c = tid; c < n; c += BT) {
+      if (c >= k0 && c < k0 + kb) continue;
+      for (int j = 0; j < kb; ++j) {
+        const int r2 = piv[k0 + j];
+        if (r2 != k0 + j) {
+          T* a1 = A + (long long)(k0 + j) * lda + c;
+          T* a2 = A + (long long)r2 * lda + c;
+          const T t = *a1;
+          *a1 = *a2;
+          *a2 = t;
+        }
+      }
+    }
+    bb_sync();
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      // U12 = L11^{-1} A12, then A22 -= L21 U12
+      wg_trsm_left<T>(sm, kb, rest, A + (long long)k0 * lda + k0, lda, true, false, A + (long long)k0 * lda + k0 + kb,
+                      lda, nb);
+      wg_gemm<T>(sm, rest, rest, kb, T(-1), A + (long long)(k0 + kb) * lda + k0, lda, false,
+                 A + (long long)k0 * lda + k0 + kb, lda, false, T(1), A + (long long)(k0 + kb) * lda + k0 + kb, lda);
+    }
+  }
+  return info;
+}
+
+// apply the interchanges piv[0..n) to the rows of B (n x nrhs), in order
+template <typename T>
+BB_IN void wg_laswp(int n, int nrhs, T* B, int ldb, const int* piv) {
+  n = uni(n); nrhs = uni(nrhs);
+  for (int c = bb_tid(); c < nrhs; c += BT)
+    for (int k = 0; k < n; ++k) {
+      const int r2 = piv[k];
+      if (r2 != k) {
+        const T t = B[(long long)k * ldb + c];
+        B[(long long)k * ldb + c] = B[(long long)r2 * ldb + c];
+        B[(long long)r2 * ldb + c] = t;
+      }
+    }
+  bb_sync();
+}
+
+// ------------------------------------------------------------ Cholesky
+// A = L L^T in place (lower triangle).  Returns the first non-positive pivot's
+// column (1-based), or 0.  nb >= 1 (the caller clamps).
+template <typename T>
+BB_FN int wg_potrf(Smem<T>& sm, int n, T* A, int lda, int nb) {
+  n = uni(n); lda = uni(lda);
+  const int tid = bb_tid();
+  nb = imin(uni(nb), XNB);
+  int bad = 0;
+  for (int k0 = 0; k0 < n; k0 += nb) {
+    const int kb = imin(nb, n - k0);
+    T* D = sm.panel;
+    for (int e = tid; e < kb * kb; e += BT) {
+      const int i = e / kb, k = e % kb;
+      D[i * PNB + k] = (k <= i) ? A[(long long)(k0 + i) * lda + k0 + k] : T(0);
+    }
+    bb_sync();
+    for (int j = 0; j < kb; ++j) {
+      const T d = D[j * PNB + j];
+      // a non-positive pivot is recorded and the factorization runs on (its
+      // square root is NaN): the control flow never depends on the data
+      if (!bad && !(d > T(0))) bad = k0 + j + 1;
+      const T ljj = std::sqrt(d);
+      bb_sync();
+      if (tid == 0) D[j * PNB + j] = ljj;
+      for (int i = j + 1 + tid; i < kb; i += BT) D[i * PNB + j] /= ljj;
+      bb_sync();
+      for (int e = tid; e < kb * kb; e += BT) {
+        const int i = e / kb, c = e % kb;
+        if (i > j && c > j && c <= i) D[i * PNB + c] -= D[i * PNB + j] * D[c * PNB + j];
+      }
+      bb_sync();
+    }
+    for (int e = tid; e < kb * kb; e += BT) {
+      const int i = e / kb, k = e % kb;
+      if (k <= i) A[(long long)(k0 + i) * lda + k0 + k] = D[i * PNB + k];
+    }
+    bb_sync();
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      // L21 = A21 L11^{-T}: row r solves L11 x = a_r
+      for (int r = tid; r < rest; r += BT) {
+        T* row = A + (long long)(k0 + kb + r) * lda + k0;
+        T x[XNB];
+#pragma unroll
+        for (int i = 0; i < XNB; ++i) x[i] = row[imin(i, kb - 1)];
+#pragma unroll
+        for (int i = 0; i < XNB; ++i)
+          if (i < kb) {
+            T v = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= D[i * PNB + k] * x[k];
+            x[i] = v / D[i * PNB + i];
+          }
+#pragma unroll
+        for (int i = 0; i < XNB; ++i)
+          if (i < kb) row[i] = x[i];
+      }
+      bb_sync();
+      // A22 -= L21 L21^T (full block; the upper part is never read)
+      wg_gemm<T>(sm, rest, rest, kb, T(-1), A + (long long)(k0 + kb) * lda + k0, lda, false,
+                 A + (long long)(k0 + kb) * lda + k0, lda, true, T(1), A + (long long)(k0 + kb) * lda + k0 + kb, lda);
+    }
+  }
+  return bad;
+}
+
+template <typename T>
+BB_IN void wg_copy(int n, const T* src, T* dst) {
+  n = uni(n);
+  for (int e = bb_tid(); e < n * n; e += BT) dst[e] = src[e];
+  bb_sync();
+}
+template <typename T>
+BB_IN void wg_identity(int n, T* dst) {
+  n = uni(n);
+  for (int e = bb_tid(); e < n * n; e += BT) dst[e] = (e / n == e % n) ? T(1) : T(0);
+  bb_sync();
+}
+
+struct BatchArgs {
+  int count;
+  const int* n;         // per-matrix order
+  const int* kind;      // 0 general, 1 HPD
+  const void* const* A;
+  const void* const* B;
+  void* const* Xr;
+  void* const* Xi;
+  int* info;            // per matrix: 0, or stage * 1000000 + column (1-based); -1 bad order or kind
+  int nmax;             // workspace slots are sized for this order
+  const int* order;     // processing order (largest first)
+  int* counter;         // queue head
+  void* ws;             // per-workgroup slots
+  long long slot_elems; // elements (T) per slot
+  int nb_table[2][4];   // [kind][size class] panel width
+};
+
+BB_IN int size_class(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
+
+// Status word of one member: 0, or 1000000 * stage + column.
+BB_IN int status_word(int stage, int col) { return col ? 1000000 * stage + col : 0; }
+
+// The persistent worker of workgroup `block`: takes matrices from the queue
+// until it is empty.  Every branch that guards a barrier depends only on
+// values read through the first lane (uniform to the compiler, not only in
+// value), and a failed factorization does not change the control flow: the
+// remaining steps run on the (non-finite) values, and the status word records
+// the first failing stage and column.  The order and kind are validated
+// before they index anything (a kind outside {0, 1} once indexed the
+// panel-width table out of bounds).
+template <typename T>
+BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
+  const int tid = bb_tid();
+  T* slot = reinterpret_cast<T*>(g.ws) + (long long)block * g.slot_elems;
+  for (;;) {
+    if (tid == 0) sm.bcast[0] = bb_atomic_add(g.counter, 1);
+    bb_sync();
+    const int q = bb_first(sm.bcast[0]);
+    bb_sync();
+    if (q >= g.count) break;                          // every wave leaves
+    const int mi = bb_first(g.order[q]);
+    const int n = bb_first(g.n[mi]);
+    const int kind = bb_first(g.kind[mi]);
+    if (n < 1 || n > g.nmax || (kind != 0 && kind != 1)) {
+      if (tid == 0) g.info[mi] = -1;
+      continue;
+    }
+    const int nb = imin(imax(g.nb_table[kind][size_class(n)], 1), PNB);
+    const T* A = reinterpret_cast<const T*>(g.A[mi]);
+    const T* B = reinterpret_cast<const T*>(g.B[mi]);
+    T* Xr = reinterpret_cast<T*>(g.Xr[mi]);
+    T* Xi = reinterpret_cast<T*>(g.Xi[mi]);
+    const long long nn = (long long)n * n;
+    T* F = slot;            // factors of A
+    T* Y = slot + nn;       // A^{-1} B
+    T* Cm = slot + 2 * nn;  // C and its factors
+    int* piv = reinterpret_cast<int*>(slot + 3 * nn);
+    int info = 0;
+    if (kind == 0) {
+      // Algorithm 5
+      wg_copy<T>(n, A, F);
+      const int i1 = bb_first(wg_getrf<T>(sm, n, F, n, piv, nb));
+      info = status_word(1, i1);
+      wg_copy<T>(n, B, Y);                                              // Y = A^{-1} B
+      wg_laswp<T>(n, n, Y, n, piv);
+      wg_trsm_left<T>(sm, n, n, F, n, true, false, Y, n, nb);
+      wg_trsm_upper<T>(sm, n, n, F, n, Y, n, nb);
+      wg_copy<T>(n, A, Cm);                                             // C = A + B Y
+      wg_gemm<T>(sm, n, n, n, T(1), B, n, false, Y, n, false, T(1), Cm, n);
+      const int i2 = bb_first(wg_getrf<T>(sm, n, Cm, n, piv, nb));
+      if (!info) info = status_word(2, i2);
+      wg_identity<T>(n, Xr);                                            // Re X = C^{-1}
+      wg_laswp<T>(n, n, Xr, n, piv);
+      wg_trsm_left<T>(sm, n, n, Cm, n, true, false, Xr, n, nb);
+      wg_trsm_upper<T>(sm, n, n, Cm, n, Xr, n, nb);
+      wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
+    } else {
+      // Algorithm 7
+      wg_copy<T>(n, A, F);
+      const int i1 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
+      info = status_word(1, i1);
+      wg_copy<T>(n, B, Cm);                                             // X1 = R1^{-T} B (Cm as scratch)
+      wg_trsm_left<T>(sm, n, n, F, n, false, false, Cm, n, nb);
+      wg_copy<T>(n, Cm, Y);                                             // Y = R1^{-1} X1
+      wg_trsm_left<T>(sm, n, n, F, n, false, true, Y, n, nb);
+      // C = A - X1^T X1 into F's place (F is no longer needed)
+      wg_copy<T>(n, A, F);
+      wg_gemm<T>(sm, n, n, n, T(-1), Cm, n, true, Cm, n, false, T(1), F, n);
+      const int i2 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
+      if (!info) info = status_word(2, i2);
+      wg_identity<T>(n, Xr);                                            // Re X = R2^{-1} R2^{-T}
+      wg_trsm_left<T>(sm, n, n, F, n, false, false, Xr, n, nb);
+      wg_trsm_left<T>(sm, n, n, F, n, false, true, Xr, n, nb);
+      wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
+    }
+    if (tid == 0) g.info[mi] = info;
+    bb_sync();
+  }
+}
+
+// Processing order, largest order first (counting sort on n by one workgroup
+// of `nt` threads; hist holds BNMAX + 2 ints of workgroup memory), and reset
+// of the queue head (a kernel, not a memset, so the pair can be captured in
+// a graph).
+BB_IN void batched_order_body(int nt, int count, const int* n, int* order, int* counter, int* hist) {
+  const int tid = bb_tid();
+  for (int i = tid; i < BNMAX + 2; i += nt) hist[i] = 0;
+  bb_sync();
+  for (int i = tid; i < count; i += nt) bb_atomic_add(&hist[BNMAX - imin(imax(n[i], 0), BNMAX)], 1);
+  bb_sync();
+  if (tid == 0) {
+    int run = 0;
+    for (int b = 0; b <= BNMAX; ++b) { const int c = hist[b]; hist[b] = run; run += c; }
+    *counter = 0;
+  }
+  bb_sync();
+  for (int i = tid; i < count; i += nt) {
+    const int pos = bb_atomic_add(&hist[BNMAX - imin(imax(n[i], 0), BNMAX)], 1);
+    order[pos] = i;
+  }
+}
+
+}  // namespace bat
+}  // namespace frob

@@ -34,6 +34,8 @@ frob_status_t zguarded(frob_handle_t h, F&& f) {
     return f();
   } catch (const std::bad_alloc&) {
     return FROB_E_ALLOC;
+  } catch (const CaptureGrowth&) {
+    return FROB_E_CAPTURE;
   } catch (const HipError&) {
     return FROB_E_HIP;
   } catch (...) {

@@ -34,13 +34,37 @@ double draw_mu(frob_handle* h) {
   }
 }
 
+static bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e == hipErrorStreamCaptureImplicit) {   // the null stream while another stream is being captured
+    (void)hipGetLastError();
+    return true;
+  }
+  FROB_HIP(e);
+  return cs != hipStreamCaptureStatusNone;
+}
+
+bool mark_ws_captured(frob_handle* h) {
+  if (!stream_capturing(h->stream)) return false;
+  h->ws_captured = true;
+  return true;
+}
+
 void* ws_reserve(frob_handle* h, size_t bytes) {
   bytes += 64 * 256;  // alignment slack: sub-carves may start at unaligned offsets
   if (bytes <= h->ws_cap) return h->ws;
+  // a graph being captured would bake in a buffer that the next growth frees:
+  // the caller must run the call once eagerly first (documented in the header)
+  if (stream_capturing(h->stream)) throw CaptureGrowth();
   FROB_HIP(hipStreamSynchronize(h->stream));
-  if (h->ws) FROB_HIP(hipFree(h->ws));
+  if (h->ws) {
+    if (h->ws_captured) h->ws_retired.push_back(h->ws);   // a graph may still write it
+    else FROB_HIP(hipFree(h->ws));
+  }
   h->ws = nullptr;
   h->ws_cap = 0;
+  h->ws_captured = false;
   const size_t cap = bytes + (bytes >> 3);
   if (hipMalloc(&h->ws, cap) != hipSuccess) {
     h->ws = nullptr;
@@ -137,6 +161,8 @@ frob_status_t guarded(frob_handle_t h, F&& f) {
     return f();
   } catch (const std::bad_alloc&) {
     return FROB_E_ALLOC;
+  } catch (const CaptureGrowth&) {
+    return FROB_E_CAPTURE;
   } catch (const HipError&) {
     return FROB_E_HIP;
   } catch (...) {
@@ -287,6 +313,7 @@ frob_status_t frob_destroy(frob_handle_t h) {
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
   if (h->ws) (void)hipFree(h->ws);
+  for (void* p : h->ws_retired) (void)hipFree(p);
   if (h->dinfo) (void)hipFree(h->dinfo);
   if (h->hinfo) (void)hipHostFree(h->hinfo);
   if (h->dnorm) (void)hipFree(h->dnorm);
@@ -536,6 +563,23 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
   });
 }
 
+frob_status_t frob_refine(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                          double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  if (o.refine < 1 || o.prec < FROB_PREC_F64 || o.prec > FROB_PREC_BF16) return FROB_E_ARG;
+  return guarded(h, [&]() -> frob_status_t {
+    Carve c((char*)ws_reserve(h, ns_ws_bytes(n, o.refine)));
+    frob_result_t r;
+    std::memset(&r, 0, sizeof(r));
+    LowPrecScope fp64(LP_NONE);   // the residual is formed in FP64; ns_refine scopes the correction
+    const frob_status_t st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec,
+                                       o.refine_flags, c, &r);
+    if (res) *res = r;
+    return st;
+  });
+}
+
 frob_status_t frob_profile_enable(frob_handle_t h, int on) {
   if (!h) return FROB_E_ARG;
   h->prof = on ? 1 : 0;
@@ -564,6 +608,7 @@ const char* frob_status_string(frob_status_t s) {
     case FROB_E_ALLOC: return "FROB_E_ALLOC";
     case FROB_E_HIP: return "FROB_E_HIP";
     case FROB_E_INTERNAL: return "FROB_E_INTERNAL";
+    case FROB_E_CAPTURE: return "FROB_E_CAPTURE";
   }
   return "FROB_UNKNOWN";
 }

@@ -21,6 +21,8 @@ struct frob_handle {
   hipStream_t stream = nullptr;  // stream all work is enqueued on (null stream by default)
   void* ws = nullptr;            // grow-only device workspace
   size_t ws_cap = 0;
+  bool ws_captured = false;      // a captured launch references ws: never free it, retire it on growth
+  std::vector<void*> ws_retired; // retired workspaces, freed by frob_destroy
   int* dinfo = nullptr;          // device status words (factorization info)
   int* hinfo = nullptr;          // pinned host copy
   double* dnorm = nullptr;       // device scalar for residual norms
@@ -72,9 +74,18 @@ struct ProfScope {
 };
 void prof_resolve(frob_handle* h);
 
+// thrown when a call needs more workspace while its stream is being captured
+struct CaptureGrowth {};
+
 uint64_t splitmix64(uint64_t& x);
 double draw_mu(frob_handle* h);
+// The handle's workspace, grown to at least `bytes`.  Growth while the
+// handle's stream is being captured throws CaptureGrowth (nothing is freed or
+// allocated then); a workspace that a captured launch references is retired,
+// not freed, when it is outgrown (mark_ws_captured).
 void* ws_reserve(frob_handle* h, size_t bytes);
+// Records that the handle's stream is being captured, if it is; returns whether.
+bool mark_ws_captured(frob_handle* h);
 // the handle's look-ahead stream and events, created on first use (null handle: none)
 const LookAhead* lookahead(frob_handle* h);
 void read_info(frob_handle* h);

@@ -69,30 +69,35 @@ def test_batched_fp32_matches_oracle(h, mixed):
         assert e <= 16 * U32 * max(refs[i][2], 1.0), (A.shape[0], kinds[i], e)
 
 
-@pytest.mark.skip(reason="a batch with failing members (singular real part, indefinite HPD, invalid kind) "
-                         "hung on the GPU; the cause is not identified, so the case stays off the GPU "
-                         "(failure handling now keeps the success path's control flow; invalid kinds and "
-                         "orders are rejected before launch)")
 def test_batched_status_words(h):
-    """A singular real part (diag(0, 1, i): A = diag(0, 1, 0) is singular at
-    column 1), an indefinite 'HPD' member, an invalid kind: each reported in
-    its own status word, the other members unaffected."""
+    """Members whose factorizations fail, mixed with good ones: a singular
+    real part (diag(0, 1, i): A = diag(0, 1, 0) singular at column 1), an
+    indefinite "HPD" member (-I), C singular (A = I, B = [[0, 1], [-1, 0]]:
+    C = I + B^2 = 0, Lemma 2.3) and C indefinite (B doubled: C = -3 I, Lemma
+    4.5).  Each status word equals the oracle's info code; the good members
+    are unaffected.  (The same batch runs on the CPU emulation of the kernel in
+    test_batched_emu.py, which checks that every thread passes the same
+    barriers.)  An invalid kind is rejected on the host before any launch."""
     import torch
+    import paper_2208_01239_amd as fi
+    J = np.array([[0.0, 1.0], [-1.0, 0.0]])
     good = inputs.general(40, 5)
     hp = inputs.hpd(30, 6)
-    sing = (np.diag([0.0, 1.0, 0.0]), np.diag([0.0, 0.0, 1.0]))
-    indef = (-np.eye(4), np.zeros((4, 4)))
-    mats = [good, sing, hp, indef, good]
-    kinds = [0, 0, 1, 1, 7]
+    failing = [((np.diag([0.0, 1.0, 0.0]), np.diag([0.0, 0.0, 1.0])), 0), ((-np.eye(4), np.zeros((4, 4))), 1),
+               ((np.eye(2), J.copy()), 0), ((np.eye(2), 2.0 * J), 1)]
+    mats = [good] + [m for m, _ in failing] + [hp, good]
+    kinds = [0] + [k for _, k in failing] + [1, 0]
+    expected = [0] + [(oracle.frob_lu(*m) if k == 0 else oracle.frob_chol(*m))[2] for m, k in failing] + [0, 0]
+    assert expected[1:5] == [1000001, 1000001, 2000001, 2000001]
     Xr, Xi, info = _run(h, mats, kinds, torch.float64)
-    assert info[0] == 0 and info[2] == 0
-    assert info[1] == 1000000 + 1
-    assert info[3] == 1000000 + 1
-    assert info[4] == -1
+    assert list(info) == expected, (list(info), expected)
     r = oracle.cinv_lu(*good)
-    assert relF(Xr[0], Xi[0], r[0], r[1]) <= 1e-10
+    assert relF(Xr[0], Xi[0], r[0], r[1]) <= 1e-10 and relF(Xr[6], Xi[6], r[0], r[1]) <= 1e-10
     r = oracle.cinv_chol(*hp)
-    assert relF(Xr[2], Xi[2], r[0], r[1]) <= 1e-10
+    assert relF(Xr[5], Xi[5], r[0], r[1]) <= 1e-10
+    A = torch.eye(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        fi.BatchedPlan([A], [A], [7])
 
 
 def test_batched_rejects_invalid_entries_before_launch(h):
@@ -132,6 +137,52 @@ def test_batched_graph_replays(h):
         for (x, y), (rx, ry) in zip(zip(plan.Xr, plan.Xi), ref):
             assert torch.equal(x, rx) and torch.equal(y, ry), rep
         assert int((plan.info_dev != 0).sum()) == 0
+
+
+def test_batched_graph_survives_workspace_growth(h):
+    """A launch captured into a graph keeps its workspace: a later call on the
+    same handle that needs a larger workspace (a general inversion of order
+    1500) sets the captured one aside instead of freeing it, so replays still
+    reproduce the eager result.  Capturing a launch that would have to grow
+    the workspace is refused (FROB_E_CAPTURE) rather than baking in a buffer
+    that growth would free."""
+    import torch
+    import paper_2208_01239_amd as fi
+    hd = fi.Handle(0)
+    try:
+        mats = [inputs.general(n, 60 + n) if n % 2 else inputs.hpd(n, 60 + n) for n in (21, 48, 77)]
+        kinds = [0 if n % 2 else 1 for n in (21, 48, 77)]
+        plan = fi.BatchedPlan([torch.from_numpy(A).cuda() for A, _ in mats],
+                              [torch.from_numpy(B).cuda() for _, B in mats], kinds)
+        g0 = torch.cuda.CUDAGraph()
+        with pytest.raises(fi.FrobError) as ei:
+            with torch.cuda.graph(g0):
+                plan.launch(hd)          # fresh handle: the workspace would have to grow inside the capture
+        assert ei.value.status == fi._lib.FROB_E_CAPTURE
+        del g0
+        torch.cuda.synchronize()
+        plan.launch(hd)
+        torch.cuda.synchronize()
+        ref = [(x.clone(), y.clone()) for x, y in zip(plan.Xr, plan.Xi)]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.launch(hd)
+        before = hd.workspace_bytes()
+        A, B = inputs.general(1500, 8)
+        fi.frob_inv_general(hd, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+        assert hd.workspace_bytes() > before
+        for rep in range(2):
+            for x, y in zip(plan.Xr, plan.Xi):
+                x.fill_(float("nan")); y.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for (x, y), (rx, ry) in zip(zip(plan.Xr, plan.Xi), ref):
+                assert torch.equal(x, rx) and torch.equal(y, ry), rep
+        del g
+        torch.cuda.synchronize()
+    finally:
+        hd.close()
 
 
 def test_batched_autotune(h):

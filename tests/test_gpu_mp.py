@@ -101,13 +101,25 @@ def test_newton_schulz_squares_the_residual(h):
 
 def test_no_convergence_reported(h):
     """BF16 operands on a general matrix with kappa = 1e4: ||I - M X0||_F >= 1, so
-    refinement cannot start; the status says so and X is returned unrefined."""
+    the start needs the spectral-norm estimate.  Either refinement is refused
+    (estimate >= 1, or the residual grew and X0 was restored) -- then X is the
+    unrefined inverse, bit for bit -- or it converges to the FP64 bar."""
     import paper_2208_01239_amd as fi
-    A, B, _, _ = _case("general", 1e4)
-    with pytest.raises(fi.FrobNoConvergenceError) as ex:
-        _inv(h, "general", A, B, prec=2, refine=4)
-    r = ex.value.result
-    assert r.refine_steps == 0 and r.resid0 * math.sqrt(N) >= 1.0
+    import torch
+    A, B, Rr, Ri = _case("general", 1e4)
+    dA, dB = to_dev(A), to_dev(B)
+    U = fi.frob_inv_general(h, dA, dB, prec=2)
+    Xr, Xi = torch.empty_like(dA), torch.empty_like(dA)
+    try:
+        _, _, res = fi.frob_inv_general(h, dA, dB, Xr, Xi, prec=2, refine=8)
+    except fi.FrobNoConvergenceError as ex:
+        r = ex.result
+        print(f"bf16 general: refused, resid0 {r.resid0:.2e}, norm2_est {r.norm2_est:.2e}")
+        assert r.refine_steps == 0 and r.resid0 * math.sqrt(N) >= 1.0 and r.norm2_est > 0.0
+        assert torch.equal(Xr, U[0]) and torch.equal(Xi, U[1])
+        return
+    print(f"bf16 general: converged in {res['refine_steps']} steps, norm2_est {res['norm2_est']:.2e}")
+    assert relF(to_host(Xr), to_host(Xi), Rr, Ri) <= TOL
 
 
 def test_fp64_precision_flag_is_default(h):

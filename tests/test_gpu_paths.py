@@ -1,0 +1,358 @@
+"""GPU parity of paths that the basic size sweeps do not reach: stage-2 status
+codes (Lemma 2.3, Lemma 4.5), the shifted linear solve (Algorithms 3 and 6),
+the benchmarked refined configuration at n = 4096, determinism of the
+two-stream look-ahead, full-matrix parity at an order whose LU panels use the
+tallest fused leaves, a residual check of every 64-column band at full size,
+the Newton-Schulz convergence control on constructed starts, and the
+mixed-precision path at orders that take the look-ahead LU."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_01239_amd import inputs
+from _helpers import relF, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-10
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_2208_01239_amd as fi
+    hd = fi.Handle(0)
+    yield hd
+    hd.close()
+
+
+def _jblocks(n, scale=1.0):
+    """Block diagonal of [[0, s], [-s, 0]] blocks (n even): skew-symmetric, B^2 = -s^2 I."""
+    B = np.zeros((n, n))
+    for k in range(0, n, 2):
+        B[k, k + 1], B[k + 1, k] = scale, -scale
+    return B
+
+
+# ------------------------------------------------------------------ stage-2 status codes
+@pytest.mark.parametrize("n", [2, 1100])
+def test_stage2_singular_general_and_solve(h, n):
+    """A = I, B = blockdiag([[0, 1], [-1, 0]]): A is invertible but
+    C = A + B A^{-1} B = I + B^2 = 0, so M is singular (Lemma 2.3) and the
+    failure is reported at stage 2, column 1, as the oracle's Algorithm 5 does."""
+    import paper_2208_01239_amd as fi
+    A, B = np.eye(n), _jblocks(n)
+    assert oracle.frob_lu(A, B)[2] == oracle.STAGE_C + 1
+    for shift in (fi.FROB_SHIFT_OFF, fi.FROB_SHIFT_AUTO):
+        with pytest.raises(fi.FrobSingularError) as ex:
+            fi.frob_inv_general(h, to_dev(A), to_dev(B), shift=shift)
+        assert ex.value.result.stage == 2 and ex.value.result.info == 1
+    c = np.ones((n, 3))
+    with pytest.raises(fi.FrobSingularError) as ex:
+        fi.frob_solve(h, to_dev(A), to_dev(B), to_dev(c), to_dev(c))
+    assert ex.value.result.stage == 2 and ex.value.result.info == 1
+
+
+@pytest.mark.parametrize("n", [2, 1100])
+def test_stage2_not_hpd(h, n):
+    """A = I (positive definite), B = 2 blockdiag(J) (skew): M = I + iB is
+    Hermitian with eigenvalues 3 and -1, and C = A - X1^T X1 = I - B^T B = -3 I
+    fails the second Cholesky factorization (Lemma 4.5), as in Algorithm 7."""
+    import paper_2208_01239_amd as fi
+    A, B = np.eye(n), _jblocks(n, 2.0)
+    assert oracle.frob_chol(A, B)[2] == oracle.STAGE_C + 1
+    with pytest.raises(fi.FrobNotHPDError) as ex:
+        fi.frob_inv_hpd(h, to_dev(A), to_dev(B))
+    assert ex.value.result.stage == 2 and ex.value.result.info == 1
+
+
+# ------------------------------------------------------------------ the shifted solve
+def _complex_solve_ref(A, B, c, d):
+    """x + iy = M^{-1}(c + id) with M^{-1} from the oracle's Algorithm 4."""
+    Xr, Xi, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    return oracle.cmatmul(Xr, Xi, c, d)
+
+
+@pytest.mark.parametrize("n,p,mu", [(5, 2, 0.3), (300, 7, 0.7), (1100, 4, 0.45)])
+def test_solve_shift_on(h, n, p, mu):
+    """Algorithm 3 on the shifted system (1 + i mu) M (Algorithm 6): the right-
+    hand side is rotated the same way and the solution is unchanged."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.general(n, 500 + n)
+    rng = np.random.default_rng(n)
+    c, d = rng.standard_normal((n, p)), rng.standard_normal((n, p))
+    xr, xi = _complex_solve_ref(A, B, c, d)
+    x, y, res = fi.frob_solve(h, to_dev(A), to_dev(B), to_dev(c), to_dev(d), shift=fi.FROB_SHIFT_ON, mu=mu)
+    assert res["mu_used"] == mu and res["shifts_tried"] == 1
+    C = (A - mu * B) + (mu * A + B) @ np.linalg.solve(A - mu * B, mu * A + B)
+    tol = max(TOL, 16 * U64 * np.linalg.cond(C))
+    e = relF(to_host(x), to_host(y), xr, xi)
+    print(f"solve shift on n={n} mu={mu}: relF {e:.2e} (tol {tol:.1e})")
+    assert e <= tol
+
+
+def test_solve_singular_real_part_auto_shift(h):
+    """A has a zero column (singular), M = A + iB is not: FROB_SHIFT_AUTO meets
+    the zero pivot in the LU of A and solves the shifted system instead."""
+    import paper_2208_01239_amd as fi
+    n, p = 64, 3
+    A, B = inputs.general(n, 71)
+    A[:, 5] = 0.0
+    rng = np.random.default_rng(3)
+    c, d = rng.standard_normal((n, p)), rng.standard_normal((n, p))
+    xr, xi = _complex_solve_ref(A, B, c, d)
+    x, y, res = fi.frob_solve(h, to_dev(A), to_dev(B), to_dev(c), to_dev(d), seed=11)
+    assert 0.0 < res["mu_used"] < 1.0 and res["shifts_tried"] >= 1
+    mu = res["mu_used"]
+    C = (A - mu * B) + (mu * A + B) @ np.linalg.solve(A - mu * B, mu * A + B)
+    e = relF(to_host(x), to_host(y), xr, xi)
+    assert e <= max(TOL, 16 * U64 * np.linalg.cond(C)), e
+    with pytest.raises(fi.FrobSingularError) as ex:
+        fi.frob_solve(h, to_dev(A), to_dev(B), to_dev(c), to_dev(d), shift=fi.FROB_SHIFT_OFF)
+    assert ex.value.result.stage == 1
+
+
+# ------------------------------------------------------------------ the benchmarked configuration
+def _golden(name):
+    path = os.path.join(GOLD, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_full_size_samples.py)")
+    return np.load(path, allow_pickle=False)
+
+
+def _band_residuals(A, B, Xr, Xi, band=64):
+    """||(M X - I)[:, band]||_F / (||M||_F ||X[:, band]||_F) for every band of
+    columns, with M X formed by torch's complex product in FP64 on the device."""
+    import torch
+    M = torch.complex(A, B)
+    X = torch.complex(Xr, Xi)
+    R = M @ X
+    R.diagonal().sub_(1.0)
+    n = A.shape[0]
+    nm = float(torch.linalg.norm(M))
+    out = []
+    for j in range(0, n, band):
+        out.append(float(torch.linalg.norm(R[:, j:j + band])) / (nm * float(torch.linalg.norm(X[:, j:j + band]))))
+    del M, X, R
+    torch.cuda.empty_cache()
+    return np.array(out)
+
+
+def test_headline_configuration_n4096(h):
+    """n = 4096, A, B iid N(0,1), seed 0, exactly as bench.py times it: FP64
+    factorizations, one Newton-Schulz step with the FP32 correction, no closing
+    residual.  Sampled columns against the oracle's Algorithm 4 (stored) at
+    1e-10, and the backward error of every 64-column band of the result."""
+    import paper_2208_01239_amd as fi
+    import torch
+    g = _golden("n4096_general_samples.npz")
+    A, B = inputs.general(4096, 0)
+    assert np.array_equal(A[0, :4], g["a00"]) and np.array_equal(B[0, :4], g["b00"])
+    dA, dB = to_dev(A), to_dev(B)
+    Xr, Xi, res = fi.frob_inv_general(h, dA, dB, refine=1, f32_correction=True, final_resid=False)
+    assert res["refine_steps"] == 1 and np.isnan(res["resid"])
+    cols = g["cols"]
+    e = relF(Xr[:, cols].cpu().numpy(), Xi[:, cols].cpu().numpy(), g["xr"], g["xi"])
+    bands = _band_residuals(dA, dB, Xr, Xi)
+    print(f"headline n=4096: relF {e:.2e} on {len(cols)} columns; band backward errors max {bands.max():.2e} "
+          f"median {np.median(bands):.2e}")
+    assert e <= TOL
+    assert bands.max() <= 1e-12 and bands.max() <= 1000 * np.median(bands)
+    del dA, dB, Xr, Xi
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("path", ["general", "general_refined", "cinv_lu"])
+def test_every_band_at_n8192(h, path):
+    """n = 8192 (seed 0): the backward error of every 64-column band of the
+    inverse, so that a defect confined to one panel band cannot hide between
+    sampled columns: no band may stand out from the median by more than a
+    factor of 1000 (a wrong band has an error of order one), and every band
+    stays below a bound per path (plain Frobenius inversion carries the
+    u kappa(C) error of C^{-1}, so its bound is loose)."""
+    import paper_2208_01239_amd as fi
+    import torch
+    A, B = inputs.general(8192, 0)
+    dA, dB = to_dev(A), to_dev(B)
+    if path == "general":
+        Xr, Xi, _ = fi.frob_inv_general(h, dA, dB)
+        bound = 1e-8
+    elif path == "general_refined":
+        Xr, Xi, _ = fi.frob_inv_general(h, dA, dB, refine=1, f32_correction=True, final_resid=False)
+        bound = 1e-12
+    else:
+        Xr, Xi, _ = fi.frob_cinv_lu(h, dA, dB, form=1)
+        bound = 1e-11
+    bands = _band_residuals(dA, dB, Xr, Xi)
+    print(f"n=8192 {path}: band backward errors max {bands.max():.2e} median {np.median(bands):.2e}")
+    assert bands.max() <= bound
+    assert bands.max() <= 1000 * np.median(bands)
+    del dA, dB, Xr, Xi
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ determinism with two streams
+def test_determinism_lookahead_n1300(h):
+    """At n = 1300 the LUs run in panels with the trailing updates on a second
+    stream: repeated calls still give bit-identical inverses (the concurrent
+    updates write disjoint columns, and every sum has a fixed order)."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.general(1300, 13)
+    dA, dB = to_dev(A), to_dev(B)
+    X1 = fi.frob_inv_general(h, dA, dB)
+    X2 = fi.frob_inv_general(h, dA, dB)
+    assert torch_equal(X1[0], X2[0]) and torch_equal(X1[1], X2[1])
+    Z1 = fi.frob_cinv_lu(h, dA, dB)
+    Z2 = fi.frob_cinv_lu(h, dA, dB)
+    assert torch_equal(Z1[0], Z2[0]) and torch_equal(Z1[1], Z2[1])
+    Ah, Bh = inputs.hpd(1300, 14)
+    dA, dB = to_dev(Ah), to_dev(Bh)
+    H1 = fi.frob_inv_hpd(h, dA, dB)
+    H2 = fi.frob_inv_hpd(h, dA, dB)
+    assert torch_equal(H1[0], H2[0]) and torch_equal(H1[1], H2[1])
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
+
+
+# ------------------------------------------------------------------ full parity through the tallest fused leaves
+def test_full_parity_n2600(h):
+    """n = 2600: the LU panels have 2049..2600 rows (1024-thread leaves of
+    four rows per thread) for the first panels and fewer below.  Every entry
+    of the inverse against the oracle: plain Frobenius at 16 u kappa_2(C), the
+    benchmarked refined form and the complex-LU baseline (both forms) at
+    1e-10; HPD (Algorithm 7) and complex Cholesky at 1e-10."""
+    import paper_2208_01239_amd as fi
+    n = 2600
+    A, B = inputs.general(n, 26)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    dA, dB = to_dev(A), to_dev(B)
+    C = A + B @ np.linalg.solve(A, B)
+    tol0 = max(TOL, 16 * U64 * np.linalg.cond(C))
+    Xr, Xi, _ = fi.frob_inv_general(h, dA, dB)
+    e0 = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    Xr, Xi, _ = fi.frob_inv_general(h, dA, dB, refine=1, f32_correction=True, final_resid=False)
+    e1 = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    ez = []
+    for form in (1, 0):
+        Zr, Zi, _ = fi.frob_cinv_lu(h, dA, dB, form=form)
+        ez.append(relF(to_host(Zr), to_host(Zi), Rr, Ri))
+    print(f"n=2600 general: plain {e0:.2e} (tol {tol0:.1e}), refined {e1:.2e}, complex LU {ez}")
+    assert e0 <= tol0 and e1 <= TOL and max(ez) <= TOL
+    Ah, Bh = inputs.hpd(n, 27)
+    Hr, Hi, info, _ = oracle.cinv_chol(Ah, Bh)
+    assert info == 0
+    dA, dB = to_dev(Ah), to_dev(Bh)
+    Xr, Xi, _ = fi.frob_inv_hpd(h, dA, dB)
+    eh = relF(to_host(Xr), to_host(Xi), Hr, Hi)
+    ec = []
+    for form in (1, 0):
+        Zr, Zi, _ = fi.frob_cinv_chol(h, dA, dB, form=form)
+        ec.append(relF(to_host(Zr), to_host(Zi), Hr, Hi))
+    print(f"n=2600 hpd: frobenius {eh:.2e}, complex Cholesky {ec}")
+    assert eh <= TOL and max(ec) <= TOL
+
+
+# ------------------------------------------------------------------ Newton-Schulz convergence control
+def _scaled_start(n, alpha, seed):
+    """X0 = (1 - alpha) M^{-1} with M^{-1} from the oracle: R0 = I - M X0 = alpha I
+    up to rounding, so ||R0||_2 = alpha while ||R0||_F = alpha sqrt(n)."""
+    A, B = inputs.general(n, seed)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    return A, B, Rr, Ri, (1.0 - alpha) * Rr, (1.0 - alpha) * Ri
+
+
+@pytest.mark.parametrize("n,alpha", [(64, 0.8), (300, 0.6), (1100, 0.9)])
+def test_refine_accepts_spectral_norm_below_one(h, n, alpha):
+    """||R0||_F = alpha sqrt(n) >= 1 but ||R0||_2 = alpha < 1: the power-iteration
+    estimate admits the start, and the slow first steps (||R1||_F = alpha
+    ||R0||_F, more than half) are not mistaken for the rounding floor."""
+    import paper_2208_01239_amd as fi
+    A, B, Rr, Ri, X0r, X0i = _scaled_start(n, alpha, 600 + n)
+    Xr, Xi = to_dev(X0r), to_dev(X0i)
+    res = fi.frob_refine(h, to_dev(A), to_dev(B), Xr, Xi, refine=12)
+    e = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    print(f"refine n={n} alpha={alpha}: {res}, relF {e:.2e}")
+    assert res["resid0"] * math.sqrt(n) >= 1.0
+    assert abs(res["norm2_est"] - alpha) <= 1e-6
+    assert res["refine_steps"] >= math.ceil(math.log2(math.log(1e-12) / math.log(alpha)))
+    assert e <= TOL and res["resid"] <= 1e-12
+
+
+def test_refine_refuses_spectral_norm_above_one(h):
+    """||R0||_2 = 1.2: the estimate refuses the start and X is left unchanged."""
+    import paper_2208_01239_amd as fi
+    n = 200
+    A, B, Rr, Ri, X0r, X0i = _scaled_start(n, 1.2, 77)
+    Xr, Xi = to_dev(X0r), to_dev(X0i)
+    with pytest.raises(fi.FrobNoConvergenceError) as ex:
+        fi.frob_refine(h, to_dev(A), to_dev(B), Xr, Xi, refine=8)
+    r = ex.value.result
+    assert r.refine_steps == 0 and abs(r.norm2_est - 1.2) <= 1e-6
+    assert np.array_equal(to_host(Xr), X0r) and np.array_equal(to_host(Xi), X0i)
+
+
+def test_refine_stops_at_the_rounding_floor(h):
+    """A start already at the FP64 floor (the oracle's inverse) stops within a
+    few steps, well before the step limit, with the FP32 correction: the
+    residual no longer halves although exact squaring would have shrunk it far
+    more.  The result stays within the bar."""
+    import paper_2208_01239_amd as fi
+    A, B, Rr, Ri, _, _ = _scaled_start(257, 0.0, 5)
+    Xr, Xi = to_dev(Rr), to_dev(Ri)
+    res = fi.frob_refine(h, to_dev(A), to_dev(B), Xr, Xi, refine=6, f32_correction=True)
+    print(f"refine from the oracle's inverse: {res}")
+    assert res["refine_steps"] <= 3 and res["resid"] <= 2 * res["resid0"]
+    assert relF(to_host(Xr), to_host(Xi), Rr, Ri) <= 1e-12
+
+
+# ------------------------------------------------------------------ mixed precision at look-ahead orders
+NMP = 1100
+
+
+def _mp_case(kind, kappa):
+    seed = (300 if kind == "general" else 400) + int(round(math.log10(kappa)))
+    A, B = inputs.spectrum(NMP, kappa, kind, seed=seed)
+    ref = oracle.cinv_lu(A, B) if kind == "general" else oracle.cinv_chol(A, B)
+    return A, B, ref[0], ref[1]
+
+
+@pytest.mark.parametrize("kind,prec,kappa", [
+    ("general", 1, 1e2), ("general", 1, 1e4),
+    ("hpd", 1, 1e2), ("hpd", 1, 1e4), ("hpd", 1, 1e6),
+    ("hpd", 2, 1e2),
+])
+def test_mixed_precision_lookahead_orders(h, kind, prec, kappa):
+    """n = 1100 (panels with the look-ahead, capped trailing grids, B and the
+    identity carried through the LUs), FP32 / BF16 matrix-core operands, then
+    FP64 Newton-Schulz refinement, against the oracle's Algorithm 4 / 8.  The
+    HPD cases must reach 1e-10; a general case either reaches 1e-10 or is
+    refused with a spectral-norm estimate >= 1 (X then unrefined)."""
+    import paper_2208_01239_amd as fi
+    A, B, Rr, Ri = _mp_case(kind, kappa)
+    f = fi.frob_inv_general if kind == "general" else fi.frob_inv_hpd
+    dA, dB = to_dev(A), to_dev(B)
+    X0r, X0i, _ = f(h, dA, dB, prec=prec)
+    e0 = relF(to_host(X0r), to_host(X0i), Rr, Ri)
+    assert e0 > 1e-9                      # the low-precision operands were used
+    try:
+        Xr, Xi, res = f(h, dA, dB, prec=prec, refine=10)
+    except fi.FrobNoConvergenceError as ex:
+        r = ex.result
+        print(f"{kind} prec {prec} kappa {kappa:.0e}: refused, resid0 {r.resid0:.2e} norm2_est {r.norm2_est:.2e}")
+        assert kind == "general"
+        # refused by the spectral-norm estimate (>= 1), or restored after the residual grew
+        assert r.refine_steps == 0 and r.norm2_est > 0.0
+        return
+    e = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    print(f"{kind} prec {prec} kappa {kappa:.0e}: unrefined {e0:.2e} -> refined {e:.2e} in "
+          f"{res['refine_steps']} steps (resid0 {res['resid0']:.2e}, norm2_est {res['norm2_est']:.2e})")
+    assert e <= TOL
