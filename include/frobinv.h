@@ -233,6 +233,23 @@ frob_status_t frob_inv_batched(frob_handle_t handle, int count, int nmax, const 
                                const void *const *A_dev, const void *const *B_dev, void *const *Xr_dev,
                                void *const *Xi_dev, int *info_dev, int storage);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched inversion as frob_inv_batched, same arguments and results, with its
+ * scratch (queue head, processing order, per-workgroup slots of three
+ * nmax x nmax matrices) in a fixed device array of 128 MiB that the library
+ * holds on every GPU it runs on until the process ends.  Nothing is
+ * allocated or freed and the handle's workspace is not used.  Limits:
+ * count <= 1048576, nmax <= 512; the persistent grid is the number of compute
+ * units or the number of slots that fit, whichever is smaller (at least 20;
+ * all 256 for nmax <= 147 in FP64 and nmax <= 208 in FP32).  Returns FROB_E_ARG
+ * beyond the limits.  Calls that overlap on one GPU (concurrent streams,
+ * handles or threads) share the array and race: order them.  Each call
+ * rewrites the queue head and order before its kernel reads them. */
+frob_status_t frob_inv_batched_noalloc(frob_handle_t handle, int count, int nmax, const int *n_dev,
+                                       const int *kind_dev, const void *const *A_dev, const void *const *B_dev,
+                                       void *const *Xr_dev, void *const *Xi_dev, int *info_dev, int storage);
+
 /* Autotuner for frob_inv_batched: for each kind and order class (<= 64, 128,
  * 256, 512) times the persistent kernel on synthetic diagonally dominant
  * batches with panel widths 8, 16 and 32 and keeps the fastest in the handle.

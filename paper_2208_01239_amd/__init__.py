@@ -300,15 +300,17 @@ class BatchedPlan:
         self.pA, self.pB, self.pXr, self.pXi = ptrs(self.As), ptrs(self.Bs), ptrs(self.Xr), ptrs(self.Xi)
         self.info_dev = torch.zeros(self.count, dtype=torch.int32, device=dev)
 
-    def launch(self, h: "Handle"):
-        """Enqueue the batched inversion on the handle's stream (asynchronous)."""
+    def launch(self, h: "Handle", noalloc: bool = False):
+        """Enqueue the batched inversion on the handle's stream (asynchronous).
+        noalloc=True uses frob_inv_batched_noalloc (fixed device scratch, no allocation)."""
         h.bind_stream()
         vp = ctypes.c_void_p
-        st = _lib.load().frob_inv_batched(h.ptr, self.count, self.nmax, vp(self.n_dev.data_ptr()),
-                                          vp(self.kind_dev.data_ptr()), vp(self.pA.data_ptr()),
-                                          vp(self.pB.data_ptr()), vp(self.pXr.data_ptr()),
-                                          vp(self.pXi.data_ptr()), vp(self.info_dev.data_ptr()), self.storage)
-        _lib.check(st, "frob_inv_batched")
+        name = "frob_inv_batched_noalloc" if noalloc else "frob_inv_batched"
+        st = getattr(_lib.load(), name)(h.ptr, self.count, self.nmax, vp(self.n_dev.data_ptr()),
+                                         vp(self.kind_dev.data_ptr()), vp(self.pA.data_ptr()),
+                                         vp(self.pB.data_ptr()), vp(self.pXr.data_ptr()),
+                                         vp(self.pXi.data_ptr()), vp(self.info_dev.data_ptr()), self.storage)
+        _lib.check(st, name)
 
 
 def frob_inv_batched(h: Handle, As, Bs, kinds):

@@ -73,6 +73,7 @@ SIGNATURES = {
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_inv_adjoint": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "frob_inv_batched": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i]),
+    "frob_inv_batched_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i]),
     "frob_batched_tune": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_int)]),
     "frob_profile_enable": (_i, [_vp, _i]),
     "frob_profile_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_d),

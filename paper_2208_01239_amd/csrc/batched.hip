@@ -20,7 +20,9 @@
 // workgroup owns a private slot of workspace (three n_max x n_max matrices and
 // the pivot indices).  Panel width NB per size class comes from the caller's
 // table (autotuned by frob_batched_tune).
+#include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "common.hpp"
 #include "handle.hpp"
@@ -83,16 +85,17 @@ int batched_grid(frob_handle* h) {
   return cus > 0 ? cus : 256;
 }
 
-// counter | order[count] | per-workgroup slots
-void batched_launch(frob_handle* h, int count, int nmax, const int* n_dev, const int* kind_dev, const void* const* A,
-                    const void* const* B, void* const* Xr, void* const* Xi, int* info_dev, int storage) {
+size_t batched_slot_elems(int nmax, int storage) {
+  const size_t el = storage == FROB_PREC_F32 ? sizeof(float) : sizeof(double);
+  return 3 * (size_t)nmax * nmax + ((size_t)nmax * sizeof(int) + el - 1) / el + 64;
+}
+
+// The two launches of a batched inversion on memory the caller provides:
+// the queue head, the order array (count ints) and `grid` slots.
+static void batched_enqueue(frob_handle* h, int grid, int* counter, int* order, void* slots, int count, int nmax,
+                            const int* n_dev, const int* kind_dev, const void* const* A, const void* const* B,
+                            void* const* Xr, void* const* Xi, int* info_dev, int storage) {
   hipStream_t s = h->stream;
-  const int grid = batched_grid(h);
-  char* ws = (char*)ws_reserve(h, batched_ws_bytes(grid, nmax, count, storage));
-  mark_ws_captured(h);   // a captured launch keeps this workspace alive
-  int* counter = reinterpret_cast<int*>(ws);
-  int* order = reinterpret_cast<int*>(ws + 256);
-  void* slots = ws + 256 + (((size_t)count * sizeof(int) + 255) & ~size_t(255));
   hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(1024), 0, s, count, n_dev, order, counter);
   FROB_LAUNCH_CHECK();
   BatchArgs g;
@@ -100,15 +103,55 @@ void batched_launch(frob_handle* h, int count, int nmax, const int* n_dev, const
   g.A = A; g.B = B; g.Xr = Xr; g.Xi = Xi; g.info = info_dev;
   g.order = order; g.counter = counter; g.ws = slots;
   g.nmax = nmax;
-  const size_t el = storage == FROB_PREC_F32 ? sizeof(float) : sizeof(double);
-  g.slot_elems = 3 * (long long)nmax * nmax + ((long long)nmax * sizeof(int) + el - 1) / el + 64;
+  g.slot_elems = (long long)batched_slot_elems(nmax, storage);
   const int si = storage == FROB_PREC_F32 ? 1 : 0;
   for (int k = 0; k < 2; ++k)
     for (int c = 0; c < 4; ++c) g.nb_table[k][c] = h->batch_nb[si][k][c];
-  ProfScope ps(h, PROF_BATCHED, 0.0);
   if (storage == FROB_PREC_F32) hipLaunchKernelGGL(k_batched_inv<float>, dim3(grid), dim3(BT), 0, s, g);
   else hipLaunchKernelGGL(k_batched_inv<double>, dim3(grid), dim3(BT), 0, s, g);
   FROB_LAUNCH_CHECK();
+}
+
+// counter | order[count] | per-workgroup slots, in the handle's workspace
+void batched_launch(frob_handle* h, int count, int nmax, const int* n_dev, const int* kind_dev, const void* const* A,
+                    const void* const* B, void* const* Xr, void* const* Xi, int* info_dev, int storage) {
+  const int grid = batched_grid(h);
+  char* ws = (char*)ws_reserve(h, batched_ws_bytes(grid, nmax, count, storage));
+  mark_ws_captured(h);   // a captured launch keeps this workspace alive
+  int* counter = reinterpret_cast<int*>(ws);
+  int* order = reinterpret_cast<int*>(ws + 256);
+  void* slots = ws + 256 + (((size_t)count * sizeof(int) + 255) & ~size_t(255));
+  ProfScope ps(h, PROF_BATCHED, 0.0);
+  batched_enqueue(h, grid, counter, order, slots, count, nmax, n_dev, kind_dev, A, B, Xr, Xi, info_dev, storage);
+}
+
+// ----------------------------------------------------- no-allocation variant
+namespace {
+
+// Scratch of frob_inv_batched_noalloc (queue head, order array, workgroup
+// slots) as a file-scope device array: each GPU the library runs on holds
+// its own copy until the process ends.  Host code must use the per-device
+// address resolved in batched_scratch_init, never the array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+constexpr int NOALLOC_MAX_COUNT = 1 << 20;
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+char* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < NOALLOC_MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
+}  // namespace
+
+void batched_scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES || g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  FROB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));   // `device` is current
+  g_scratch_ptr[device] = static_cast<char*>(p);
 }
 
 namespace {
@@ -167,6 +210,33 @@ extern "C" frob_status_t frob_inv_batched(frob_handle_t h, int count, int nmax, 
     return FROB_E_ALLOC;
   } catch (const CaptureGrowth&) {
     return FROB_E_CAPTURE;
+  } catch (const HipError&) {
+    return FROB_E_HIP;
+  } catch (...) {
+    return FROB_E_INTERNAL;
+  }
+}
+
+extern "C" frob_status_t frob_inv_batched_noalloc(frob_handle_t h, int count, int nmax, const int* n_dev,
+                                                  const int* kind_dev, const void* const* A_dev,
+                                                  const void* const* B_dev, void* const* Xr_dev, void* const* Xi_dev,
+                                                  int* info_dev, int storage) {
+  if (!h || count < 1 || count > NOALLOC_MAX_COUNT || nmax < 1 || nmax > BNMAX || !n_dev || !kind_dev || !A_dev ||
+      !B_dev || !Xr_dev || !Xi_dev || !info_dev || (storage != FROB_PREC_F64 && storage != FROB_PREC_F32))
+    return FROB_E_ARG;
+  try {
+    FROB_HIP(hipSetDevice(h->device));
+    char* base = scratch_ptr(h->device);
+    if (!base) return FROB_E_INTERNAL;
+    const size_t head = 256 + (((size_t)count * sizeof(int) + 255) & ~size_t(255));
+    const size_t el = storage == FROB_PREC_F32 ? sizeof(float) : sizeof(double);
+    const size_t slot_bytes = batched_slot_elems(nmax, storage) * el;
+    const size_t fit = (NOALLOC_SCRATCH_BYTES - head) / slot_bytes;   // >= 20 for every accepted shape
+    const int grid = (int)std::min<size_t>((size_t)batched_grid(h), fit);
+    if (grid < 1) return FROB_E_ARG;
+    batched_enqueue(h, grid, reinterpret_cast<int*>(base), reinterpret_cast<int*>(base + 256), base + head, count,
+                    nmax, n_dev, kind_dev, A_dev, B_dev, Xr_dev, Xi_dev, info_dev, storage);
+    return FROB_OK;
   } catch (const HipError&) {
     return FROB_E_HIP;
   } catch (...) {

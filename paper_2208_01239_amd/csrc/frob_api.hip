@@ -295,6 +295,7 @@ frob_status_t frob_create(frob_handle_t* out, int device) {
   h->rng = 0x2208012390ull;
   try {
     FROB_HIP(hipSetDevice(device));
+    batched_scratch_init(device);
     h->stream = nullptr;   // the device's null stream until frob_set_stream says otherwise
     FROB_HIP(hipMalloc((void**)&h->dinfo, sizeof(int) * INFO_SLOTS));
     FROB_HIP(hipHostMalloc((void**)&h->hinfo, sizeof(int) * INFO_SLOTS, hipHostMallocDefault));

@@ -86,6 +86,9 @@ double draw_mu(frob_handle* h);
 void* ws_reserve(frob_handle* h, size_t bytes);
 // Records that the handle's stream is being captured, if it is; returns whether.
 bool mark_ws_captured(frob_handle* h);
+// Resolves, once per device, the device address of the no-allocation batched
+// entry point's scratch array (the device must be current).
+void batched_scratch_init(int device);
 // the handle's look-ahead stream and events, created on first use (null handle: none)
 const LookAhead* lookahead(frob_handle* h);
 void read_info(frob_handle* h);
