@@ -17,11 +17,14 @@ persistent launch, FP64 and FP32) beside a per-matrix complex-LU loop on a
 sample of it; and the adjoint (256 HPD matrices of order 256, dM = -X^H G X^H
 by three-multiplication complex products, FP32 and FP64); Frobenius against
 complex-LU inversion at n = 8192 (same recipe, errors on the oracle's sampled
-columns).  The dominant kernel (the n x n x n FP64 matrix-core
-GEMM) is timed with HIP events on the library's stream during the timed steps
-and reported against the FP64 matrix peak.  The CPU baseline is the FP64
-oracle of the test suite timed on this host on a smaller matrix of the same
-recipe and scaled by n^3.
+columns).  The roofline kernel is the look-ahead LUs' trailing-update GEMM
+(FP64 matrix cores, on the library's second stream), timed with HIP events on
+that stream during the timed steps; the n x n x n products are reported
+beside it.  The CPU baseline is the FP64 oracle of the test suite timed on
+this host on smaller matrices of the same recipe (all threads, and one
+thread), scaled by n^3.  The JSON line on stdout carries the contract fields
+and the headline comparison; every measurement is also written to
+gpurun_out/bench_detail.json.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096]
 """
@@ -46,7 +49,9 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip HPD and baseline measurements")
-    ap.add_argument("--cpu-n", type=int, default=1536)
+    ap.add_argument("--cpu-n", type=int, default=2048)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle once at the full order on all host threads (minutes)")
     ap.add_argument("--no-mp-large", action="store_true", help="skip the n = 8192 mixed-precision leg")
     ap.add_argument("--mp-n", type=int, default=8192)
     ap.add_argument("--no-large", action="store_true", help="skip the n = 8192 Frobenius / complex-LU comparison")
@@ -276,7 +281,9 @@ def main():
 
     def measure(fn):
         """W warm-up steps, then K timed steps with the library's kernel
-        profiling on (HIP events on its stream around the n x n x n GEMMs)."""
+        profiling on: HIP events on the library's stream around the n x n x n
+        GEMMs, and on its second stream around the look-ahead LUs'
+        trailing-update GEMMs."""
         for _ in range(W):
             fn()
         torch.cuda.synchronize()
@@ -287,7 +294,7 @@ def main():
             fn()
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / K
-        prof = h.profile_read(0)
+        prof = {"nnn": h.profile_read(0), "trail": h.profile_read(6)}
         h.profile(False)
         return t, prof
 
@@ -343,7 +350,6 @@ def main():
             if chosen["refine"]:
                 break
     t_step = chosen["t"]
-    launches, gemm_ms, gemm_flops = chosen["prof"]
     berr, relf_samples = chosen["berr"], chosen["err"]
 
     extra = {"plain_fp64": {"ms": t_plain * 1e3, "relF_vs_oracle_sampled_cols": err_plain,
@@ -398,16 +404,35 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
+        # bounded sample: Algorithm 5 of the FP64 oracle on all host threads at
+        # n = cpu_n, and on one thread at n = cpu_n / 2, each scaled by n^3
         m = min(args.cpu_n, n)
         Ac, Bc = inputs.general(m, 0)
-        log(f"[bench] cpu baseline: oracle Algorithm 5 at n={m}, {oracle.num_threads()} threads")
+        threads = oracle.num_threads()
+        log(f"[bench] cpu baseline: oracle Algorithm 5 at n={m}, {threads} threads")
         tc0 = time.perf_counter()
         oracle.frob_lu(Ac, Bc)
         tc = time.perf_counter() - tc0
-        scaled = tc * (n / m) ** 3
-        cpu = {"value": 1.0 / scaled, "unit": "inversions/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"one n={m} general matrix of the same recipe (seed 0), Algorithm 5 in the FP64 oracle, "
-                         f"{tc:.2f} s, scaled to n={n} by (n/{m})^3"}
+        m1 = max(1, m // 2)
+        A1, B1 = inputs.general(m1, 0)
+        log(f"[bench] cpu baseline: oracle Algorithm 5 at n={m1}, 1 thread")
+        prev = oracle.set_num_threads(1)
+        tc1_0 = time.perf_counter()
+        oracle.frob_lu(A1, B1)
+        tc1 = time.perf_counter() - tc1_0
+        oracle.set_num_threads(prev)
+        cpu = {"value": 1.0 / (tc * (n / m) ** 3), "unit": "inversions/s", "cores": threads, "kind": "oracle",
+               "sample": f"one n={m} general matrix of the same recipe (seed 0), Algorithm 5 in the FP64 oracle on "
+                         f"{threads} threads, {tc:.2f} s, scaled to n={n} by (n/{m})^3",
+               "single_thread_value": 1.0 / (tc1 * (n / m1) ** 3),
+               "single_thread_sample": f"n={m1}, 1 thread, {tc1:.2f} s, scaled by (n/{m1})^3"}
+        if args.cpu_full and m < n:
+            log(f"[bench] cpu baseline: oracle Algorithm 5 at the full order n={n}, {threads} threads")
+            tf0 = time.perf_counter()
+            oracle.frob_lu(A, B)
+            tf = time.perf_counter() - tf0
+            cpu["full_size_value"] = 1.0 / tf
+            cpu["full_size_sample"] = f"one run at n={n} on {threads} threads, {tf:.1f} s"
 
     comparison = None
     if "cinv_lu_form1_ms" in extra:
@@ -418,20 +443,38 @@ def main():
                       "complex_lu_printed_form_ms": extra.get("cinv_lu_form0_ms"),
                       "complex_lu_printed_form_relF": extra.get("cinv_lu_form0_relF_vs_oracle_sampled_cols")}
 
-    # HBM traffic of the dominant kernel from the committed rocprofv3 counter
-    # summary, valid only while the kernel source is the one measured
-    traffic = None
-    tj = os.path.join(ROOT, "profiles", "gemm_f64_128x128_n4096_hbm_traffic.json")
-    if n == 4096 and os.path.exists(tj):
-        import hashlib
-        with open(tj) as f:
-            td = json.load(f)
-        with open(os.path.join(ROOT, "paper_2208_01239_amd", "csrc", "gemm_f64.hip"), "rb") as f:
-            cur = hashlib.sha256(f.read()).hexdigest()
-        if cur == td.get("gemm_f64_hip_sha256"):
-            traffic = td["traffic_bytes_per_launch"]
-    gemm_avg_ms = gemm_ms / launches if launches else None
-    achieved = (gemm_flops / launches) / (gemm_avg_ms * 1e-3) / 1e12 if launches else None
+    def roof(cls, kernel, traffic_file, sources):
+        launches, ms, flops = chosen["prof"][cls]
+        if not launches:
+            return None
+        avg_ms = ms / launches
+        achieved = flops / (ms * 1e-3) / 1e12
+        # HBM traffic from the committed rocprofv3 counter summary, valid only
+        # while the kernel's sources are the ones measured
+        traffic = None
+        tj = os.path.join(ROOT, "profiles", traffic_file)
+        if n == 4096 and os.path.exists(tj):
+            import hashlib
+            with open(tj) as f:
+                td = json.load(f)
+            ok = True
+            for src, key in sources:
+                with open(os.path.join(ROOT, "paper_2208_01239_amd", "csrc", src), "rb") as f:
+                    ok = ok and hashlib.sha256(f.read()).hexdigest() == td.get(key)
+            if ok:
+                traffic = td["traffic_bytes_per_launch"]
+        return {"bound": "mfma", "kernel": kernel, "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                "avg_launch_ms": avg_ms, "launches_per_step": launches / K,
+                "alg_flops_per_launch": flops / launches,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"}
+
+    roof_trail = roof("trail", "k_gemm_f64 persistent (capped grid): trailing-update GEMMs of the look-ahead LUs of A "
+                      "and C on the second stream, 2 m w k flops per launch",
+                      "gemm_f64_trailing_n4096_hbm_traffic.json",
+                      [("gemm_f64.hip", "gemm_f64_hip_sha256"), ("lu_f64.hip", "lu_f64_hip_sha256")])
+    roof_nnn = roof("nnn", "k_gemm_f64<128,128>: the n x n x n products B*Y and -Y*C^-1, 2 n^3 flops per launch",
+                    "gemm_f64_128x128_n4096_hbm_traffic.json", [("gemm_f64.hip", "gemm_f64_hip_sha256")])
     line = {
         "metric": "complex inversions/s & eff. TFLOP/s, Frobenius vs complex-LU at rel err <=1e-10",
         "value": 1.0 / t_step,
@@ -450,18 +493,30 @@ def main():
                    "newton_schulz_f32_correction": chosen.get("f32c", False),
                    "accuracy": "rel. Frobenius error vs the FP64 oracle on sampled columns <= 1e-10"},
         "eff_tflops_8n3": 8.0 * n ** 3 / t_step / 1e12,
-        "alg_tflops_26n3_3": (26.0 / 3.0) * n ** 3 / t_step / 1e12,
-        "backward_error_sampled_cols": berr,
         "relF_vs_oracle_sampled_cols": relf_samples,
-        "roofline": {"bound": "mfma", "kernel": "k_gemm_f64<128,128> (n x n x n products B*Y and -Y*C^-1)",
-                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
-                     "avg_launch_ms": gemm_avg_ms, "launches": launches, "traffic": traffic,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"},
+        "roofline": roof_trail if roof_trail is not None else roof_nnn,
+        "roofline_nnn": roof_nnn,
         "cpu_baseline": cpu,
-        "frobenius_vs_complex_lu": comparison,
     }
-    line.update(extra)
+    if "cinv_lu_form1_ms" in extra:
+        line["complex_lu_ms"] = {"getri": extra["cinv_lu_form1_ms"], "printed": extra.get("cinv_lu_form0_ms")}
+        line["frobenius_plain_ms"] = t_plain * 1e3
+        line["frobenius_plain_relF"] = err_plain
+        line["hpd_ms"] = {"frobenius": extra.get("hpd_ms"), "complex_chol_potri": extra.get("cinv_chol_form1_ms"),
+                          "complex_chol_printed": extra.get("cinv_chol_form0_ms")}
+    detail = dict(line)
+    detail["backward_error_sampled_cols"] = berr
+    detail["alg_tflops_26n3_3"] = (26.0 / 3.0) * n ** 3 / t_step / 1e12
+    detail["frobenius_vs_complex_lu"] = comparison
+    detail.update(extra)
+    out_dir = os.path.join(ROOT, "gpurun_out")
+    try:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "bench_detail.json"), "w") as f:
+            json.dump(detail, f, indent=1)
+        log(f"[bench] details written to {os.path.join(out_dir, 'bench_detail.json')}")
+    except OSError as e:
+        log(f"[bench] details not written: {e}")
     print(json.dumps(line), flush=True)
 
 

@@ -161,6 +161,24 @@ frob_status_t frob_solve(frob_handle_t handle, int n, int nrhs, const double *A,
                          const double *c, const double *d, int ldc, double *x, double *y, int ldxy,
                          const frob_opts_t *opts, frob_result_t *res);
 
+/* FP32-storage twins of frob_inv_general (Algorithm 5 with Algorithm 6),
+ * frob_inv_hpd (Algorithm 7) and frob_solve (Algorithm 3): the same
+ * arguments with float matrices (row-major, leading dimensions in elements,
+ * device memory, caller-owned).  The operands are widened into FP64 copies in
+ * the handle's workspace (4 n^2 doubles, or 2 n^2 + 4 n nrhs for the solve,
+ * ahead of the FP64 call's own), the FP64 entry point runs on them with the
+ * given options (opts->prec selects FP64, FP32 or BF16 matrix-core operands;
+ * opts->refine refines before rounding), and the results are rounded to FP32.
+ * Status and result as for the FP64 calls; on FROB_NO_CONVERGENCE the
+ * unrefined inverse is returned. */
+frob_status_t frob_inv_general_f32(frob_handle_t handle, int n, const float *A, int lda, const float *B, int ldb,
+                                   float *Xr, float *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+frob_status_t frob_inv_hpd_f32(frob_handle_t handle, int n, const float *A, int lda, const float *B, int ldb,
+                               float *Xr, float *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+frob_status_t frob_solve_f32(frob_handle_t handle, int n, int nrhs, const float *A, int lda, const float *B, int ldb,
+                             const float *c, const float *d, int ldc, float *x, float *y, int ldxy,
+                             const frob_opts_t *opts, frob_result_t *res);
+
 /* Newton-Schulz refinement of a caller-supplied approximate inverse X of
  * M = A + iB, in place (the refinement the precision line applies after a
  * low-precision inversion; not in the paper):
@@ -262,7 +280,10 @@ frob_status_t frob_batched_tune(frob_handle_t handle, int storage, int table_out
  * kernel class and accumulates, per class, the number of launches, their
  * summed duration in milliseconds and their algorithmic FP64 flop count.
  * Class 0: the n x n x n matrix-core GEMMs of the inversion paths (B Y and
- * -Y C^{-1}).  Enabling resets the counters.  Reading is valid after a call
+ * -Y C^{-1}).  Class 4: batched launches.  Class 5: adjoint products.
+ * Class 6: the trailing-update GEMMs of the look-ahead LU factorizations on
+ * the handle's second stream (real LU, orders >= 1024; flops 2 m w k per
+ * launch for an m x w update of rank k).  Enabling resets the counters.  Reading is valid after a call
  * returned (its final synchronization resolves the events). */
 frob_status_t frob_profile_enable(frob_handle_t handle, int on);
 frob_status_t frob_profile_read(frob_handle_t handle, int kernel_class, long long *launches, double *total_ms,

@@ -49,8 +49,9 @@ def _load():
     lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_cmatmul.restype = None
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     for name in ("orc_cinv_lu", "orc_cinv_gj", "orc_frob_lu", "orc_frob_shift", "orc_frob_chol",
-                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads"):
+                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads", "orc_set_num_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -68,6 +69,11 @@ def _out(*shape):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(t: int) -> int:
+    """Threads of later calls (timing only); returns the previous count."""
+    return _load().orc_set_num_threads(int(t))
 
 
 def cinv_lu(Mr, Mi):

@@ -66,6 +66,18 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of later calls (t >= 1); returns the previous count.  Timing only. */
+int orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  const int prev = omp_get_max_threads();
+  if (t >= 1) omp_set_num_threads(t);
+  return prev;
+#else
+  (void)t;
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Complex Gaussian elimination with partial pivoting: P M = L U, in place.   */
 /* Pivot: largest |z| in the column, lowest row index on ties.  Whole rows    */

@@ -83,6 +83,7 @@ void orc_cmatmul(int n, int k, int m, const double *Xr, const double *Xi, const 
 
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
 int orc_num_threads(void);
+int orc_set_num_threads(int t);
 
 #ifdef __cplusplus
 }

@@ -6,8 +6,9 @@ tensors provide device memory and the current stream; all arithmetic runs in
 the library's HIP kernels.  Importing this package does not load the library;
 the first call does, and raises if it is missing (there is no fallback path).
 
-Tensors: float64, on a ROCm device, row-major with unit column stride (a
-leading dimension ``stride(0) >= n`` is allowed).
+Tensors: float64 (or float32 for the FP32-storage twins of the single-matrix
+calls), on a ROCm device, row-major with unit column stride (a leading
+dimension ``stride(0) >= n`` is allowed).
 """
 from __future__ import annotations
 
@@ -83,10 +84,11 @@ class Handle:
         _lib.check(_lib.load().frob_set_stream(self.ptr, ctypes.c_void_p(s.cuda_stream)), "frob_set_stream")
 
 
-def _mat(t, n_rows, n_cols, name):
+def _mat(t, n_rows, n_cols, name, dtype=None):
     import torch
-    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda":
-        raise TypeError(f"{name}: expected a float64 tensor on a ROCm device")
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device.type != "cuda":
+        raise TypeError(f"{name}: expected a {dtype} tensor on a ROCm device")
     if t.dim() != 2 or t.shape[0] != n_rows or t.shape[1] != n_cols:
         raise ValueError(f"{name}: expected shape ({n_rows}, {n_cols}), got {tuple(t.shape)}")
     if t.stride(1) != 1 or t.stride(0) < n_cols:
@@ -110,7 +112,13 @@ def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32
 
 def _empty_like_sq(A, n):
     import torch
-    return torch.empty((n, n), dtype=torch.float64, device=A.device)
+    return torch.empty((n, n), dtype=A.dtype, device=A.device)
+
+
+def _fn32(name, A):
+    """The FP64 entry point, or its FP32-storage twin for float32 operands."""
+    import torch
+    return (name + "_f32", torch.float32) if A.dtype == torch.float32 else (name, torch.float64)
 
 
 def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0,
@@ -124,18 +132,19 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     f32_correction=True: after FP64 factorizations, form each step's
     correction X R with FP32 matrix-core operands (the residual stays FP64)."""
     n = A.shape[0]
+    name, dt = _fn32("frob_inv_general", A)
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
     Xi = _empty_like_sq(A, n) if Xi is None else Xi
-    pa, lda = _mat(A, n, n, "A")
-    pb, ldb = _mat(B, n, n, "B")
-    pr, ldx = _mat(Xr, n, n, "Xr")
-    pi, ldxi = _mat(Xi, n, n, "Xi")
+    pa, lda = _mat(A, n, n, "A", dt)
+    pb, ldb = _mat(B, n, n, "B", dt)
+    pr, ldx = _mat(Xr, n, n, "Xr", dt)
+    pi, ldxi = _mat(Xi, n, n, "Xi", dt)
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
     o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
-    st = _lib.load().frob_inv_general(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
-    _lib.check(st, "frob_inv_general", r)
+    st = getattr(_lib.load(), name)(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, name, r)
     return Xr, Xi, r.as_dict()
 
 
@@ -143,18 +152,19 @@ def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_
                  final_resid=True, f32_correction=False):
     """(A + iB)^{-1} for Hermitian positive definite A + iB (Algorithm 7)."""
     n = A.shape[0]
+    name, dt = _fn32("frob_inv_hpd", A)
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
     Xi = _empty_like_sq(A, n) if Xi is None else Xi
-    pa, lda = _mat(A, n, n, "A")
-    pb, ldb = _mat(B, n, n, "B")
-    pr, ldx = _mat(Xr, n, n, "Xr")
-    pi, ldxi = _mat(Xi, n, n, "Xi")
+    pa, lda = _mat(A, n, n, "A", dt)
+    pb, ldb = _mat(B, n, n, "B", dt)
+    pr, ldx = _mat(Xr, n, n, "Xr", dt)
+    pi, ldxi = _mat(Xi, n, n, "Xi", dt)
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
     o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
-    st = _lib.load().frob_inv_hpd(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
-    _lib.check(st, "frob_inv_hpd", r)
+    st = getattr(_lib.load(), name)(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, name, r)
     return Xr, Xi, r.as_dict()
 
 
@@ -179,25 +189,27 @@ def frob_refine(h: Handle, A, B, Xr, Xi, *, refine=4, prec=FROB_PREC_F64, refine
 
 
 def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0):
-    """Solve (A + iB)(x + iy) = c + id for n x p right-hand sides (Algorithm 3)."""
+    """Solve (A + iB)(x + iy) = c + id for n x p right-hand sides (Algorithm 3).
+    float32 operands use the FP32-storage twin (FP64 arithmetic)."""
     import torch
     n = A.shape[0]
     p = c.shape[1]
-    x = torch.empty((n, p), dtype=torch.float64, device=A.device) if x is None else x
-    y = torch.empty((n, p), dtype=torch.float64, device=A.device) if y is None else y
-    pa, lda = _mat(A, n, n, "A")
-    pb, ldb = _mat(B, n, n, "B")
-    pc, ldc = _mat(c, n, p, "c")
-    pd, ldd = _mat(d, n, p, "d")
-    px, ldx = _mat(x, n, p, "x")
-    py, ldy = _mat(y, n, p, "y")
+    name, dt = _fn32("frob_solve", A)
+    x = torch.empty((n, p), dtype=dt, device=A.device) if x is None else x
+    y = torch.empty((n, p), dtype=dt, device=A.device) if y is None else y
+    pa, lda = _mat(A, n, n, "A", dt)
+    pb, ldb = _mat(B, n, n, "B", dt)
+    pc, ldc = _mat(c, n, p, "c", dt)
+    pd, ldd = _mat(d, n, p, "d", dt)
+    px, ldx = _mat(x, n, p, "x", dt)
+    py, ldy = _mat(y, n, p, "y", dt)
     if ldc != ldd or ldx != ldy:
         raise ValueError("c/d and x/y must share leading dimensions")
     h.bind_stream()
     o, r = _opts(shift, mu, seed, 0), frob_result_t()
-    st = _lib.load().frob_solve(h.ptr, n, p, pa, lda, pb, ldb, pc, pd, ldc, px, py, ldx, ctypes.byref(o),
-                                ctypes.byref(r))
-    _lib.check(st, "frob_solve", r)
+    st = getattr(_lib.load(), name)(h.ptr, n, p, pa, lda, pb, ldb, pc, pd, ldc, px, py, ldx, ctypes.byref(o),
+                                    ctypes.byref(r))
+    _lib.check(st, name, r)
     return x, y, r.as_dict()
 
 

@@ -68,6 +68,9 @@ SIGNATURES = {
     "frob_inv_general": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_inv_hpd": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_inv_general_f32": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_inv_hpd_f32": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_solve_f32": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_refine": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),

@@ -118,6 +118,16 @@ __global__ void k_mirror_lower(int n, double* a, int lda, double sign) {
   if (j < n && j > i) a[(long long)i * lda + j] = sign * a[(long long)j * lda + i];
 }
 
+__global__ void k_cvt_f32_f64(int m, int n, const float* __restrict__ src, int lds, double* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n) dst[(long long)i * ldd + j] = (double)src[(long long)i * lds + j];
+}
+
+__global__ void k_cvt_f64_f32(int m, int n, const double* __restrict__ src, int lds, float* __restrict__ dst, int ldd) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j < n) dst[(long long)i * ldd + j] = (float)src[(long long)i * lds + j];
+}
+
 __global__ void k_zero_upper(int n, double* a, int lda) {
   const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
   if (j < n && j > i) a[(long long)i * lda + j] = 0.0;
@@ -198,6 +208,18 @@ void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, c
 void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_mirror_lower, grid2d(n, n), dim3(EB), 0, s, n, a, lda, sign);
+  FROB_LAUNCH_CHECK();
+}
+
+void convert_f32_f64(hipStream_t s, int m, int n, const float* src, int lds, double* dst, int ldd) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_cvt_f32_f64, grid2d(m, n), dim3(EB), 0, s, m, n, src, lds, dst, ldd);
+  FROB_LAUNCH_CHECK();
+}
+
+void convert_f64_f32(hipStream_t s, int m, int n, const double* src, int lds, float* dst, int ldd) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_cvt_f64_f32, grid2d(m, n), dim3(EB), 0, s, m, n, src, lds, dst, ldd);
   FROB_LAUNCH_CHECK();
 }
 

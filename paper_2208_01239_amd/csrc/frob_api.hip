@@ -80,6 +80,7 @@ const LookAhead* lookahead(frob_handle* h) {
     // default priority (the same as every other stream the library uses)
     FROB_HIP(hipStreamCreateWithFlags(&h->la.s1, hipStreamNonBlocking));
     for (auto& e : h->la.ev) FROB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->la.prof = h;
   }
   return &h->la;
 }
@@ -109,17 +110,18 @@ static hipEvent_t prof_event(frob_handle* h) {
   return e;
 }
 
-ProfScope::ProfScope(frob_handle* hh, int c, double fl) : h(hh), cls(c), flops(fl) {
+ProfScope::ProfScope(frob_handle* hh, int c, double fl, hipStream_t s) : h(hh), cls(c), flops(fl), st(s) {
   if (!h || !h->prof) return;
+  if (!st) st = h->stream;
   e0 = prof_event(h);
-  FROB_HIP(hipEventRecord(e0, h->stream));
+  FROB_HIP(hipEventRecord(e0, st));
 }
 
 ProfScope::~ProfScope() {
   if (!h || !h->prof || !e0) return;
   try {
     hipEvent_t e1 = prof_event(h);
-    if (hipEventRecord(e1, h->stream) != hipSuccess) return;
+    if (hipEventRecord(e1, st) != hipSuccess) return;
     h->pending.push_back({e0, e1, cls, flops});
   } catch (...) {
   }
@@ -203,6 +205,58 @@ GenWs gen_ws_carve(Carve& c, int n) {
   w.ldF = 2 * n;
   w.h = nullptr;
   return w;
+}
+
+// Workspace carved ahead of an entry point's own: the FP32-storage twins keep
+// their FP64 copies of the operands there while they call the FP64 entry
+// point (set only for the duration of that call, on the calling thread).
+thread_local size_t t_lead_bytes = 0;
+
+struct LeadScope {
+  size_t prev;
+  explicit LeadScope(size_t b) : prev(t_lead_bytes) { t_lead_bytes = b; }
+  ~LeadScope() { t_lead_bytes = prev; }
+};
+
+size_t lead_total(size_t bytes) { return t_lead_bytes + 256 + bytes; }
+
+// bytes of `doubles` FP64 values, rounded up to the carving alignment
+size_t lead_of(size_t doubles) { return ((doubles * sizeof(double)) + 255) & ~size_t(255); }
+
+Carve reserve_carve(frob_handle* h, size_t bytes) {
+  Carve c((char*)ws_reserve(h, lead_total(bytes)));
+  c.off = t_lead_bytes;
+  return c;
+}
+
+// Bytes of workspace of one call of each FP64 entry point.
+size_t general_ws(int n, int refine) {
+  const size_t nn = (size_t)n * n;
+  Carve sz(nullptr);
+  sz.take<char>(gen_ws_bytes(n));
+  sz.take<double>(nn); sz.take<double>(nn);   // shifted A, B
+  sz.take<char>(ns_ws_bytes(n, refine));
+  return sz.off;
+}
+
+size_t hpd_ws(int n, int refine) {
+  const size_t nn = (size_t)n * n;
+  Carve sz(nullptr);
+  for (int k = 0; k < 5; ++k) sz.take<double>(nn);
+  sz.take<double>(solver_work_elems(n));
+  sz.take<double>(trsm_work_elems(n));
+  sz.take<char>(ns_ws_bytes(n, refine));
+  return sz.off;
+}
+
+size_t solve_ws(int n, int nrhs) {
+  const size_t nn = (size_t)n * n;
+  const int q = 2 * nrhs;
+  Carve sz(nullptr);
+  sz.take<char>(gen_ws_bytes(n));
+  sz.take<double>(nn); sz.take<double>(nn);
+  sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q);
+  return sz.off;
 }
 
 // Steps 1-4 of Algorithm 5 (shared with Algorithm 3): LU of A, Y = A^{-1} B,
@@ -350,11 +404,7 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
-    Carve sz(nullptr);
-    sz.take<char>(gen_ws_bytes(n));
-    sz.take<double>(nn); sz.take<double>(nn);   // shifted A, B
-    sz.take<char>(ns_ws_bytes(n, o.refine));
-    Carve c((char*)ws_reserve(h, sz.off));
+    Carve c = reserve_carve(h, general_ws(n, o.refine));
     GenWs w = gen_ws_carve(c, n);
     w.h = h;
     double* As = c.take<double>(nn);
@@ -412,12 +462,7 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
   return guarded(h, [&]() -> frob_status_t {
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
-    Carve sz(nullptr);
-    for (int k = 0; k < 5; ++k) sz.take<double>(nn);
-    sz.take<double>(solver_work_elems(n));
-    sz.take<double>(trsm_work_elems(n));
-    sz.take<char>(ns_ws_bytes(n, o.refine));
-    Carve c((char*)ws_reserve(h, sz.off));
+    Carve c = reserve_carve(h, hpd_ws(n, o.refine));
     double* F = c.take<double>(nn);   // R1^T (lower)
     double* Wm = c.take<double>(nn);  // W = R2^{-T} (F stays readable for the concurrent solve)
     double* X1 = c.take<double>(nn);
@@ -493,11 +538,7 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const int q = 2 * nrhs;
-    Carve sz(nullptr);
-    sz.take<char>(gen_ws_bytes(n));
-    sz.take<double>(nn); sz.take<double>(nn);
-    sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q); sz.take<double>((size_t)n * q);
-    Carve c((char*)ws_reserve(h, sz.off));
+    Carve c = reserve_carve(h, solve_ws(n, nrhs));
     GenWs w = gen_ws_carve(c, n);
     w.h = h;
     double* As = c.take<double>(nn);
@@ -560,6 +601,100 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
     }
     if (!done) st = FROB_SINGULAR;
     if (res) *res = r;
+    return st;
+  });
+}
+
+// ------------------------------------------------ FP32-storage twins
+// The FP32 operands are widened into FP64 copies at the front of the
+// workspace, the FP64 entry point runs on them (its products in opts->prec),
+// and the FP64 results are rounded into the caller's FP32 outputs.
+frob_status_t frob_inv_general_f32(frob_handle_t h, int n, const float* A, int lda, const float* B, int ldb,
+                                   float* Xr, float* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    const size_t lead = 4 * lead_of(nn);
+    double* base = (double*)ws_reserve(h, lead + 256 + general_ws(n, o.refine));
+    double *A64 = base, *B64 = base + lead_of(nn) / 8, *Xr64 = base + 2 * lead_of(nn) / 8,
+           *Xi64 = base + 3 * lead_of(nn) / 8;
+    convert_f32_f64(s, n, n, A, lda, A64, n);
+    convert_f32_f64(s, n, n, B, ldb, B64, n);
+    frob_status_t st;
+    {
+      LeadScope ls(lead);
+      st = frob_inv_general(h, n, A64, n, B64, n, Xr64, Xi64, n, &o, res);
+    }
+    if (st == FROB_OK || st == FROB_NO_CONVERGENCE) {
+      convert_f64_f32(s, n, n, Xr64, n, Xr, ldx);
+      convert_f64_f32(s, n, n, Xi64, n, Xi, ldx);
+      FROB_HIP(hipStreamSynchronize(s));
+    }
+    return st;
+  });
+}
+
+frob_status_t frob_inv_hpd_f32(frob_handle_t h, int n, const float* A, int lda, const float* B, int ldb, float* Xr,
+                               float* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    const size_t lead = 4 * lead_of(nn);
+    double* base = (double*)ws_reserve(h, lead + 256 + hpd_ws(n, o.refine));
+    double *A64 = base, *B64 = base + lead_of(nn) / 8, *Xr64 = base + 2 * lead_of(nn) / 8,
+           *Xi64 = base + 3 * lead_of(nn) / 8;
+    convert_f32_f64(s, n, n, A, lda, A64, n);
+    convert_f32_f64(s, n, n, B, ldb, B64, n);
+    frob_status_t st;
+    {
+      LeadScope ls(lead);
+      st = frob_inv_hpd(h, n, A64, n, B64, n, Xr64, Xi64, n, &o, res);
+    }
+    if (st == FROB_OK || st == FROB_NO_CONVERGENCE) {
+      convert_f64_f32(s, n, n, Xr64, n, Xr, ldx);
+      convert_f64_f32(s, n, n, Xi64, n, Xi, ldx);
+      FROB_HIP(hipStreamSynchronize(s));
+    }
+    return st;
+  });
+}
+
+frob_status_t frob_solve_f32(frob_handle_t h, int n, int nrhs, const float* A, int lda, const float* B, int ldb,
+                             const float* cv, const float* dv, int ldc, float* x, float* y, int ldxy,
+                             const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || !A || !B || !cv || !dv || !x || !y || bad_dims(n, lda) || ldb < n || nrhs < 1 || ldc < nrhs ||
+      ldxy < nrhs)
+    return FROB_E_ARG;
+  const frob_opts_t o = opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n, np = (size_t)n * nrhs;
+    const size_t lead = 2 * lead_of(nn) + 4 * lead_of(np);
+    char* base = (char*)ws_reserve(h, lead + 256 + solve_ws(n, nrhs));
+    double* A64 = (double*)base;
+    double* B64 = (double*)(base + lead_of(nn));
+    double* c64 = (double*)(base + 2 * lead_of(nn));
+    double* d64 = (double*)(base + 2 * lead_of(nn) + lead_of(np));
+    double* x64 = (double*)(base + 2 * lead_of(nn) + 2 * lead_of(np));
+    double* y64 = (double*)(base + 2 * lead_of(nn) + 3 * lead_of(np));
+    convert_f32_f64(s, n, n, A, lda, A64, n);
+    convert_f32_f64(s, n, n, B, ldb, B64, n);
+    convert_f32_f64(s, n, nrhs, cv, ldc, c64, nrhs);
+    convert_f32_f64(s, n, nrhs, dv, ldc, d64, nrhs);
+    frob_status_t st;
+    {
+      LeadScope ls(lead);
+      st = frob_solve(h, n, nrhs, A64, n, B64, n, c64, d64, nrhs, x64, y64, nrhs, &o, res);
+    }
+    if (st == FROB_OK) {
+      convert_f64_f32(s, n, nrhs, x64, nrhs, x, ldxy);
+      convert_f64_f32(s, n, nrhs, y64, nrhs, y, ldxy);
+      FROB_HIP(hipStreamSynchronize(s));
+    }
     return st;
   });
 }

@@ -62,14 +62,16 @@ struct Carve {
 size_t solver_work_elems(int n);
 
 // kernel classes for frob_profile_read
-enum { PROF_GEMM_NNN = 0, PROF_FACTOR = 1, PROF_TRSM = 2, PROF_ALL_CALL = 3, PROF_BATCHED = 4, PROF_ADJOINT = 5 };
-// Record an event pair around the launches issued between begin and end.
+enum { PROF_GEMM_NNN = 0, PROF_BATCHED = 4, PROF_ADJOINT = 5, PROF_TRAIL_GEMM = 6 };
+// Record an event pair around the launches issued between begin and end, on
+// stream `s` (default: the handle's stream).
 struct ProfScope {
   frob_handle* h;
   int cls;
   double flops;
+  hipStream_t st;
   hipEvent_t e0 = nullptr;
-  ProfScope(frob_handle* hh, int c, double fl);
+  ProfScope(frob_handle* hh, int c, double fl, hipStream_t s = nullptr);
   ~ProfScope();
 };
 void prof_resolve(frob_handle* h);

@@ -4,6 +4,8 @@
 
 #include "common.hpp"
 
+struct frob_handle;
+
 namespace frob {
 
 // ----------------------------------------------------------------- GEMM (FP64)
@@ -111,6 +113,7 @@ void trtri_z64(hipStream_t s, int tri, int opT, int n, ZOp T, double* Wre, doubl
 struct LookAhead {
   hipStream_t s1 = nullptr;
   hipEvent_t ev[8] = {};
+  frob_handle* prof = nullptr;   // times the second stream's trailing-update GEMMs when profiling is on
 };
 // Panel widths (real, complex): the next panel's update is then one
 // recursion-node launch (real nodes up to 64 columns, complex up to 32).
@@ -169,5 +172,8 @@ void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, c
 void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign);
 // Zero the strict upper triangle
 void zero_upper_f64(hipStream_t s, int n, double* a, int lda);
+// Widen / round between FP32 and FP64 storage (m x n, leading dimensions)
+void convert_f32_f64(hipStream_t s, int m, int n, const float* src, int lds, double* dst, int ldd);
+void convert_f64_f32(hipStream_t s, int m, int n, const double* src, int lds, float* dst, int ldd);
 
 }  // namespace frob

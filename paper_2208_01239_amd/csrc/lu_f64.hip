@@ -18,6 +18,7 @@
 
 #include "common.hpp"
 #include "devutil.hpp"
+#include "handle.hpp"
 #include "internal.hpp"
 #include "tri_dev.hpp"
 
@@ -648,14 +649,16 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
   auto evF = [&](int j) { return la.ev[j & 3]; };
   auto evR = [&](int j) { return la.ev[4 + (j & 3)]; };
   // columns c .. c + w - 1 of the trailing matrix, updated with panel k0 .. k0 + nb
-  auto update = [&](hipStream_t st, int k0, int nb, int c, int w, const int* trows, double* wk) {
+  auto update = [&](hipStream_t st, int k0, int nb, int c, int w, const int* trows, double* wk, bool timed) {
     DOp L11{a + k0, lda, perm + k0};
     DOut A12{a + c, lda, perm + k0, nullptr};
     trsm_f64(st, false, TRI_LOWER_UNIT, false, nb, w, L11, A12, wk);
     DOp L21{a + k0, lda, trows};
     DOp U12{a + c, lda, perm + k0};
     DOut A22{a + c, lda, trows, nullptr};
-    gemm_f64(st, false, false, n - (k0 + nb), w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
+    const int m = n - (k0 + nb);
+    ProfScope ps(timed ? la.prof : nullptr, PROF_TRAIL_GEMM, 2.0 * m * (double)w * nb, st);
+    gemm_f64(st, false, false, m, w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
   };
   const int np = ceil_div(n, LA_NB);
   int last_r = -1;
@@ -669,7 +672,7 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
       // the last panel's rows of the extra columns: U12 = L11^{-1} A12 only
       if (q > 0) {
         if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
-        update(s0, k0, nb, n, q, perm + r0, work0);
+        update(s0, k0, nb, n, q, perm + r0, work0, false);
       }
       break;
     }
@@ -678,12 +681,12 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
     if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
     // the next panel's update is a recursion node (solve and update in one launch)
     if (nb <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, k0, n - k0, nb, w1, cnt);
-    else update(s0, k0, nb, c1, w1, perm + r0, work0);
+    else update(s0, k0, nb, c1, w1, perm + r0, work0, false);
     const int c2 = c1 + w1, w2 = nt - c2;
     if (w2 > 0) {
       FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
       GridCapScope cap(LA_GRID_CAP);   // leave compute units to the panel chain
-      update(s1, k0, nb, c2, w2, sn, work1);
+      update(s1, k0, nb, c2, w2, sn, work1, true);
       FROB_HIP(hipEventRecord(evR(j), s1));
       last_r = j;
     }
