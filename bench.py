@@ -413,7 +413,7 @@ def main():
         tc0 = time.perf_counter()
         oracle.frob_lu(Ac, Bc)
         tc = time.perf_counter() - tc0
-        m1 = max(1, m // 2)
+        m1 = max(1, (3 * m) // 8)
         A1, B1 = inputs.general(m1, 0)
         log(f"[bench] cpu baseline: oracle Algorithm 5 at n={m1}, 1 thread")
         prev = oracle.set_num_threads(1)
@@ -444,11 +444,13 @@ def main():
                       "complex_lu_printed_form_relF": extra.get("cinv_lu_form0_relF_vs_oracle_sampled_cols")}
 
     def roof(cls, kernel, traffic_file, sources):
-        launches, ms, flops = chosen["prof"][cls]
+        launches, ms, flops, nbytes = chosen["prof"][cls]
         if not launches:
             return None
         avg_ms = ms / launches
         achieved = flops / (ms * 1e-3) / 1e12
+        intensity = flops / nbytes if nbytes else None
+        ridge = FP64_MFMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
         # HBM traffic from the committed rocprofv3 counter summary, valid only
         # while the kernel's sources are the ones measured
         traffic = None
@@ -463,11 +465,17 @@ def main():
                     ok = ok and hashlib.sha256(f.read()).hexdigest() == td.get(key)
             if ok:
                 traffic = td["traffic_bytes_per_launch"]
-        return {"bound": "mfma", "kernel": kernel, "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
-                "avg_launch_ms": avg_ms, "launches_per_step": launches / K,
-                "alg_flops_per_launch": flops / launches,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"}
+        common = {"kernel": kernel, "traffic": traffic, "avg_launch_ms": avg_ms, "launches_per_step": launches / K,
+                  "alg_flops_per_launch": flops / launches, "alg_bytes_per_launch": nbytes / launches,
+                  "intensity_flop_per_byte": intensity, "fp64_ridge_flop_per_byte": ridge,
+                  "mfma_tflops": achieved, "mfma_frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                  "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"}
+        if intensity is not None and intensity < ridge:
+            gbs = nbytes / (ms * 1e-3) / 1e9     # below the ridge: the HBM roof bounds the kernel
+            return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    **common}
+        return {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS, **common}
 
     roof_trail = roof("trail", "k_gemm_f64 persistent (capped grid): trailing-update GEMMs of the look-ahead LUs of A "
                       "and C on the second stream, 2 m w k flops per launch",

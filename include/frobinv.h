@@ -278,7 +278,9 @@ frob_status_t frob_batched_tune(frob_handle_t handle, int storage, int table_out
 /* Kernel timing with HIP events (for measurement).  When enabled, the library
  * records an event pair on the handle's stream around every launch of a
  * kernel class and accumulates, per class, the number of launches, their
- * summed duration in milliseconds and their algorithmic FP64 flop count.
+ * summed duration in milliseconds, their algorithmic FP64 flop count and
+ * their algorithmic HBM bytes (operands read once, outputs written once;
+ * 0 where a class does not state them).
  * Class 0: the n x n x n matrix-core GEMMs of the inversion paths (B Y and
  * -Y C^{-1}).  Class 4: batched launches.  Class 5: adjoint products.
  * Class 6: the trailing-update GEMMs of the look-ahead LU factorizations on
@@ -287,7 +289,7 @@ frob_status_t frob_batched_tune(frob_handle_t handle, int storage, int table_out
  * returned (its final synchronization resolves the events). */
 frob_status_t frob_profile_enable(frob_handle_t handle, int on);
 frob_status_t frob_profile_read(frob_handle_t handle, int kernel_class, long long *launches, double *total_ms,
-                                double *flops);
+                                double *flops, double *bytes);
 
 /* Human-readable name of a status code (static string). */
 const char *frob_status_string(frob_status_t status);

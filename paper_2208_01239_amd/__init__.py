@@ -72,11 +72,11 @@ class Handle:
         _lib.check(_lib.load().frob_profile_enable(self.ptr, 1 if on else 0), "frob_profile_enable")
 
     def profile_read(self, kernel_class: int = 0):
-        """(launches, total_ms, flops) accumulated for a kernel class."""
-        n, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        """(launches, total_ms, flops, bytes) accumulated for a kernel class."""
+        n, ms, fl, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _lib.check(_lib.load().frob_profile_read(self.ptr, int(kernel_class), ctypes.byref(n), ctypes.byref(ms),
-                                                 ctypes.byref(fl)), "frob_profile_read")
-        return int(n.value), float(ms.value), float(fl.value)
+                                                 ctypes.byref(fl), ctypes.byref(by)), "frob_profile_read")
+        return int(n.value), float(ms.value), float(fl.value), float(by.value)
 
     def bind_stream(self, stream=None):
         import torch

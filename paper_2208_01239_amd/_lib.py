@@ -80,7 +80,7 @@ SIGNATURES = {
     "frob_batched_tune": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_int)]),
     "frob_profile_enable": (_i, [_vp, _i]),
     "frob_profile_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_d),
-                               ctypes.POINTER(_d)]),
+                               ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "frob_status_string": (ctypes.c_char_p, [_i]),
 }
 

@@ -110,7 +110,8 @@ static hipEvent_t prof_event(frob_handle* h) {
   return e;
 }
 
-ProfScope::ProfScope(frob_handle* hh, int c, double fl, hipStream_t s) : h(hh), cls(c), flops(fl), st(s) {
+ProfScope::ProfScope(frob_handle* hh, int c, double fl, hipStream_t s, double by)
+    : h(hh), cls(c), flops(fl), bytes(by), st(s) {
   if (!h || !h->prof) return;
   if (!st) st = h->stream;
   e0 = prof_event(h);
@@ -122,7 +123,7 @@ ProfScope::~ProfScope() {
   try {
     hipEvent_t e1 = prof_event(h);
     if (hipEventRecord(e1, st) != hipSuccess) return;
-    h->pending.push_back({e0, e1, cls, flops});
+    h->pending.push_back({e0, e1, cls, flops, bytes});
   } catch (...) {
   }
 }
@@ -133,6 +134,7 @@ void prof_resolve(frob_handle* h) {
     if (hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
       h->prof_ms[p.cls] += ms;
       h->prof_flops[p.cls] += p.flops;
+      h->prof_bytes[p.cls] += p.bytes;
       h->prof_count[p.cls] += 1;
     }
     h->pool.push_back(p.e0);
@@ -287,7 +289,7 @@ bool frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double*
   // step 3: C = A + B Y
   copy_f64(s, n, n, A, lda, nullptr, w.C, lf);
   {
-    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n, nullptr, 32.0 * n * (double)n);
     gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
              DOut{w.C, lf, nullptr, nullptr});
   }
@@ -314,7 +316,7 @@ void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* 
   }
   // step 5, second block row: Im X = -Y C^{-1}
   {
-    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+    ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n, nullptr, 24.0 * n * (double)n);
     gemm_f64(s, false, false, n, n, n, -1.0, DOp{w.Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
              DOut{Xi, ldx, nullptr, nullptr});
   }
@@ -507,7 +509,7 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     // step 9: Im X = -Y C^{-1}
     if (la) FROB_HIP(hipStreamWaitEvent(s, la->ev[4], 0));
     {
-      ProfScope ps(h, PROF_GEMM_NNN, 2.0 * n * (double)n * n);
+      ProfScope ps(h, PROF_GEMM_NNN, 2.0 * n * (double)n * n, nullptr, 24.0 * n * (double)n);
       gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
                DOut{Xi, ldx, nullptr, nullptr});
     }
@@ -719,17 +721,19 @@ frob_status_t frob_refine(frob_handle_t h, int n, const double* A, int lda, cons
 frob_status_t frob_profile_enable(frob_handle_t h, int on) {
   if (!h) return FROB_E_ARG;
   h->prof = on ? 1 : 0;
-  for (int k = 0; k < 16; ++k) { h->prof_ms[k] = 0; h->prof_flops[k] = 0; h->prof_count[k] = 0; }
+  for (int k = 0; k < 16; ++k) { h->prof_ms[k] = 0; h->prof_flops[k] = 0; h->prof_bytes[k] = 0; h->prof_count[k] = 0; }
   return FROB_OK;
 }
 
-frob_status_t frob_profile_read(frob_handle_t h, int cls, long long* launches, double* total_ms, double* flops) {
+frob_status_t frob_profile_read(frob_handle_t h, int cls, long long* launches, double* total_ms, double* flops,
+                                double* bytes) {
   if (!h || cls < 0 || cls >= 16) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     prof_resolve(h);
     if (launches) *launches = h->prof_count[cls];
     if (total_ms) *total_ms = h->prof_ms[cls];
     if (flops) *flops = h->prof_flops[cls];
+    if (bytes) *bytes = h->prof_bytes[cls];
     return FROB_OK;
   });
 }

@@ -13,7 +13,7 @@
 struct frob_prof_pending {
   hipEvent_t e0, e1;
   int cls;
-  double flops;
+  double flops, bytes;
 };
 
 struct frob_handle {
@@ -36,6 +36,7 @@ struct frob_handle {
   frob::LookAhead la;            // second stream and events of the look-ahead LU (created on first use)
   double prof_ms[16] = {0};
   double prof_flops[16] = {0};
+  double prof_bytes[16] = {0};
   long long prof_count[16] = {0};
 };
 
@@ -68,10 +69,10 @@ enum { PROF_GEMM_NNN = 0, PROF_BATCHED = 4, PROF_ADJOINT = 5, PROF_TRAIL_GEMM = 
 struct ProfScope {
   frob_handle* h;
   int cls;
-  double flops;
+  double flops, bytes;
   hipStream_t st;
   hipEvent_t e0 = nullptr;
-  ProfScope(frob_handle* hh, int c, double fl, hipStream_t s = nullptr);
+  ProfScope(frob_handle* hh, int c, double fl, hipStream_t s = nullptr, double by = 0.0);
   ~ProfScope();
 };
 void prof_resolve(frob_handle* h);

@@ -121,6 +121,9 @@ struct LookAhead {
 // Frobenius inversion, complex 32 / 64 -> 39.8 / 44.0 ms per complex LU
 // inversion; 128 to 512 were slower still.
 constexpr int LA_NB = 64;
+// Panels per super-panel of the real LU: columns right of a super-panel take
+// its panels as one rank-(LA_SUPER * LA_NB) update.
+constexpr int LA_SUPER = 1;
 constexpr int ZLA_NB = 32;
 constexpr int LA_MIN = 1024;
 // Workgroups of a trailing update on the second stream: fewer than the chip

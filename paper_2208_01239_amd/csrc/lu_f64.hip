@@ -624,73 +624,114 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
 }
 
-// Panels of LA_NB columns with a look-ahead of one panel (see internal.hpp).
+// Panels of LA_NB columns with a look-ahead of one panel (see internal.hpp),
+// grouped into super-panels of LA_SUPER panels.
 // Row interchanges only permute `perm` among the trailing positions, so a
 // trailing update may run while a later panel pivots, provided it addresses
 // its rows through a copy of perm taken when its panel was finished (the set
 // of trailing physical rows is the same; their order does not matter to a
 // row-wise update); the panel's last leaf writes that copy beside perm.
-// Ordering:
+// Inside a super-panel each panel updates only the super-panel's columns:
 //   s0: panel j (with the snapshot) -> event F_j -> [wait R_{j-1}] update of
-//       panel j+1's columns -> panel j+1 ...
-//   s1: [wait F_j] update of the columns right of panel j+1 -> event R_j
-// The update of panel j+1's columns waits for R_{j-1}, the previous update
-// of those columns; the snapshot buffer of panel j is rewritten at panel
-// j + 2, after s0 has waited for R_j.
+//       panel j+1's columns (one node launch) -> panel j+1 ...
+//   s1: [wait F_j] rank-LA_NB update of the super-panel's columns right of
+//       panel j+1 -> event R_j
+// Columns right of the super-panel receive its LA_SUPER panels at once, as
+// one rank-(LA_SUPER * LA_NB) update (a deeper, more efficient GEMM):
+//   s0: [wait G_{s-1}] the next super-panel's columns -> its first panel ...
+//   s1: [wait F_j] every column further right -> event G_s
+// The next super-panel's columns wait for G_{s-1}, the previous far update
+// of those columns.  Snapshots: panel j's (within a super-panel) is rewritten
+// at panel j + 2, after s0 has waited for R_j; a super-panel's (written by its
+// last panel, read by the far updates) at super-panel s + 2, after s0 has
+// waited for G_s.
 void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm, int* info, double* work, int* cnt,
                      const LookAhead& la) {
   const int nt = n + q;   // the q columns right of the matrix take every update and no pivot search
+  constexpr int SW = LA_NB * LA_SUPER;   // super-panel width
   hipStream_t s1 = la.s1;
   double* work0 = work;
   double* work1 = work0 + trsm_work_elems(n / 2 + 8);
   int* snap[2];
-  snap[0] = reinterpret_cast<int*>(work1 + trsm_work_elems(LA_NB));
+  int* snapF[2];
+  snap[0] = reinterpret_cast<int*>(work1 + trsm_work_elems(SW));
   snap[1] = snap[0] + n;
+  snapF[0] = snap[1] + n;
+  snapF[1] = snapF[0] + n;
   auto evF = [&](int j) { return la.ev[j & 3]; };
-  auto evR = [&](int j) { return la.ev[4 + (j & 3)]; };
-  // columns c .. c + w - 1 of the trailing matrix, updated with panel k0 .. k0 + nb
+  auto evR = [&](int j) { return la.ev[4 + (j & 1)]; };
+  auto evG = [&](int sp) { return la.ev[6 + (sp & 1)]; };
+  // columns c .. c + w - 1 of the trailing matrix, updated with the factored
+  // columns k0 .. k0 + nb (rows of the update through trows)
   auto update = [&](hipStream_t st, int k0, int nb, int c, int w, const int* trows, double* wk, bool timed) {
     DOp L11{a + k0, lda, perm + k0};
     DOut A12{a + c, lda, perm + k0, nullptr};
     trsm_f64(st, false, TRI_LOWER_UNIT, false, nb, w, L11, A12, wk);
+    const int m = n - (k0 + nb);
+    if (m <= 0) return;
     DOp L21{a + k0, lda, trows};
     DOp U12{a + c, lda, perm + k0};
     DOut A22{a + c, lda, trows, nullptr};
-    const int m = n - (k0 + nb);
-    ProfScope ps(timed ? la.prof : nullptr, PROF_TRAIL_GEMM, 2.0 * m * (double)w * nb, st);
+    // algorithmic bytes: L21 and U12 read once, A22 read and written
+    ProfScope ps(timed ? la.prof : nullptr, PROF_TRAIL_GEMM, 2.0 * m * (double)w * nb, st,
+                 8.0 * ((double)m * nb + (double)nb * w + 2.0 * m * w));
     gemm_f64(st, false, false, m, w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
   };
   const int np = ceil_div(n, LA_NB);
-  int last_r = -1;
+  int last_r = -1, last_g = -1;
   for (int j = 0; j < np; ++j) {
     const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
     const int r0 = k0 + nb;
-    int* sn = snap[j & 1];
+    const int sp = j / LA_SUPER;
+    const int K0 = sp * SW;                        // first column of this super-panel
+    const int spend = min(n, K0 + SW);             // end of this super-panel's columns
+    const bool last_in_sp = r0 >= spend;
+    int* sn = last_in_sp ? snapF[sp & 1] : snap[j & 1];
     // the panel's last leaf also writes the snapshot perm[r0 .. n)
     getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
+    if (!last_in_sp) {
+      FROB_HIP(hipEventRecord(evF(j), s0));
+      const int c1 = r0, w1 = min(LA_NB, spend - c1);
+      if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
+      // the next panel's update is a recursion node (solve and update in one launch)
+      if (nb <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, k0, n - k0, nb, w1, cnt);
+      else update(s0, k0, nb, c1, w1, perm + r0, work0, false);
+      const int c2 = c1 + w1, w2 = spend - c2;
+      if (w2 > 0) {
+        FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
+        GridCapScope cap(LA_GRID_CAP);   // leave compute units to the panel chain
+        update(s1, k0, nb, c2, w2, sn, work1, true);
+        FROB_HIP(hipEventRecord(evR(j), s1));
+        last_r = j;
+      }
+      continue;
+    }
+    // the super-panel is factored: its rank-(r0 - K0) update of the columns
+    // right of it (the extra columns included)
+    const int KB = r0 - K0;
     if (r0 >= n) {
-      // the last panel's rows of the extra columns: U12 = L11^{-1} A12 only
+      // no rows below: the extra columns' rows of this super-panel only (U12)
       if (q > 0) {
-        if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
-        update(s0, k0, nb, n, q, perm + r0, work0, false);
+        if (last_g >= 0) FROB_HIP(hipStreamWaitEvent(s0, evG(last_g), 0));
+        update(s0, K0, KB, n, q, perm + r0, work0, false);
       }
       break;
     }
     FROB_HIP(hipEventRecord(evF(j), s0));
-    const int c1 = r0, w1 = min(LA_NB, n - c1);
-    if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
-    // the next panel's update is a recursion node (solve and update in one launch)
-    if (nb <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, k0, n - k0, nb, w1, cnt);
-    else update(s0, k0, nb, c1, w1, perm + r0, work0, false);
+    if (last_g == sp - 1 && sp >= 1) FROB_HIP(hipStreamWaitEvent(s0, evG(sp - 1), 0));
+    const int c1 = r0, w1 = min(SW, n - c1);
+    if (KB <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, K0, n - K0, KB, w1, cnt);
+    else update(s0, K0, KB, c1, w1, sn, work0, false);
     const int c2 = c1 + w1, w2 = nt - c2;
     if (w2 > 0) {
       FROB_HIP(hipStreamWaitEvent(s1, evF(j), 0));
-      GridCapScope cap(LA_GRID_CAP);   // leave compute units to the panel chain
-      update(s1, k0, nb, c2, w2, sn, work1, true);
-      FROB_HIP(hipEventRecord(evR(j), s1));
-      last_r = j;
+      GridCapScope cap(LA_GRID_CAP);
+      update(s1, K0, KB, c2, w2, sn, work1, true);
+      FROB_HIP(hipEventRecord(evG(sp), s1));
+      last_g = sp;
     }
   }
+  if (last_g >= 0) FROB_HIP(hipStreamWaitEvent(s0, evG(last_g), 0));
   if (last_r >= 0) FROB_HIP(hipStreamWaitEvent(s0, evR(last_r), 0));
 }
 
@@ -698,9 +739,10 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
 
 size_t getrf_work_elems(int n) {
   // node counter, recursion and look-ahead scratch of s0, solve scratch of the
-  // second stream, two snapshots of n row indices; or the solve of extra
+  // second stream, four snapshots of n row indices; or the solve of extra
   // columns without the look-ahead
-  return 64 + std::max(trsm_work_elems(n / 2 + 8) + trsm_work_elems(LA_NB) + (size_t)n, trsm_work_elems(n));
+  return 64 + std::max(trsm_work_elems(n / 2 + 8) + trsm_work_elems(LA_NB * LA_SUPER) + 2 * (size_t)n,
+                       trsm_work_elems(n));
 }
 
 bool getrf_lookahead_on(int n, const LookAhead* la) { return la && la->s1 && n >= LA_MIN; }
