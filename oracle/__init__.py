@@ -48,10 +48,14 @@ def _load():
     lib.orc_adjoint.restype = None
     lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_cmatmul.restype = None
+    lib.orc_sign_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _ip]
+    lib.orc_polar_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _dp, _dp, _ip]
+    lib.orc_sylvester_newton.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, d, i, _dp, _dp, _ip]
     lib.orc_num_threads.argtypes = []
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     for name in ("orc_cinv_lu", "orc_cinv_gj", "orc_frob_lu", "orc_frob_shift", "orc_frob_chol",
-                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads", "orc_set_num_threads"):
+                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads", "orc_set_num_threads", "orc_sign_newton",
+                 "orc_polar_newton", "orc_sylvester_newton"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,3 +186,38 @@ def cmatmul(Xr, Xi, Yr, Yi):
     (Zr, pr), (Zi, pi) = _out(n, m), _out(n, m)
     lib.orc_cmatmul(n, k, m, a, b, c, d, pr, pi)
     return Zr, Zi
+
+
+def sign_newton(Xr, Xi, eps=1e-3, kmax=100):
+    """Matrix sign by the Newton iteration of Section 5.3.  Returns (Sr, Si, info, iters)."""
+    lib = _load()
+    n = Xr.shape[0]
+    (Xr, a), (Xi, b) = _c(Xr), _c(Xi)
+    (Sr, pr), (Si, pi) = _out(n, n), _out(n, n)
+    it = ctypes.c_int(0)
+    info = lib.orc_sign_newton(n, a, b, float(eps), int(kmax), pr, pi, ctypes.byref(it))
+    return Sr, Si, info, it.value
+
+
+def polar_newton(Xr, Xi, eps=1e-3, kmax=100):
+    """Polar decomposition X = Q P by the Newton iteration of Section 5.5.
+    Returns (Qr, Qi, Pr, Pi, info, iters)."""
+    lib = _load()
+    n = Xr.shape[0]
+    (Xr, a), (Xi, b) = _c(Xr), _c(Xi)
+    (Qr, qr), (Qi, qi), (Pr, pr), (Pi, pi) = _out(n, n), _out(n, n), _out(n, n), _out(n, n)
+    it = ctypes.c_int(0)
+    info = lib.orc_polar_newton(n, a, b, float(eps), int(kmax), qr, qi, pr, pi, ctypes.byref(it))
+    return Qr, Qi, Pr, Pi, info, it.value
+
+
+def sylvester_newton(Ar, Ai, Br, Bi, Cr, Ci, eps=1e-1, kmax=100):
+    """A Y + Y B = C through the sign of [[A, -C], [0, -B]] (Section 5.4).
+    Returns (Yr, Yi, info, iters)."""
+    lib = _load()
+    p, q = Ar.shape[0], Br.shape[0]
+    (Ar, a1), (Ai, a2), (Br, b1), (Bi, b2), (Cr, c1), (Ci, c2) = (_c(x) for x in (Ar, Ai, Br, Bi, Cr, Ci))
+    (Yr, yr), (Yi, yi) = _out(p, q), _out(p, q)
+    it = ctypes.c_int(0)
+    info = lib.orc_sylvester_newton(p, q, a1, a2, b1, b2, c1, c2, float(eps), int(kmax), yr, yi, ctypes.byref(it))
+    return Yr, Yi, info, it.value

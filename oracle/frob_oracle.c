@@ -605,3 +605,128 @@ void orc_cmatmul(int n, int k, int m, const double *Xr, const double *Xi, const 
       Zi[(size_t)i * m + j] = s.im;
     }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Section 5 (experiments): Newton iterations built on inversion.             */
+/* The max norm of eq. (maxnorm) is the largest |entry| over both parts.      */
+/* ------------------------------------------------------------------------- */
+static double planar_maxabs(size_t cnt, const double *re, const double *im) {
+  double m = 0.0;
+  for (size_t t = 0; t < cnt; ++t) {
+    const double a = fabs(re[t]), b = fabs(im[t]);
+    if (a > m) m = a;
+    if (b > m) m = b;
+  }
+  return m;
+}
+
+/* Section 5.3, eq. (iter): X_{k+1} = (X_k + X_k^{-1}) / 2 from X_0 = X, each
+ * inverse by Algorithm 4; stop when ||X_k - X_{k-1}||_max / ||X_k||_max <= eps
+ * or k >= kmax.  Returns 0, or the info of the inversion that failed. */
+int orc_sign_newton(int n, const double *Xr, const double *Xi, double eps, int kmax, double *Sr, double *Si,
+                    int *iters) {
+  const size_t nn = (size_t)n * n;
+  double *Ir = re_alloc(n, n), *Ii = re_alloc(n, n);
+  memcpy(Sr, Xr, nn * sizeof(double));
+  memcpy(Si, Xi, nn * sizeof(double));
+  int k = 0, info = 0;
+  while (k < kmax) {
+    info = orc_cinv_lu(n, Sr, Si, Ir, Ii, NULL, NULL);
+    if (info) break;
+    double dmax = 0.0;
+    for (size_t t = 0; t < nn; ++t) {
+      const double nr = 0.5 * (Sr[t] + Ir[t]), ni = 0.5 * (Si[t] + Ii[t]);
+      const double dr = fabs(nr - Sr[t]), di = fabs(ni - Si[t]);
+      if (dr > dmax) dmax = dr;
+      if (di > dmax) dmax = di;
+      Sr[t] = nr;
+      Si[t] = ni;
+    }
+    ++k;
+    if (dmax <= eps * planar_maxabs(nn, Sr, Si)) break;
+  }
+  if (iters) *iters = k;
+  free(Ir); free(Ii);
+  return info;
+}
+
+/* Section 5.5, eq. (iter2): X_{k+1} = (X_k + X_k^{-H}) / 2 from X_0 = X (the
+ * unitary polar factor Q in the limit), the same stopping rule, then
+ * P = Q^H X.  Returns 0, or the info of the inversion that failed. */
+int orc_polar_newton(int n, const double *Xr, const double *Xi, double eps, int kmax, double *Qr, double *Qi,
+                     double *Pr, double *Pi, int *iters) {
+  const size_t nn = (size_t)n * n;
+  double *Ir = re_alloc(n, n), *Ii = re_alloc(n, n), *Nr = re_alloc(n, n), *Ni = re_alloc(n, n);
+  memcpy(Qr, Xr, nn * sizeof(double));
+  memcpy(Qi, Xi, nn * sizeof(double));
+  int k = 0, info = 0;
+  while (k < kmax) {
+    info = orc_cinv_lu(n, Qr, Qi, Ir, Ii, NULL, NULL);
+    if (info) break;
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const size_t t = (size_t)i * n + j, tt = (size_t)j * n + i;   /* (X^{-H})_{ij} = conj((X^{-1})_{ji}) */
+        Nr[t] = 0.5 * (Qr[t] + Ir[tt]);
+        Ni[t] = 0.5 * (Qi[t] - Ii[tt]);
+        const double dr = fabs(Nr[t] - Qr[t]), di = fabs(Ni[t] - Qi[t]);
+        if (dr > dmax) dmax = dr;
+        if (di > dmax) dmax = di;
+      }
+    memcpy(Qr, Nr, nn * sizeof(double));
+    memcpy(Qi, Ni, nn * sizeof(double));
+    ++k;
+    if (dmax <= eps * planar_maxabs(nn, Qr, Qi)) break;
+  }
+  if (iters) *iters = k;
+  if (!info) {
+    /* P = Q^H X: P[i][j] = sum_t conj(Q[t][i]) X[t][j] */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        cx s = cx_make(0.0, 0.0);
+        for (int t = 0; t < n; ++t)
+          s = cx_add(s, cx_mul(cx_make(Qr[(size_t)t * n + i], -Qi[(size_t)t * n + i]),
+                               cx_make(Xr[(size_t)t * n + j], Xi[(size_t)t * n + j])));
+        Pr[(size_t)i * n + j] = s.re;
+        Pi[(size_t)i * n + j] = s.im;
+      }
+  }
+  free(Ir); free(Ii); free(Nr); free(Ni);
+  return info;
+}
+
+/* Section 5.4: the Sylvester equation A Y + Y B = C (A p x p, B q x q, C p x q)
+ * with sign(A) = I and sign(B) = I, through
+ *   sign([[A, -C], [0, -B]]) = [[I, -2Y], [0, -I]]:
+ * the Newton iteration of Section 5.3 on the (p + q) x (p + q) block matrix,
+ * then Y = -(1/2) times its upper right block.  Returns 0 or the failing info. */
+int orc_sylvester_newton(int p, int q, const double *Ar, const double *Ai, const double *Br, const double *Bi,
+                         const double *Cr, const double *Ci, double eps, int kmax, double *Yr, double *Yi,
+                         int *iters) {
+  const int N = p + q;
+  double *Xr = re_alloc(N, N), *Xi = re_alloc(N, N), *Sr = re_alloc(N, N), *Si = re_alloc(N, N);
+  for (int i = 0; i < p; ++i) {
+    for (int j = 0; j < p; ++j) {
+      Xr[(size_t)i * N + j] = Ar[(size_t)i * p + j];
+      Xi[(size_t)i * N + j] = Ai[(size_t)i * p + j];
+    }
+    for (int j = 0; j < q; ++j) {
+      Xr[(size_t)i * N + p + j] = -Cr[(size_t)i * q + j];
+      Xi[(size_t)i * N + p + j] = -Ci[(size_t)i * q + j];
+    }
+  }
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) {
+      Xr[(size_t)(p + i) * N + p + j] = -Br[(size_t)i * q + j];
+      Xi[(size_t)(p + i) * N + p + j] = -Bi[(size_t)i * q + j];
+    }
+  const int info = orc_sign_newton(N, Xr, Xi, eps, kmax, Sr, Si, iters);
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < q; ++j) {
+      Yr[(size_t)i * q + j] = -0.5 * Sr[(size_t)i * N + p + j];
+      Yi[(size_t)i * q + j] = -0.5 * Si[(size_t)i * N + p + j];
+    }
+  free(Xr); free(Xi); free(Sr); free(Si);
+  return info;
+}

@@ -82,6 +82,23 @@ void orc_cmatmul(int n, int k, int m, const double *Xr, const double *Xi, const 
                  const double *Yi, double *Zr, double *Zi);
 
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
+/* Section 5.3, eq. (iter): the matrix sign function by the Newton iteration
+ * X_{k+1} = (X_k + X_k^{-1}) / 2, X_0 = X, each inverse by Algorithm 4; stop
+ * when ||X_k - X_{k-1}||_max / ||X_k||_max <= eps (eq. (maxnorm)) or at kmax
+ * steps.  *iters receives the number of steps.  Returns 0 or the failing
+ * inversion's info. */
+int orc_sign_newton(int n, const double *Xr, const double *Xi, double eps, int kmax, double *Sr, double *Si,
+                    int *iters);
+/* Section 5.5, eq. (iter2): the unitary polar factor Q by X_{k+1} =
+ * (X_k + X_k^{-H}) / 2 with the same stopping rule, and P = Q^H X. */
+int orc_polar_newton(int n, const double *Xr, const double *Xi, double eps, int kmax, double *Qr, double *Qi,
+                     double *Pr, double *Pi, int *iters);
+/* Section 5.4: A Y + Y B = C (A p x p, B q x q, C p x q, sign(A) = I, sign(B) =
+ * I) by the Newton iteration on [[A, -C], [0, -B]], whose sign is
+ * [[I, -2Y], [0, -I]]. */
+int orc_sylvester_newton(int p, int q, const double *Ar, const double *Ai, const double *Br, const double *Bi,
+                         const double *Cr, const double *Ci, double eps, int kmax, double *Yr, double *Yi,
+                         int *iters);
 int orc_num_threads(void);
 int orc_set_num_threads(int t);
 

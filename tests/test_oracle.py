@@ -493,3 +493,81 @@ def test_paper_accuracy_generator():
     ref = np.linalg.inv(cplx(A, B))
     for name, (Xr, Xi) in routes.items():
         assert relF(Xr, Xi, ref.real, ref.imag) < 1e-12, name
+
+
+# ----------------------------------------------------------------------------- Section 5: Newton iterations
+def _diagonalizable(n, rng, lo=1.0, hi=3.0, mixed=True):
+    """X = Z J Z^{-1} with Z entries uniform in [-1, 1] (both parts) and J
+    diagonal: half the eigenvalues with positive, half with negative real part
+    (mixed=True), all positive otherwise (Section 5.3 / 5.4 generators)."""
+    Z = rng.uniform(-1, 1, (n, n)) + 1j * rng.uniform(-1, 1, (n, n))
+    re = rng.uniform(lo, hi, n)
+    if mixed:
+        re[n // 2:] *= -1
+    J = re + 1j * rng.uniform(-2, 2, n)
+    Zi = np.linalg.inv(Z)
+    return Z @ np.diag(J) @ Zi, Z @ np.diag(np.sign(J.real)) @ Zi
+
+
+@pytest.mark.parametrize("n", [1, 2, 8, 30])
+def test_sign_newton_closed_form(n):
+    """Section 5.3: the Newton iteration reproduces sign(X) = Z diag(+-1) Z^{-1}
+    of a diagonalizable X (the eq. (sign) definition), and sign(X)^2 = I,
+    sign(X) X = X sign(X)."""
+    rng = np.random.default_rng(40 + n)
+    X, S = _diagonalizable(n, rng)
+    Sr, Si, info, it = oracle.sign_newton(X.real.copy(), X.imag.copy(), eps=1e-13, kmax=100)
+    assert info == 0 and 1 <= it < 100
+    Sh = Sr + 1j * Si
+    assert np.abs(Sh - S).max() <= 1e-10 * np.abs(S).max()
+    assert np.abs(Sh @ Sh - np.eye(n)).max() <= 1e-10
+    assert np.abs(Sh @ X - X @ Sh).max() <= 1e-10 * np.abs(X).max()
+
+
+def test_sign_newton_scalar_and_stopping_rule():
+    """n = 1: sign(a + ib) = sign(a); the iteration stops at the first step
+    whose relative change in the max norm is <= eps."""
+    for a, b in ((2.5, -1.0), (-0.3, 4.0)):
+        Sr, Si, info, it = oracle.sign_newton(np.array([[a]]), np.array([[b]]), eps=1e-14)
+        assert info == 0 and abs(Sr[0, 0] - np.sign(a)) <= 1e-14 and abs(Si[0, 0]) <= 1e-14
+    rng = np.random.default_rng(7)
+    X, S = _diagonalizable(20, rng)
+    _, _, _, it_loose = oracle.sign_newton(X.real.copy(), X.imag.copy(), eps=1e-3)
+    _, _, _, it_tight = oracle.sign_newton(X.real.copy(), X.imag.copy(), eps=1e-13)
+    assert 1 <= it_loose < it_tight
+    Sr, Si, _, _ = oracle.sign_newton(X.real.copy(), X.imag.copy(), eps=1e-13, kmax=2)
+    assert np.abs(Sr + 1j * Si - S).max() > 1e-3          # two steps are not enough: kmax is honoured
+
+
+@pytest.mark.parametrize("n", [1, 5, 24])
+def test_polar_newton_matches_svd(n):
+    """Section 5.5: Q from the iteration X_{k+1} = (X_k + X_k^{-H}) / 2 is the
+    unitary polar factor U V^H of the SVD X = U S V^H, and P = Q^H X = V S V^H
+    is Hermitian positive definite."""
+    rng = np.random.default_rng(60 + n)
+    X = rng.uniform(-1, 1, (n, n)) + 1j * rng.uniform(-1, 1, (n, n))
+    U, s, Vh = np.linalg.svd(X)
+    Qref, Pref = U @ Vh, Vh.conj().T @ np.diag(s) @ Vh
+    Qr, Qi, Pr, Pi, info, it = oracle.polar_newton(X.real.copy(), X.imag.copy(), eps=1e-13)
+    assert info == 0 and it >= 1
+    Q, P = Qr + 1j * Qi, Pr + 1j * Pi
+    assert np.abs(Q - Qref).max() <= 1e-10
+    assert np.abs(P - Pref).max() <= 1e-10 * np.abs(Pref).max()
+    assert np.abs(Q.conj().T @ Q - np.eye(n)).max() <= 1e-12
+    assert np.abs(Q @ P - X).max() <= 1e-12 * np.abs(X).max()
+
+
+@pytest.mark.parametrize("p,q,lyap", [(6, 4, False), (20, 13, False), (12, 12, True)])
+def test_sylvester_newton_recovers_constructed_solution(p, q, lyap):
+    """Section 5.4: with A = Z J Z^{-1}, Re J in [9, 10] (so sign(A) = I), B
+    likewise (B = A^H for the Lyapunov case), Y uniform and C = A Y + Y B, the
+    iteration on [[A, -C], [0, -B]] returns Y."""
+    rng = np.random.default_rng(80 + p + q)
+    A, _ = _diagonalizable(p, rng, 9.0, 10.0, mixed=False)
+    B = A.conj().T if lyap else _diagonalizable(q, rng, 9.0, 10.0, mixed=False)[0]
+    Y = rng.uniform(-1, 1, (p, q)) + 1j * rng.uniform(-1, 1, (p, q))
+    C = A @ Y + Y @ B
+    Yr, Yi, info, it = oracle.sylvester_newton(A.real.copy(), A.imag.copy(), B.real.copy(), B.imag.copy(),
+                                               C.real.copy(), C.imag.copy(), eps=1e-13)
+    assert info == 0 and it >= 1
+    assert np.abs(Yr + 1j * Yi - Y).max() <= 1e-9 * np.abs(Y).max()
