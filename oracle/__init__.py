@@ -48,13 +48,14 @@ def _load():
     lib.orc_adjoint.restype = None
     lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_cmatmul.restype = None
+    lib.orc_frob_chol_spd_pair.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
     lib.orc_sign_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _ip]
     lib.orc_polar_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _dp, _dp, _ip]
     lib.orc_sylvester_newton.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, d, i, _dp, _dp, _ip]
     lib.orc_num_threads.argtypes = []
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     for name in ("orc_cinv_lu", "orc_cinv_gj", "orc_frob_lu", "orc_frob_shift", "orc_frob_chol",
-                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads", "orc_set_num_threads", "orc_sign_newton",
+                 "orc_cinv_chol", "orc_frob_solve", "orc_num_threads", "orc_set_num_threads", "orc_sign_newton", "orc_frob_chol_spd_pair",
                  "orc_polar_newton", "orc_sylvester_newton"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -132,6 +133,18 @@ def frob_chol(A, B):
     (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
     fl = ctypes.c_double(0)
     info = lib.orc_frob_chol(n, pa, pb, xr, xi, ctypes.byref(fl))
+    return Xr, Xi, info, fl.value
+
+
+def frob_chol_spd_pair(A, B):
+    """Algorithm 7 with step 5 X4 = A + X3 (A, B symmetric positive definite).
+    Returns (Xr, Xi, info, flops)."""
+    lib = _load()
+    n = A.shape[0]
+    (A, pa), (B, pb) = _c(A), _c(B)
+    (Xr, xr), (Xi, xi) = _out(n, n), _out(n, n)
+    fl = ctypes.c_double(0)
+    info = lib.orc_frob_chol_spd_pair(n, pa, pb, xr, xi, ctypes.byref(fl))
     return Xr, Xi, info, fl.value
 
 

@@ -427,7 +427,11 @@ static void re_trsm_upper(int n, int p, const double *R, const double *Rhs, doub
 /* Steps 2 and 7 are printed as "backward" substitutions; R^T is lower        */
 /* triangular, so they are forward substitutions here.                        */
 /* ------------------------------------------------------------------------- */
-int orc_frob_chol(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops) {
+/* step5_sign = -1: Algorithm 7 as printed (B skew: B A^{-1} B = -X1^T X1);
+ * step5_sign = +1: the class closing Section 4.3, A and B symmetric positive
+ * definite (B symmetric: B A^{-1} B = +X1^T X1), so step 5 reads X4 = A + X3. */
+static int frob_chol_steps(int n, const double *A, const double *B, double step5_sign, double *Xr, double *Xi,
+                           double *flops) {
   double fl = 0.0;
   int info = 0;
   size_t nn = (size_t)n * n;
@@ -447,7 +451,7 @@ int orc_frob_chol(int n, const double *A, const double *B, double *Xr, double *X
       X3[(size_t)j * n + i] = s;
     }
   fl += 2.0 * (double)n * ((double)n * (n + 1) / 2.0);
-  for (size_t t = 0; t < nn; ++t) X4[t] = A[t] - X3[t];       /* step 5 */
+  for (size_t t = 0; t < nn; ++t) X4[t] = A[t] + step5_sign * X3[t];   /* step 5 */
   fl += (double)nn;
   k = re_potrf_upper(n, X4, R2, &fl);                         /* step 6 */
   if (k) { info = ORC_STAGE_C + k; goto done; }
@@ -459,6 +463,14 @@ done:
   if (flops) *flops = fl;
   free(R1); free(X1); free(X2); free(X3); free(X4); free(R2); free(X5); free(X6); free(X7);
   return info;
+}
+
+int orc_frob_chol(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops) {
+  return frob_chol_steps(n, A, B, -1.0, Xr, Xi, flops);
+}
+
+int orc_frob_chol_spd_pair(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops) {
+  return frob_chol_steps(n, A, B, 1.0, Xr, Xi, flops);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -99,6 +99,11 @@ int orc_polar_newton(int n, const double *Xr, const double *Xi, double eps, int 
 int orc_sylvester_newton(int p, int q, const double *Ar, const double *Ai, const double *Br, const double *Bi,
                          const double *Cr, const double *Ci, double eps, int kmax, double *Yr, double *Yi,
                          int *iters);
+/* Algorithm 7 for the class closing Section 4.3: A and B symmetric positive
+ * definite (M = A + iB complex symmetric, not Hermitian).  With B symmetric,
+ * B A^{-1} B = X1^T X1, so step 5 reads X4 = A + X3; every other step as
+ * printed.  Same return codes as orc_frob_chol. */
+int orc_frob_chol_spd_pair(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops);
 int orc_num_threads(void);
 int orc_set_num_threads(int t);
 

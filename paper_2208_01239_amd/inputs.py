@@ -22,6 +22,18 @@ of the paper (Section 5) and the synthetic configurations used for measurement:
                       with torch on a device (its own random stream), with
                       the inverse V diag(1/sigma) U^H from the same factors.
 * ``batch``        -- uneven batch: n ~ U{16..512}, kinds alternate general/HPD.
+* ``spd_pair``     -- A = G1 G1^T / n + I and B = G2 G2^T / n + I with G1, G2
+                      iid N(0, 1): both symmetric positive definite (the class
+                      closing Section 4.3).
+* ``sign_problem`` -- X = Z J Z^{-1} with Z uniform in [-1, 1] (both parts)
+                      and J diagonal, half the eigenvalues with positive and
+                      half with negative real part, away from zero (Section
+                      5.3), with sign(X) = Z diag(+-1) Z^{-1} beside it.
+* ``sylvester_problem`` -- A = Z J Z^{-1} with Re J in [9, 10] (sign(A) = I),
+                      B likewise or B = A^H (Lyapunov), Y uniform in [-1, 1],
+                      C = A Y + Y B (Section 5.4).
+* ``polar_problem`` -- X = U P with U the unitary factor of a QR of a uniform
+                      complex matrix and P = Z^H Z (Section 5.5).
 """
 from __future__ import annotations
 
@@ -178,3 +190,55 @@ def adjoint_batch(count: int = 256, n: int = 256, seed: int = 5):
         rng = np.random.default_rng(int(children[count + b].generate_state(1)[0]))
         ws.append((rng.standard_normal((n, n)), rng.standard_normal((n, n))))
     return mats, ws
+
+
+def _uniform_complex(rng, shape):
+    return rng.uniform(-1.0, 1.0, size=shape) + 1j * rng.uniform(-1.0, 1.0, size=shape)
+
+
+def sign_problem(n: int, seed: int = 50):
+    """(Xr, Xi, Sr, Si): X = Z J Z^{-1} and its sign Z diag(sign Re J) Z^{-1}."""
+    rng = np.random.default_rng(seed)
+    Z = _uniform_complex(rng, (n, n))
+    re = rng.uniform(0.5, 2.0, n)
+    re[n // 2:] *= -1.0
+    J = re + 1j * rng.uniform(-1.0, 1.0, n)
+    Zi = np.linalg.inv(Z)
+    X = (Z * J) @ Zi
+    S = (Z * np.sign(J.real)) @ Zi
+    return (np.ascontiguousarray(X.real), np.ascontiguousarray(X.imag), np.ascontiguousarray(S.real),
+            np.ascontiguousarray(S.imag))
+
+
+def sylvester_problem(p: int, q: int, seed: int = 51, lyapunov: bool = False):
+    """(A, B, C, Y) as complex numpy arrays with A Y + Y B = C, sign(A) = sign(B) = I."""
+    rng = np.random.default_rng(seed)
+
+    def stable(m):
+        Z = _uniform_complex(rng, (m, m))
+        J = rng.uniform(9.0, 10.0, m) + 1j * rng.uniform(-1.0, 1.0, m)
+        return (Z * J) @ np.linalg.inv(Z)
+    A = stable(p)
+    B = A.conj().T.copy() if lyapunov else stable(q)
+    Y = _uniform_complex(rng, (p, q if not lyapunov else p))
+    C = A @ Y + Y @ B
+    return A, B, C, Y
+
+
+def polar_problem(n: int, seed: int = 52):
+    """(X, Q, P) as complex numpy arrays with X = Q P, Q unitary, P = Z^H Z."""
+    rng = np.random.default_rng(seed)
+    U, R = np.linalg.qr(_uniform_complex(rng, (n, n)))
+    Z = _uniform_complex(rng, (n, n))
+    P = Z.conj().T @ Z
+    return U @ P, U, P
+
+
+def spd_pair(n: int, seed: int = 53):
+    """A, B symmetric positive definite (M = A + iB complex symmetric)."""
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((n, n))
+    G2 = rng.standard_normal((n, n))
+    A = G1 @ G1.T / n + np.eye(n)
+    B = G2 @ G2.T / n + np.eye(n)
+    return np.ascontiguousarray(0.5 * (A + A.T)), np.ascontiguousarray(0.5 * (B + B.T))

@@ -571,3 +571,31 @@ def test_sylvester_newton_recovers_constructed_solution(p, q, lyap):
                                                C.real.copy(), C.imag.copy(), eps=1e-13)
     assert info == 0 and it >= 1
     assert np.abs(Yr + 1j * Yi - Y).max() <= 1e-9 * np.abs(Y).max()
+
+
+# ----------------------------------------------------------------------------- A > 0, B > 0 (end of Section 4.3)
+@pytest.mark.parametrize("n", [1, 2, 7, 40])
+def test_spd_pair_variant_matches_complex_inverse(n):
+    """A and B symmetric positive definite: Algorithm 7 with step 5 read as
+    X4 = A + X3 equals the inverse by complex Gaussian elimination and by
+    LAPACK, and the inverse of the complex symmetric M is complex symmetric.
+    The printed step 5 (A - X3) does not give the inverse."""
+    A, B = inputs.spd_pair(n, seed=90 + n)
+    Xr, Xi, info, _ = oracle.frob_chol_spd_pair(A, B)
+    assert info == 0
+    Rr, Ri, _, _, _ = oracle.cinv_lu(A, B)
+    assert relF(Xr, Xi, Rr, Ri) <= 1e-12
+    ref = np.linalg.inv(A + 1j * B)
+    assert relF(Xr, Xi, ref.real, ref.imag) <= 1e-12
+    assert np.abs(Xr - Xr.T).max() <= 1e-12 * np.abs(Xr).max() and np.abs(Xi - Xi.T).max() <= 1e-12 * np.abs(Xi).max()
+    if n > 1:
+        Pr, Pi, pinfo, _ = oracle.frob_chol(A, B)
+        assert pinfo != 0 or relF(Pr, Pi, Rr, Ri) > 1e-3
+
+
+def test_spd_pair_scalar_closed_form():
+    """n = 1: (a + ib)^{-1} = (a - ib) / (a^2 + b^2), and C = a + b^2 / a."""
+    a, b = 2.0, 3.0
+    Xr, Xi, info, _ = oracle.frob_chol_spd_pair(np.array([[a]]), np.array([[b]]))
+    assert info == 0
+    assert abs(Xr[0, 0] - a / (a * a + b * b)) <= 1e-16 and abs(Xi[0, 0] + b / (a * a + b * b)) <= 1e-16
