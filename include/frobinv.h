@@ -148,6 +148,15 @@ frob_status_t frob_inv_general(frob_handle_t handle, int n, const double *A, int
 frob_status_t frob_inv_hpd(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
                            double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
 
+/* A and B both symmetric positive definite (M = A + iB complex symmetric;
+ * the class named at the end of Section 4.3): Algorithm 7 with step 5 read
+ * as C = A + X1^T X1, since B A^{-1} B = (R1^{-T} B)^T (R1^{-T} B) for
+ * symmetric B; every other step as in frob_inv_hpd (lower triangle of A read,
+ * full B).  The inverse is complex symmetric.  Returns FROB_NOT_HPD (stage 1)
+ * if A is not positive definite, (stage 2) if C is not. */
+frob_status_t frob_inv_spd_pair(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
+                                double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
 /* Linear system (A + iB)(x + iy) = c + id for nrhs right-hand sides
  * (Algorithm 3 with the sign of step 7 taken as y = y1 - y2, which is what
  * eq. (Finv) gives).  No inverse is formed: LU of A, Y = A^{-1} B,
@@ -197,6 +206,59 @@ frob_status_t frob_solve_f32(frob_handle_t handle, int n, int nrhs, const float 
  *   res    : resid0, resid, norm2_est, refine_steps (may be NULL) */
 frob_status_t frob_refine(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
                           double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
+/* Newton iterations whose every step is one Frobenius inversion (the
+ * applications of Section 5 of the paper).  Stopping rule of Section 5.3:
+ * stop when ||X_k - X_{k-1}||_max / ||X_k||_max <= tol, with the max norm of
+ * eq. (maxnorm) (the largest |entry| over both parts), or after max_iter
+ * steps. */
+typedef struct {
+  double tol;           /* <= 0: 1e-3 (the paper's choice for sign and polar)                                */
+  int max_iter;         /* <= 0: 100                                                                      */
+  frob_opts_t inv;      /* options of every inversion (shift, precision, refinement); zeroed = defaults     */
+} frob_newton_opts_t;
+
+typedef struct {
+  int iterations;       /* Newton steps taken                                                              */
+  double last_change;   /* ||X_k - X_{k-1}||_max / ||X_k||_max of the last step                            */
+  frob_result_t inv;    /* result of the last inversion                                                    */
+} frob_newton_result_t;
+
+/* Fill *opts with the defaults (tol 1e-3, 100 steps, frob_default_opts). */
+void frob_default_newton_opts(frob_newton_opts_t *opts);
+
+/* Matrix sign function (Section 5.3, eq. (sign)) by the Newton iteration
+ * X_{k+1} = (X_k + X_k^{-1}) / 2, X_0 = X (eq. (iter)), every inverse by
+ * frob_inv_general.  X must have no eigenvalue on the imaginary axis.
+ *   Xr, Xi : n x n input (leading dimension ldx); Sr, Si : n x n output (lds)
+ * Workspace: 4 n^2 doubles ahead of the inversion's own.  A step whose
+ * inversion fails returns that status (FROB_SINGULAR: X_k singular). */
+frob_status_t frob_sign(frob_handle_t handle, int n, const double *Xr, const double *Xi, int ldx, double *Sr,
+                        double *Si, int lds, const frob_newton_opts_t *opts, frob_newton_result_t *res);
+
+/* Polar decomposition X = Q P (Section 5.5): the unitary factor by
+ * X_{k+1} = (X_k + X_k^{-H}) / 2, X_0 = X (eq. (iter2)), then P = Q^H X
+ * (a complex matrix-core product).  X must be invertible.
+ *   Qr, Qi : unitary factor (ldq);  Pr, Pi : Hermitian factor (ldp) */
+frob_status_t frob_polar(frob_handle_t handle, int n, const double *Xr, const double *Xi, int ldx, double *Qr,
+                         double *Qi, int ldq, double *Pr, double *Pi, int ldp, const frob_newton_opts_t *opts,
+                         frob_newton_result_t *res);
+
+/* Sylvester equation A Y + Y B = C (Section 5.4) for A (p x p) and B (q x q)
+ * with sign(A) = I and sign(B) = I: the Newton iteration on
+ * [[A, -C], [0, -B]] (order p + q), whose sign is [[I, -2Y], [0, -I]];
+ * Y = -(1/2) times its upper right block.
+ *   A : p x p (lda), B : q x q (ldb), C : p x q (ldc), Y : p x q output (ldy) */
+frob_status_t frob_sylvester(frob_handle_t handle, int p, int q, const double *Ar, const double *Ai, int lda,
+                             const double *Br, const double *Bi, int ldb, const double *Cr, const double *Ci, int ldc,
+                             double *Yr, double *Yi, int ldy, const frob_newton_opts_t *opts,
+                             frob_newton_result_t *res);
+
+/* Lyapunov equation A Y + Y A^H = C (Section 5.4, B = A^H), sign(A) = I:
+ * frob_sylvester with B = A^H formed in the block matrix.  A, C, Y : p x p. */
+frob_status_t frob_lyapunov(frob_handle_t handle, int p, const double *Ar, const double *Ai, int lda,
+                            const double *Cr, const double *Ci, int ldc, double *Yr, double *Yi, int ldy,
+                            const frob_newton_opts_t *opts, frob_newton_result_t *res);
 
 /* Baseline: inversion with LU decomposition in complex arithmetic
  * (Algorithm 4), planar storage, four real matrix-core products per complex

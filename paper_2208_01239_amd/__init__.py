@@ -24,7 +24,8 @@ __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_ref
            "frob_inv_adjoint", "frob_inv_batched", "frob_batched_tune", "BatchedPlan",
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
            "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
-           "FROB_REFINE_SKIP_FINAL_RESID", "FROB_REFINE_F32_CORRECTION", "load_library"]
+           "FROB_REFINE_SKIP_FINAL_RESID", "FROB_REFINE_F32_CORRECTION", "load_library", "frob_sign", "frob_polar",
+           "frob_sylvester", "frob_lyapunov", "frob_inv_spd_pair"]
 
 
 def load_library():
@@ -91,9 +92,12 @@ def _mat(t, n_rows, n_cols, name, dtype=None):
         raise TypeError(f"{name}: expected a {dtype} tensor on a ROCm device")
     if t.dim() != 2 or t.shape[0] != n_rows or t.shape[1] != n_cols:
         raise ValueError(f"{name}: expected shape ({n_rows}, {n_cols}), got {tuple(t.shape)}")
-    if t.stride(1) != 1 or t.stride(0) < n_cols:
+    # strides of extent-1 dimensions do not address anything
+    cs = 1 if n_cols == 1 else t.stride(1)
+    ld = n_cols if n_rows == 1 else t.stride(0)
+    if cs != 1 or ld < n_cols:
         raise ValueError(f"{name}: rows must be contiguous with leading dimension >= {n_cols}")
-    return ctypes.c_void_p(t.data_ptr()), int(t.stride(0))
+    return ctypes.c_void_p(t.data_ptr()), int(ld)
 
 
 def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32_correction=False):
@@ -165,6 +169,25 @@ def frob_inv_hpd(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_
     o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
     st = getattr(_lib.load(), name)(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, name, r)
+    return Xr, Xi, r.as_dict()
+
+
+def frob_inv_spd_pair(h: Handle, A, B, Xr=None, Xi=None, *, refine=0, prec=FROB_PREC_F64, refine_tol=0.0,
+                      final_resid=True, f32_correction=False):
+    """(A + iB)^{-1} for A, B symmetric positive definite (Algorithm 7 with C = A + X1^T X1)."""
+    n = A.shape[0]
+    Xr = _empty_like_sq(A, n) if Xr is None else Xr
+    Xi = _empty_like_sq(A, n) if Xi is None else Xi
+    pa, lda = _mat(A, n, n, "A")
+    pb, ldb = _mat(B, n, n, "B")
+    pr, ldx = _mat(Xr, n, n, "Xr")
+    pi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldx != ldxi:
+        raise ValueError("Xr and Xi must share a leading dimension")
+    h.bind_stream()
+    o, r = _opts(FROB_SHIFT_OFF, 0.0, 0, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
+    st = _lib.load().frob_inv_spd_pair(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
+    _lib.check(st, "frob_inv_spd_pair", r)
     return Xr, Xi, r.as_dict()
 
 
@@ -343,3 +366,91 @@ def frob_batched_tune(h: Handle, storage=FROB_PREC_F64):
     h.bind_stream()
     _lib.check(_lib.load().frob_batched_tune(h.ptr, int(storage), table), "frob_batched_tune")
     return {(k, c): table[4 * k + c] for k in range(2) for c in range(4)}
+
+
+# ----------------------------------------------------------------- Newton iterations (Section 5)
+def _newton_opts(tol, max_iter, **inv):
+    o = _lib.frob_newton_opts_t()
+    _lib.load().frob_default_newton_opts(ctypes.byref(o))
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.inv = _opts(inv.get("shift", FROB_SHIFT_AUTO), inv.get("mu", 0.0), inv.get("seed", 0), inv.get("refine", 0),
+                  inv.get("prec", FROB_PREC_F64), inv.get("refine_tol", 0.0), inv.get("final_resid", True),
+                  inv.get("f32_correction", False))
+    return o
+
+
+def frob_sign(h: Handle, Xr, Xi, Sr=None, Si=None, *, tol=1e-3, max_iter=100, **inv):
+    """Matrix sign by Newton's iteration X <- (X + X^{-1}) / 2 (Section 5.3), every
+    inverse by Frobenius inversion.  Returns (Sr, Si, result dict)."""
+    n = Xr.shape[0]
+    Sr = _empty_like_sq(Xr, n) if Sr is None else Sr
+    Si = _empty_like_sq(Xr, n) if Si is None else Si
+    px, ldx = _mat(Xr, n, n, "Xr")
+    pxi, ldxi = _mat(Xi, n, n, "Xi")
+    ps, lds = _mat(Sr, n, n, "Sr")
+    psi, ldsi = _mat(Si, n, n, "Si")
+    if ldx != ldxi or lds != ldsi:
+        raise ValueError("planar pairs must share a leading dimension")
+    h.bind_stream()
+    o, r = _newton_opts(tol, max_iter, **inv), _lib.frob_newton_result_t()
+    _lib.check(_lib.load().frob_sign(h.ptr, n, px, pxi, ldx, ps, psi, lds, ctypes.byref(o), ctypes.byref(r)),
+               "frob_sign", r.inv)
+    return Sr, Si, r.as_dict()
+
+
+def frob_polar(h: Handle, Xr, Xi, *, tol=1e-3, max_iter=100, **inv):
+    """Polar decomposition X = Q P by X <- (X + X^{-H}) / 2 (Section 5.5), P = Q^H X.
+    Returns (Qr, Qi, Pr, Pi, result dict)."""
+    n = Xr.shape[0]
+    Qr, Qi, Pr, Pi = (_empty_like_sq(Xr, n) for _ in range(4))
+    px, ldx = _mat(Xr, n, n, "Xr")
+    pxi, ldxi = _mat(Xi, n, n, "Xi")
+    if ldx != ldxi:
+        raise ValueError("Xr and Xi must share a leading dimension")
+    h.bind_stream()
+    o, r = _newton_opts(tol, max_iter, **inv), _lib.frob_newton_result_t()
+    vp = ctypes.c_void_p
+    _lib.check(_lib.load().frob_polar(h.ptr, n, px, pxi, ldx, vp(Qr.data_ptr()), vp(Qi.data_ptr()), n,
+                                      vp(Pr.data_ptr()), vp(Pi.data_ptr()), n, ctypes.byref(o), ctypes.byref(r)),
+               "frob_polar", r.inv)
+    return Qr, Qi, Pr, Pi, r.as_dict()
+
+
+def frob_sylvester(h: Handle, Ar, Ai, Br, Bi, Cr, Ci, *, tol=1e-1, max_iter=100, **inv):
+    """A Y + Y B = C through the sign of [[A, -C], [0, -B]] (Section 5.4).
+    Returns (Yr, Yi, result dict)."""
+    import torch
+    p, q = Ar.shape[0], Br.shape[0]
+    Yr = torch.empty((p, q), dtype=torch.float64, device=Ar.device)
+    Yi = torch.empty_like(Yr)
+    pa, lda = _mat(Ar, p, p, "Ar"); pai, ldai = _mat(Ai, p, p, "Ai")
+    pb, ldb = _mat(Br, q, q, "Br"); pbi, ldbi = _mat(Bi, q, q, "Bi")
+    pc, ldc = _mat(Cr, p, q, "Cr"); pci, ldci = _mat(Ci, p, q, "Ci")
+    if lda != ldai or ldb != ldbi or ldc != ldci:
+        raise ValueError("planar pairs must share a leading dimension")
+    h.bind_stream()
+    o, r = _newton_opts(tol, max_iter, **inv), _lib.frob_newton_result_t()
+    vp = ctypes.c_void_p
+    _lib.check(_lib.load().frob_sylvester(h.ptr, p, q, pa, pai, lda, pb, pbi, ldb, pc, pci, ldc, vp(Yr.data_ptr()),
+                                          vp(Yi.data_ptr()), q, ctypes.byref(o), ctypes.byref(r)),
+               "frob_sylvester", r.inv)
+    return Yr, Yi, r.as_dict()
+
+
+def frob_lyapunov(h: Handle, Ar, Ai, Cr, Ci, *, tol=1e-1, max_iter=100, **inv):
+    """A Y + Y A^H = C (Section 5.4 with B = A^H).  Returns (Yr, Yi, result dict)."""
+    import torch
+    p = Ar.shape[0]
+    Yr = torch.empty((p, p), dtype=torch.float64, device=Ar.device)
+    Yi = torch.empty_like(Yr)
+    pa, lda = _mat(Ar, p, p, "Ar"); pai, ldai = _mat(Ai, p, p, "Ai")
+    pc, ldc = _mat(Cr, p, p, "Cr"); pci, ldci = _mat(Ci, p, p, "Ci")
+    if lda != ldai or ldc != ldci:
+        raise ValueError("planar pairs must share a leading dimension")
+    h.bind_stream()
+    o, r = _newton_opts(tol, max_iter, **inv), _lib.frob_newton_result_t()
+    vp = ctypes.c_void_p
+    _lib.check(_lib.load().frob_lyapunov(h.ptr, p, pa, pai, lda, pc, pci, ldc, vp(Yr.data_ptr()), vp(Yi.data_ptr()),
+                                         p, ctypes.byref(o), ctypes.byref(r)), "frob_lyapunov", r.inv)
+    return Yr, Yi, r.as_dict()

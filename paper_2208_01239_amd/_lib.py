@@ -52,6 +52,17 @@ class frob_result_t(ctypes.Structure):
                 "resid0": self.resid0, "resid": self.resid, "norm2_est": self.norm2_est}
 
 
+class frob_newton_opts_t(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("inv", frob_opts_t)]
+
+
+class frob_newton_result_t(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("last_change", ctypes.c_double), ("inv", frob_result_t)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "last_change": self.last_change, "inv": self.inv.as_dict()}
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -67,11 +78,21 @@ SIGNATURES = {
     "frob_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "frob_inv_general": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_inv_hpd": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_inv_spd_pair": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_solve": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_inv_general_f32": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_inv_hpd_f32": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_solve_f32": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_refine": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_default_newton_opts": (None, [ctypes.POINTER(frob_newton_opts_t)]),
+    "frob_sign": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(frob_newton_opts_t),
+                       ctypes.POINTER(frob_newton_result_t)]),
+    "frob_polar": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(frob_newton_opts_t),
+                        ctypes.POINTER(frob_newton_result_t)]),
+    "frob_sylvester": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i,
+                            ctypes.POINTER(frob_newton_opts_t), ctypes.POINTER(frob_newton_result_t)]),
+    "frob_lyapunov": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(frob_newton_opts_t),
+                           ctypes.POINTER(frob_newton_result_t)]),
     "frob_cinv_lu": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_cinv_chol": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _i, _RES]),
     "frob_inv_adjoint": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -456,8 +456,15 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
   });
 }
 
-frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
-                           double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+}  // extern "C"
+
+namespace {
+
+// Algorithm 7.  step5_sign = -1: Hermitian positive definite M (B skew, so
+// B A^{-1} B = -X1^T X1 and C = A - X1^T X1); step5_sign = +1: A and B
+// symmetric positive definite (B A^{-1} B = X1^T X1, C = A + X1^T X1).
+frob_status_t chol_path(frob_handle* h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                        double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res, double step5_sign) {
   if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
   if (o.refine < 0 || o.prec < FROB_PREC_F64 || o.prec > FROB_PREC_BF16) return FROB_E_ARG;
@@ -495,10 +502,10 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     } else {
       trsm_f64(s, false, TRI_UPPER, true, n, n, DOp{F, ld, nullptr}, DOut{Y, ld, nullptr, nullptr}, tmp);
     }
-    // steps 4-5: C = A - X1^T X1 (B skew gives B A^{-1} B = -X1^T X1), lower triangle
+    // steps 4-5: C = A + step5_sign X1^T X1, lower triangle
     copy_f64(s, n, n, A, lda, nullptr, Cm, ld);
-    gemm_f64(s, true, false, n, n, n, -1.0, DOp{X1, ld, nullptr}, TRI_NONE, DOp{X1, ld, nullptr}, TRI_NONE, 1.0,
-             DOut{Cm, ld, nullptr, nullptr}, true);
+    gemm_f64(s, true, false, n, n, n, step5_sign, DOp{X1, ld, nullptr}, TRI_NONE, DOp{X1, ld, nullptr}, TRI_NONE,
+             1.0, DOut{Cm, ld, nullptr, nullptr}, true);
     // step 6: C = R2^T R2
     potrf_f64(s, n, Cm, ld, h->dinfo + 1, tmp);
     // steps 7-8: Re X = C^{-1} = R2^{-1} R2^{-T} = W^T W with W = (R2^T)^{-1} lower
@@ -525,6 +532,20 @@ frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, con
     if (res) *res = r;
     return st;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+frob_status_t frob_inv_hpd(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb, double* Xr,
+                           double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  return chol_path(h, n, A, lda, B, ldb, Xr, Xi, ldx, opts, res, -1.0);
+}
+
+frob_status_t frob_inv_spd_pair(frob_handle_t h, int n, const double* A, int lda, const double* B, int ldb,
+                                double* Xr, double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  return chol_path(h, n, A, lda, B, ldb, Xr, Xi, ldx, opts, res, 1.0);
 }
 
 frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int lda, const double* B, int ldb,
@@ -715,6 +736,170 @@ frob_status_t frob_refine(frob_handle_t h, int n, const double* A, int lda, cons
                                        o.refine_flags, c, &r);
     if (res) *res = r;
     return st;
+  });
+}
+
+// ------------------------------------------------ Newton iterations (Section 5)
+void frob_default_newton_opts(frob_newton_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-3;
+  o->max_iter = 100;
+  frob_default_opts(&o->inv);
+}
+
+namespace {
+
+frob_newton_opts_t newton_opts_or_default(const frob_newton_opts_t* o) {
+  frob_newton_opts_t d;
+  frob_default_newton_opts(&d);
+  if (!o) return d;
+  frob_newton_opts_t r = *o;
+  if (!(r.tol > 0.0)) r.tol = d.tol;
+  if (r.max_iter <= 0) r.max_iter = d.max_iter;
+  frob_opts_t zero;
+  std::memset(&zero, 0, sizeof(zero));
+  if (std::memcmp(&r.inv, &zero, sizeof(zero)) == 0) r.inv = d.inv;   // zeroed: the inversion's defaults
+  return r;
+}
+
+// The iteration X <- (X + op(X^{-1})) / 2 on X (n x n, ld n, at the front of
+// the workspace), each inverse by frob_inv_general into I (ld n).  `lead` is
+// the size of the region holding X, I and the two max-norm words.
+frob_status_t newton_iterate(frob_handle* h, int n, double* Xr, double* Xi, double* Ir, double* Ii,
+                             unsigned long long* maxes, size_t lead, bool herm, const frob_newton_opts_t& o,
+                             frob_newton_result_t* res) {
+  frob_newton_result_t r;
+  std::memset(&r, 0, sizeof(r));
+  frob_status_t st = FROB_OK;
+  unsigned long long hm[2];
+  for (int k = 0; k < o.max_iter; ++k) {
+    {
+      LeadScope ls(lead);
+      st = frob_inv_general(h, n, Xr, n, Xi, n, Ir, Ii, n, &o.inv, &r.inv);
+    }
+    if (st != FROB_OK && st != FROB_NO_CONVERGENCE) break;
+    st = FROB_OK;
+    newton_step(h->stream, n, Xr, Xi, n, Ir, Ii, n, herm, maxes);
+    FROB_HIP(hipMemcpyAsync(hm, maxes, sizeof(hm), hipMemcpyDeviceToHost, h->stream));
+    FROB_HIP(hipStreamSynchronize(h->stream));
+    double d, x;
+    std::memcpy(&d, &hm[0], sizeof(d));
+    std::memcpy(&x, &hm[1], sizeof(x));
+    r.iterations = k + 1;
+    r.last_change = x > 0.0 ? d / x : 0.0;
+    if (r.last_change <= o.tol) break;
+  }
+  if (res) *res = r;
+  return st;
+}
+
+}  // namespace
+
+frob_status_t frob_sign(frob_handle_t h, int n, const double* Xr, const double* Xi, int ldx, double* Sr, double* Si,
+                        int lds, const frob_newton_opts_t* opts, frob_newton_result_t* res) {
+  if (!h || !Xr || !Xi || !Sr || !Si || bad_dims(n, ldx) || lds < n) return FROB_E_ARG;
+  const frob_newton_opts_t o = newton_opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    const size_t lead = 4 * lead_of(nn) + 256;
+    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine));
+    double* Wr = (double*)base;
+    double* Wi = (double*)(base + lead_of(nn));
+    double* Ir = (double*)(base + 2 * lead_of(nn));
+    double* Ii = (double*)(base + 3 * lead_of(nn));
+    unsigned long long* maxes = (unsigned long long*)(base + 4 * lead_of(nn));
+    copy_f64(s, n, n, Xr, ldx, nullptr, Wr, n);
+    copy_f64(s, n, n, Xi, ldx, nullptr, Wi, n);
+    const frob_status_t st = newton_iterate(h, n, Wr, Wi, Ir, Ii, maxes, lead, false, o, res);
+    if (st == FROB_OK) {
+      copy_f64(s, n, n, Wr, n, nullptr, Sr, lds);
+      copy_f64(s, n, n, Wi, n, nullptr, Si, lds);
+      FROB_HIP(hipStreamSynchronize(s));
+    }
+    return st;
+  });
+}
+
+frob_status_t frob_polar(frob_handle_t h, int n, const double* Xr, const double* Xi, int ldx, double* Qr, double* Qi,
+                         int ldq, double* Pr, double* Pi, int ldp, const frob_newton_opts_t* opts,
+                         frob_newton_result_t* res) {
+  if (!h || !Xr || !Xi || !Qr || !Qi || !Pr || !Pi || bad_dims(n, ldx) || ldq < n || ldp < n) return FROB_E_ARG;
+  const frob_newton_opts_t o = newton_opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    hipStream_t s = h->stream;
+    const size_t nn = (size_t)n * n;
+    const size_t lead = 4 * lead_of(nn) + 256;
+    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine));
+    double* Wr = (double*)base;
+    double* Wi = (double*)(base + lead_of(nn));
+    double* Ir = (double*)(base + 2 * lead_of(nn));
+    double* Ii = (double*)(base + 3 * lead_of(nn));
+    unsigned long long* maxes = (unsigned long long*)(base + 4 * lead_of(nn));
+    copy_f64(s, n, n, Xr, ldx, nullptr, Wr, n);
+    copy_f64(s, n, n, Xi, ldx, nullptr, Wi, n);
+    const frob_status_t st = newton_iterate(h, n, Wr, Wi, Ir, Ii, maxes, lead, true, o, res);
+    if (st == FROB_OK) {
+      copy_f64(s, n, n, Wr, n, nullptr, Qr, ldq);
+      copy_f64(s, n, n, Wi, n, nullptr, Qi, ldq);
+      // P = Q^H X
+      gemm_z64(s, OP_C, OP_N, n, n, n, 1.0, ZOp{Wr, Wi, n, nullptr}, TRI_NONE, ZOp{Xr, Xi, ldx, nullptr}, TRI_NONE,
+               0.0, ZOut{Pr, Pi, ldp, nullptr, nullptr});
+      FROB_HIP(hipStreamSynchronize(s));
+    }
+    return st;
+  });
+}
+
+namespace {
+
+frob_status_t sylvester_impl(frob_handle* h, int p, int q, const double* Ar, const double* Ai, int lda,
+                             const double* Br, const double* Bi, int ldb, bool lyap, const double* Cr,
+                             const double* Ci, int ldc, double* Yr, double* Yi, int ldy, const frob_newton_opts_t& o,
+                             frob_newton_result_t* res) {
+  hipStream_t s = h->stream;
+  const int N = p + q;
+  const size_t nn = (size_t)N * N;
+  const size_t lead = 4 * lead_of(nn) + 256;
+  char* base = (char*)ws_reserve(h, lead + 256 + general_ws(N, o.inv.refine));
+  double* Wr = (double*)base;
+  double* Wi = (double*)(base + lead_of(nn));
+  double* Ir = (double*)(base + 2 * lead_of(nn));
+  double* Ii = (double*)(base + 3 * lead_of(nn));
+  unsigned long long* maxes = (unsigned long long*)(base + 4 * lead_of(nn));
+  sylvester_assemble(s, p, q, Ar, Ai, lda, Br, Bi, ldb, lyap, Cr, Ci, ldc, Wr, Wi);
+  const frob_status_t st = newton_iterate(h, N, Wr, Wi, Ir, Ii, maxes, lead, false, o, res);
+  if (st == FROB_OK) {
+    sylvester_extract(s, p, q, Wr, Wi, Yr, Yi, ldy);
+    FROB_HIP(hipStreamSynchronize(s));
+  }
+  return st;
+}
+
+}  // namespace
+
+frob_status_t frob_sylvester(frob_handle_t h, int p, int q, const double* Ar, const double* Ai, int lda,
+                             const double* Br, const double* Bi, int ldb, const double* Cr, const double* Ci, int ldc,
+                             double* Yr, double* Yi, int ldy, const frob_newton_opts_t* opts,
+                             frob_newton_result_t* res) {
+  if (!h || !Ar || !Ai || !Br || !Bi || !Cr || !Ci || !Yr || !Yi || p < 1 || q < 1 || p + q > FROB_MAX_N ||
+      lda < p || ldb < q || ldc < q || ldy < q)
+    return FROB_E_ARG;
+  const frob_newton_opts_t o = newton_opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    return sylvester_impl(h, p, q, Ar, Ai, lda, Br, Bi, ldb, false, Cr, Ci, ldc, Yr, Yi, ldy, o, res);
+  });
+}
+
+frob_status_t frob_lyapunov(frob_handle_t h, int p, const double* Ar, const double* Ai, int lda, const double* Cr,
+                            const double* Ci, int ldc, double* Yr, double* Yi, int ldy, const frob_newton_opts_t* opts,
+                            frob_newton_result_t* res) {
+  if (!h || !Ar || !Ai || !Cr || !Ci || !Yr || !Yi || p < 1 || 2 * p > FROB_MAX_N || lda < p || ldc < p || ldy < p)
+    return FROB_E_ARG;
+  const frob_newton_opts_t o = newton_opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    return sylvester_impl(h, p, p, Ar, Ai, lda, Ar, Ai, lda, true, Cr, Ci, ldc, Yr, Yi, ldy, o, res);
   });
 }
 

@@ -175,6 +175,18 @@ void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, c
 void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign);
 // Zero the strict upper triangle
 void zero_upper_f64(hipStream_t s, int n, double* a, int lda);
+// Newton iterations on the inversion: X <- (X + op(I)) / 2 with op(I) = I or
+// I^H (herm), and maxes[0] / maxes[1] <- the max norms of the change and of
+// the new iterate (as the bit patterns of non-negative doubles).
+void newton_step(hipStream_t s, int n, double* Xr, double* Xi, int ldx, const double* Ir, const double* Ii, int ldi,
+                 bool herm, unsigned long long* maxes);
+// X = [[A, -C], [0, -B]] (B = A^H when lyap) of order p + q, leading dimension p + q
+void sylvester_assemble(hipStream_t s, int p, int q, const double* Ar, const double* Ai, int lda, const double* Br,
+                        const double* Bi, int ldb, bool lyap, const double* Cr, const double* Ci, int ldc,
+                        double* Xr, double* Xi);
+// Y = -(1/2) times the upper right p x q block of S (order p + q)
+void sylvester_extract(hipStream_t s, int p, int q, const double* Sr, const double* Si, double* Yr, double* Yi,
+                       int ldy);
 // Widen / round between FP32 and FP64 storage (m x n, leading dimensions)
 void convert_f32_f64(hipStream_t s, int m, int n, const float* src, int lds, double* dst, int ldd);
 void convert_f64_f32(hipStream_t s, int m, int n, const double* src, int lds, float* dst, int ldd);

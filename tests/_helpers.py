@@ -31,7 +31,7 @@ def res_right(Mr, Mi, Yr, Yi):
 def to_dev(a, ld=None):
     """float64 numpy -> torch cuda tensor, optionally with a padded leading dimension."""
     import torch
-    a = np.ascontiguousarray(a, dtype=np.float64)
+    a = np.array(a, dtype=np.float64, order="C", copy=True)   # fresh, standard strides (also for 1 x 1 views)
     if ld is None or ld == a.shape[1]:
         return torch.from_numpy(a).cuda()
     buf = torch.full((a.shape[0], ld), float("nan"), dtype=torch.float64, device="cuda")

@@ -1,0 +1,115 @@
+"""GPU parity of the Newton iterations built on Frobenius inversion (Section 5
+of the paper): matrix sign (eq. (iter)), Sylvester and Lyapunov equations
+through the sign of [[A, -C], [0, -B]], and the polar decomposition
+(eq. (iter2)), against the oracle's iterations (every inverse by Algorithm 4)
+run to convergence, and against the closed forms of the constructed inputs.
+
+Both sides iterate to a tight stopping tolerance (1e-10) so that they reach
+the same limit; the remaining differences are the rounding of converged
+iterates.  The Frobenius route's inverses carry errors of about u kappa(C), so
+near the limit its relative change can level off above the tolerance: then
+the iteration runs to its step limit (still at the limit's accuracy), which
+the tests allow."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_01239_amd import inputs
+from _helpers import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-10
+KMAX = 40
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_2208_01239_amd as fi
+    hd = fi.Handle(0)
+    yield hd
+    hd.close()
+
+
+def relmax(Xr, Xi, Rr, Ri):
+    """Relative max-norm error of eq. (maxnorm)."""
+    return float(max(np.abs(Xr - Rr).max(), np.abs(Xi - Ri).max()) / max(np.abs(Rr).max(), np.abs(Ri).max()))
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 300, 1100])
+def test_sign(h, n):
+    import paper_2208_01239_amd as fi
+    Xr, Xi, Sr, Si = inputs.sign_problem(n, seed=500 + n)
+    Gr, Gi, res = fi.frob_sign(h, to_dev(Xr), to_dev(Xi), tol=EPS, max_iter=KMAX)
+    gr, gi = to_host(Gr), to_host(Gi)
+    Or, Oi, info, it = oracle.sign_newton(Xr, Xi, eps=EPS, kmax=KMAX)
+    assert info == 0
+    e_or, e_cf = relmax(gr, gi, Or, Oi), relmax(gr, gi, Sr, Si)
+    print(f"sign n={n}: {res['iterations']} steps (oracle {it}), last change {res['last_change']:.1e}, "
+          f"vs oracle {e_or:.2e}, vs closed form {e_cf:.2e}")
+    assert res["last_change"] <= EPS or res["iterations"] == KMAX
+    assert e_or <= 1e-8 and e_cf <= 1e-8
+    S = gr + 1j * gi
+    assert np.abs(S @ S - np.eye(n)).max() <= 1e-8 * max(1.0, np.abs(S).max() ** 2)
+
+
+def test_sign_paper_stopping_rule(h):
+    """tol = 1e-3 (the paper's choice) stops earlier, after the same number of
+    steps as the oracle's iteration on the same input."""
+    import paper_2208_01239_amd as fi
+    Xr, Xi, Sr, Si = inputs.sign_problem(200, seed=77)
+    _, _, res = fi.frob_sign(h, to_dev(Xr), to_dev(Xi))
+    _, _, _, it = oracle.sign_newton(Xr, Xi, eps=1e-3)
+    assert res["iterations"] == it and res["last_change"] <= 1e-3
+
+
+@pytest.mark.parametrize("p,q", [(3, 2), (40, 30), (300, 200), (640, 450)])
+def test_sylvester(h, p, q):
+    import paper_2208_01239_amd as fi
+    A, B, C, Y = inputs.sylvester_problem(p, q, seed=600 + p)
+    Gr, Gi, res = fi.frob_sylvester(h, to_dev(A.real), to_dev(A.imag), to_dev(B.real), to_dev(B.imag),
+                                    to_dev(C.real), to_dev(C.imag), tol=EPS, max_iter=KMAX)
+    gr, gi = to_host(Gr), to_host(Gi)
+    Or, Oi, info, it = oracle.sylvester_newton(A.real, A.imag, B.real, B.imag, C.real, C.imag, eps=EPS, kmax=KMAX)
+    assert info == 0
+    e_or, e_cf = relmax(gr, gi, Or, Oi), relmax(gr, gi, Y.real, Y.imag)
+    print(f"sylvester p={p} q={q}: {res['iterations']} steps (oracle {it}), vs oracle {e_or:.2e}, vs Y {e_cf:.2e}")
+    assert e_or <= 1e-9 and e_cf <= 1e-9
+
+
+@pytest.mark.parametrize("p", [5, 128, 300])
+def test_lyapunov(h, p):
+    import paper_2208_01239_amd as fi
+    A, B, C, Y = inputs.sylvester_problem(p, p, seed=700 + p, lyapunov=True)
+    Gr, Gi, res = fi.frob_lyapunov(h, to_dev(A.real), to_dev(A.imag), to_dev(C.real), to_dev(C.imag), tol=EPS,
+                                   max_iter=KMAX)
+    gr, gi = to_host(Gr), to_host(Gi)
+    Or, Oi, info, it = oracle.sylvester_newton(A.real, A.imag, B.real, B.imag, C.real, C.imag, eps=EPS, kmax=KMAX)
+    e_or, e_cf = relmax(gr, gi, Or, Oi), relmax(gr, gi, Y.real, Y.imag)
+    print(f"lyapunov p={p}: {res['iterations']} steps (oracle {it}), vs oracle {e_or:.2e}, vs Y {e_cf:.2e}")
+    assert info == 0 and e_or <= 1e-9 and e_cf <= 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 33, 257, 600])
+def test_polar(h, n):
+    import paper_2208_01239_amd as fi
+    X, Q, P = inputs.polar_problem(n, seed=800 + n)
+    Qr, Qi, Pr, Pi, res = fi.frob_polar(h, to_dev(X.real), to_dev(X.imag), tol=EPS, max_iter=KMAX)
+    qr, qi, pr, pi = (to_host(t) for t in (Qr, Qi, Pr, Pi))
+    Or, Oi, Opr, Opi, info, it = oracle.polar_newton(X.real, X.imag, eps=EPS, kmax=KMAX)
+    assert info == 0
+    eq, ep = relmax(qr, qi, Or, Oi), relmax(pr, pi, Opr, Opi)
+    eqc, epc = relmax(qr, qi, Q.real, Q.imag), relmax(pr, pi, P.real, P.imag)
+    print(f"polar n={n}: {res['iterations']} steps (oracle {it}); Q vs oracle {eq:.2e}, vs U {eqc:.2e}; "
+          f"P vs oracle {ep:.2e}, vs Z^H Z {epc:.2e}")
+    assert max(eq, ep, eqc, epc) <= 1e-8
+    Qc = qr + 1j * qi
+    assert np.abs(Qc.conj().T @ Qc - np.eye(n)).max() <= 1e-10
+
+
+def test_newton_reports_singular_step(h):
+    """An iterate with an eigenvalue 0 is singular: the inversion's status is
+    returned (here at the first step)."""
+    import paper_2208_01239_amd as fi
+    X = np.diag([1.0, 0.0, -2.0])
+    with pytest.raises(fi.FrobSingularError):
+        fi.frob_sign(h, to_dev(X), to_dev(np.zeros((3, 3))), tol=EPS)

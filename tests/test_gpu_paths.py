@@ -356,3 +356,32 @@ def test_mixed_precision_lookahead_orders(h, kind, prec, kappa):
     print(f"{kind} prec {prec} kappa {kappa:.0e}: unrefined {e0:.2e} -> refined {e:.2e} in "
           f"{res['refine_steps']} steps (resid0 {res['resid0']:.2e}, norm2_est {res['norm2_est']:.2e})")
     assert e <= TOL
+
+
+# ------------------------------------------------------------------ A > 0, B > 0 (end of Section 4.3)
+@pytest.mark.parametrize("n", [1, 2, 64, 257, 1100])
+def test_spd_pair(h, n):
+    """A and B symmetric positive definite: the Cholesky variant with
+    C = A + X1^T X1 against the oracle's complex Gaussian elimination
+    (Algorithm 4) and its Algorithm 7 variant; the inverse is complex
+    symmetric.  kappa(C) <= kappa(M) for this class, so the 1e-10 bar holds."""
+    import paper_2208_01239_amd as fi
+    A, B = inputs.spd_pair(n, seed=950 + n)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    Xr, Xi, res = fi.frob_inv_spd_pair(h, to_dev(A), to_dev(B))
+    xr, xi = to_host(Xr), to_host(Xi)
+    e = relF(xr, xi, Rr, Ri)
+    Or, Oi, oinfo, _ = oracle.frob_chol_spd_pair(A, B)
+    print(f"spd pair n={n}: relF vs Algorithm 4 {e:.2e}, vs oracle variant {relF(xr, xi, Or, Oi):.2e}")
+    assert oinfo == 0 and e <= TOL and relF(xr, xi, Or, Oi) <= TOL
+    assert np.abs(xr - xr.T).max() <= 1e-10 * np.abs(xr).max()
+    assert np.abs(xi - xi.T).max() <= 1e-10 * np.abs(xi).max()
+
+
+def test_spd_pair_rejects_indefinite_real_part(h):
+    import paper_2208_01239_amd as fi
+    A, B = inputs.spd_pair(6, seed=3)
+    with pytest.raises(fi.FrobNotHPDError) as ex:
+        fi.frob_inv_spd_pair(h, to_dev(-A), to_dev(B))
+    assert ex.value.result.stage == 1
