@@ -49,6 +49,10 @@ def _load():
     lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_cmatmul.restype = None
     lib.orc_frob_chol_spd_pair.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_tower_mul.argtypes = [i, i, _dp, _dp, _dp, _dp]
+    lib.orc_tower_mul.restype = None
+    lib.orc_tower_inv.argtypes = [i, i, _dp, _dp, _dp]
+    lib.orc_tower_inv.restype = ctypes.c_int
     lib.orc_sign_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _ip]
     lib.orc_polar_newton.argtypes = [i, _dp, _dp, d, i, _dp, _dp, _dp, _dp, _ip]
     lib.orc_sylvester_newton.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, d, i, _dp, _dp, _ip]
@@ -234,3 +238,25 @@ def sylvester_newton(Ar, Ai, Br, Bi, Cr, Ci, eps=1e-1, kmax=100):
     it = ctypes.c_int(0)
     info = lib.orc_sylvester_newton(p, q, a1, a2, b1, b2, c1, c2, float(eps), int(kmax), yr, yi, ctypes.byref(it))
     return Yr, Yi, info, it.value
+
+
+def tower_mul(tau, X, Y):
+    """Product in F_m^{n x n} (Section 2.4); X, Y: (2^m, n, n) coefficient planes."""
+    lib = _load()
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    m, n = len(tau), X.shape[1]
+    (X, px), (Y, py), (t, pt) = _c(X), _c(Y), _c(tau)
+    Z, pz = _out(1 << m, n, n)
+    lib.orc_tower_mul(m, n, pt, px, py, pz)
+    return Z
+
+
+def tower_inv(tau, C):
+    """Inverse in F_m^{n x n} through the regular representation.  Returns (Xinv planes, info)."""
+    lib = _load()
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    m, n = len(tau), C.shape[1]
+    (C, pc), (t, pt) = _c(C), _c(tau)
+    X, px = _out(1 << m, n, n)
+    info = lib.orc_tower_inv(m, n, pt, pc, px)
+    return X, info

@@ -742,3 +742,73 @@ int orc_sylvester_newton(int p, int q, const double *Ar, const double *Ai, const
   free(Xr); free(Xi); free(Sr); free(Si);
   return info;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.4: matrices over an iterated quadratic extension                 */
+/*   F_m = R[xi_1, ..., xi_m] / <xi_1^2 + tau_1, ..., xi_m^2 + tau_m>          */
+/* (eq. (K_m quotient) with every f_k = x^2 + tau_k), written as              */
+/* X = sum_alpha C_alpha xi^alpha (eq. (iterquadmat)), alpha in {0,1}^m.       */
+/* Plane p holds C_alpha with alpha_k = bit k-1 of p.                         */
+/* Basis products: xi^a xi^b = s(a, b) xi^(a xor b) with s(a, b) the product  */
+/* of -tau_k over the k where both a_k and b_k are 1.                         */
+/* ------------------------------------------------------------------------- */
+static double tower_sign(int m, const double *tau, int a, int b) {
+  double s = 1.0;
+  for (int k = 0; k < m; ++k)
+    if ((a >> k) & (b >> k) & 1) s *= -tau[k];
+  return s;
+}
+
+/* Z = X Y in F_m^{n x n} from the definition: Z_g = sum_a s(a, a^g) X_a Y_(a^g). */
+void orc_tower_mul(int m, int n, const double *tau, const double *X, const double *Y, double *Z) {
+  const int P = 1 << m;
+  const size_t nn = (size_t)n * n;
+  memset(Z, 0, nn * (size_t)P * sizeof(double));
+  for (int g = 0; g < P; ++g)
+    for (int a = 0; a < P; ++a) {
+      const int b = a ^ g;
+      const double s = tower_sign(m, tau, a, b);
+      const double *Xa = X + (size_t)a * nn, *Yb = Y + (size_t)b * nn;
+      double *Zg = Z + (size_t)g * nn;
+#pragma omp parallel for schedule(static)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double acc = 0.0;
+          for (int t = 0; t < n; ++t) acc += Xa[(size_t)i * n + t] * Yb[(size_t)t * n + j];
+          Zg[(size_t)i * n + j] += s * acc;
+        }
+    }
+}
+
+/* X^{-1} in F_m^{n x n} from its definition X Z = 1: multiplication by X is a
+ * real linear map on the 2^m coefficient matrices of Z (the regular
+ * representation: block (g, b) = s(g^b, b) C_(g^b)); the coefficients of the
+ * inverse solve it with right-hand side "1" (the identity in plane 0, zeros
+ * elsewhere), by real Gaussian elimination with partial pivoting.  Returns the
+ * 1-based zero-pivot index of the 2^m n system, or 0. */
+int orc_tower_inv(int m, int n, const double *tau, const double *C, double *Xinv) {
+  const int P = 1 << m;
+  const int N = P * n;
+  const size_t nn = (size_t)n * n;
+  double *L = re_alloc(N, N), *Z = re_alloc(N, n);
+  int *piv = (int *)calloc((size_t)N, sizeof(int));
+  for (int g = 0; g < P; ++g)
+    for (int b = 0; b < P; ++b) {
+      const int a = g ^ b;
+      const double s = tower_sign(m, tau, a, b);
+      const double *Ca = C + (size_t)a * nn;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) L[(size_t)(g * n + i) * N + b * n + j] = s * Ca[(size_t)i * n + j];
+    }
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  double fl = 0.0;
+  int info = re_getrf(N, L, piv, &fl);
+  if (!info) {
+    re_getrs_cols(N, n, L, piv, Z, &fl);
+    for (int b = 0; b < P; ++b)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Xinv[(size_t)b * nn + (size_t)i * n + j] = Z[(size_t)(b * n + i) * n + j];
+  }
+  free(L); free(Z); free(piv);
+  return info;
+}

@@ -104,6 +104,15 @@ int orc_sylvester_newton(int p, int q, const double *Ar, const double *Ai, const
  * B A^{-1} B = X1^T X1, so step 5 reads X4 = A + X3; every other step as
  * printed.  Same return codes as orc_frob_chol. */
 int orc_frob_chol_spd_pair(int n, const double *A, const double *B, double *Xr, double *Xi, double *flops);
+/* Section 2.4: matrices over the iterated quadratic extension F_m with
+ * xi_k^2 = -tau_k (every f_k = x^2 + tau_k), stored as 2^m real n x n planes
+ * (plane p = coefficient of xi^alpha, alpha_k = bit k-1 of p), contiguous.
+ * orc_tower_mul: the product from the definition of F_m.
+ * orc_tower_inv: the inverse from X Z = 1 through the real regular
+ * representation (order 2^m n) and Gaussian elimination with partial
+ * pivoting; returns 0 or the 1-based zero-pivot index. */
+void orc_tower_mul(int m, int n, const double *tau, const double *X, const double *Y, double *Z);
+int orc_tower_inv(int m, int n, const double *tau, const double *C, double *Xinv);
 int orc_num_threads(void);
 int orc_set_num_threads(int t);
 

@@ -599,3 +599,59 @@ def test_spd_pair_scalar_closed_form():
     Xr, Xi, info, _ = oracle.frob_chol_spd_pair(np.array([[a]]), np.array([[b]]))
     assert info == 0
     assert abs(Xr[0, 0] - a / (a * a + b * b)) <= 1e-16 and abs(Xi[0, 0] + b / (a * a + b * b)) <= 1e-16
+
+
+# ----------------------------------------------------------------------------- Section 2.4: iterated quadratic extensions
+def _tower_planes(m, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((1 << m, n, n))
+
+
+@pytest.mark.parametrize("tau", [1.0, 2.5])
+def test_tower_m1_is_complex_inversion(tau):
+    """m = 1: F_1 = R[xi] / (xi^2 + tau) is C through xi -> i sqrt(tau), so the
+    inverse of C0 + xi C1 is R + xi S / sqrt(tau) with R + iS = (C0 + i sqrt(tau) C1)^{-1}
+    (LAPACK), and tau = 1 gives the oracle's Algorithm 4 result."""
+    C = _tower_planes(1, 9, 11)
+    X, info = oracle.tower_inv([tau], C)
+    assert info == 0
+    ref = np.linalg.inv(C[0] + 1j * np.sqrt(tau) * C[1])
+    assert relF(X[0], X[1] * np.sqrt(tau), ref.real, ref.imag) <= 1e-12
+    if tau == 1.0:
+        Rr, Ri, _, _, _ = oracle.cinv_lu(C[0], C[1])
+        assert relF(X[0], X[1], Rr, Ri) <= 1e-12
+
+
+def test_tower_bicomplex_idempotent_split():
+    """m = 2, tau = (1, 1) (bicomplex matrices, xi_1 = i, xi_2 = j, ij = ji):
+    with Z1 = C0 + i C1, Z2 = C2 + i C3 and the idempotents e1,2 = (1 +- ij)/2,
+    X = (Z1 - i Z2) e1 + (Z1 + i Z2) e2, so X^{-1} = W1 e1 + W2 e2 with
+    W1,2 = (Z1 -+ i Z2)^{-1} (two complex inverses by LAPACK)."""
+    n = 7
+    C = _tower_planes(2, n, 12)
+    X, info = oracle.tower_inv([1.0, 1.0], C)
+    assert info == 0
+    Z1, Z2 = C[0] + 1j * C[1], C[2] + 1j * C[3]
+    W1, W2 = np.linalg.inv(Z1 - 1j * Z2), np.linalg.inv(Z1 + 1j * Z2)
+    S, D = (W1 + W2) / 2, (W1 - W2) / 2
+    ref = np.stack([S.real, S.imag, -D.imag, D.real])
+    assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_tower_product_definition_and_inverse():
+    """The product from the definition: m = 1, tau = 1 is the complex product;
+    scalars (n = 1) commute; X X^{-1} = 1 for m = 3 with unequal tau."""
+    A, B = _tower_planes(1, 5, 13), _tower_planes(1, 5, 14)
+    Z = oracle.tower_mul([1.0], A, B)
+    ref = (A[0] + 1j * A[1]) @ (B[0] + 1j * B[1])
+    assert np.abs(Z[0] - ref.real).max() <= 1e-12 and np.abs(Z[1] - ref.imag).max() <= 1e-12
+    tau = [1.0, 2.0, 0.5]
+    a, b = _tower_planes(3, 1, 15), _tower_planes(3, 1, 16)
+    assert np.abs(oracle.tower_mul(tau, a, b) - oracle.tower_mul(tau, b, a)).max() <= 1e-13
+    C = _tower_planes(3, 6, 17)
+    X, info = oracle.tower_inv(tau, C)
+    assert info == 0
+    one = oracle.tower_mul(tau, C, X)
+    target = np.zeros_like(one)
+    target[0] = np.eye(6)
+    assert np.abs(one - target).max() <= 1e-10
