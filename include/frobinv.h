@@ -207,6 +207,26 @@ frob_status_t frob_solve_f32(frob_handle_t handle, int n, int nrhs, const float 
 frob_status_t frob_refine(frob_handle_t handle, int n, const double *A, int lda, const double *B, int ldb,
                           double *Xr, double *Xi, int ldx, const frob_opts_t *opts, frob_result_t *res);
 
+/* Frobenius inversion over an iterated quadratic extension (Section 2.4,
+ * Theorem 2.10 (ii)): F_m = R[xi_1, ..., xi_m] / <xi_k^2 + tau_k>, tau_k > 0
+ * (m = 1: the complex numbers; m = 2, tau = (1, 1): bicomplex numbers).  A
+ * matrix X = sum_alpha C_alpha xi^alpha is given by its 2^m real coefficient
+ * planes, plane p holding C_alpha with alpha_k = bit k-1 of p.  The inverse
+ * is computed recursively on the top generator with eq. (lem:inverse)
+ * (Algorithm 1 over x^2 + tau_m: two inversions and three products over
+ * F_{m-1}), products by Gauss's three-multiplication scheme (Theorem 2.10
+ * (i)), and the F_1 inversions by frob_inv_general (xi_1 = i sqrt(tau_1)):
+ * 2^m real LU inversions and 3 (3^m - 2^m) real products in total, plus the
+ * products inside each complex inversion.
+ *   m         : 1 .. 4;  tau : host array of m values > 0
+ *   C, X      : host arrays of 2^m device pointers to n x n planes (ldc, ldx)
+ *   opts      : options of every complex inversion (shift, precision, refinement)
+ * Workspace: (2^(m+1) n^2 + temporaries) doubles ahead of the inversion's own.
+ * A generic X is invertible through this route; FROB_SINGULAR is returned when
+ * one of the F_1 inversions meets a singular matrix (stage and info from it). */
+frob_status_t frob_inv_tower(frob_handle_t handle, int m, int n, const double *tau, const double *const *C, int ldc,
+                             double *const *X, int ldx, const frob_opts_t *opts, frob_result_t *res);
+
 /* Newton iterations whose every step is one Frobenius inversion (the
  * applications of Section 5 of the paper).  Stopping rule of Section 5.3:
  * stop when ||X_k - X_{k-1}||_max / ||X_k||_max <= tol, with the max norm of

@@ -25,7 +25,7 @@ __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_ref
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
            "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
            "FROB_REFINE_SKIP_FINAL_RESID", "FROB_REFINE_F32_CORRECTION", "load_library", "frob_sign", "frob_polar",
-           "frob_sylvester", "frob_lyapunov", "frob_inv_spd_pair"]
+           "frob_sylvester", "frob_lyapunov", "frob_inv_spd_pair", "frob_inv_tower"]
 
 
 def load_library():
@@ -454,3 +454,33 @@ def frob_lyapunov(h: Handle, Ar, Ai, Cr, Ci, *, tol=1e-1, max_iter=100, **inv):
     _lib.check(_lib.load().frob_lyapunov(h.ptr, p, pa, pai, lda, pc, pci, ldc, vp(Yr.data_ptr()), vp(Yi.data_ptr()),
                                          p, ctypes.byref(o), ctypes.byref(r)), "frob_lyapunov", r.inv)
     return Yr, Yi, r.as_dict()
+
+
+def frob_inv_tower(h: Handle, tau, C, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0, prec=FROB_PREC_F64):
+    """Inverse of X = sum_alpha C[p] xi^alpha over the iterated quadratic extension
+    with xi_k^2 = -tau[k] (Section 2.4).  C: list of 2^m float64 (n, n) device
+    tensors (plane p = coefficient of xi^alpha, alpha_k = bit k of p).
+    Returns (list of 2^m planes of X^{-1}, result dict)."""
+    import torch
+    m = len(tau)
+    if len(C) != 1 << m:
+        raise ValueError("C must hold 2^m planes")
+    n = C[0].shape[0]
+    lds = set()
+    ptrs = []
+    for p, t in enumerate(C):
+        pt, ld = _mat(t, n, n, f"C[{p}]")
+        ptrs.append(pt)
+        lds.add(ld)
+    if len(lds) != 1:
+        raise ValueError("all planes must share a leading dimension")
+    X = [torch.empty((n, n), dtype=torch.float64, device=C[0].device) for _ in C]
+    h.bind_stream()
+    vp = ctypes.c_void_p
+    cin = (vp * len(C))(*[p.value for p in ptrs])
+    xout = (vp * len(C))(*[x.data_ptr() for x in X])
+    taus = (ctypes.c_double * m)(*[float(v) for v in tau])
+    o, r = _opts(shift, mu, seed, refine, prec), frob_result_t()
+    _lib.check(_lib.load().frob_inv_tower(h.ptr, m, n, taus, cin, lds.pop(), xout, n, ctypes.byref(o),
+                                          ctypes.byref(r)), "frob_inv_tower", r)
+    return X, r.as_dict()

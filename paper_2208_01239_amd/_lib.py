@@ -84,6 +84,8 @@ SIGNATURES = {
     "frob_inv_hpd_f32": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_solve_f32": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
     "frob_refine": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _OPTS, _RES]),
+    "frob_inv_tower": (_i, [_vp, _i, _i, ctypes.POINTER(_d), ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _i, _OPTS,
+                            _RES]),
     "frob_default_newton_opts": (None, [ctypes.POINTER(frob_newton_opts_t)]),
     "frob_sign": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(frob_newton_opts_t),
                        ctypes.POINTER(frob_newton_result_t)]),

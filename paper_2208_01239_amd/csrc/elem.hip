@@ -128,6 +128,16 @@ __global__ void k_cvt_f64_f32(int m, int n, const double* __restrict__ src, int 
   if (j < n) dst[(long long)i * ldd + j] = (float)src[(long long)i * lds + j];
 }
 
+// Gauss's three products P1 (in Z0), P2 (in Z1), P3 -> Z0 = P1 - tau P2, Z1 = P3 - P1 - P2
+__global__ void k_gauss3_combine(long long cnt, double* __restrict__ Z0, double* __restrict__ Z1,
+                                 const double* __restrict__ P3, double tau) {
+  const long long e = (long long)blockIdx.x * EB + threadIdx.x;
+  if (e >= cnt) return;
+  const double p1 = Z0[e], p2 = Z1[e];
+  Z0[e] = p1 - tau * p2;
+  Z1[e] = P3[e] - p1 - p2;
+}
+
 __global__ void k_zero_upper(int n, double* a, int lda) {
   const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
   if (j < n && j > i) a[(long long)i * lda + j] = 0.0;
@@ -208,6 +218,12 @@ void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, c
 void mirror_lower_f64(hipStream_t s, int n, double* a, int lda, double sign) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_mirror_lower, grid2d(n, n), dim3(EB), 0, s, n, a, lda, sign);
+  FROB_LAUNCH_CHECK();
+}
+
+void gauss3_combine_f64(hipStream_t s, long long cnt, double* Z0, double* Z1, const double* P3, double tau) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_gauss3_combine, dim3((unsigned)((cnt + EB - 1) / EB)), dim3(EB), 0, s, cnt, Z0, Z1, P3, tau);
   FROB_LAUNCH_CHECK();
 }
 

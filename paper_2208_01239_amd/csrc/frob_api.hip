@@ -6,6 +6,7 @@
 // frob_solve:       Algorithm 3 (linear systems, sign of step 7 corrected).
 // The complex-arithmetic baselines (Algorithms 4 and 8) live in cbase.hip.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -900,6 +901,117 @@ frob_status_t frob_lyapunov(frob_handle_t h, int p, const double* Ar, const doub
   const frob_newton_opts_t o = newton_opts_or_default(opts);
   return guarded(h, [&]() -> frob_status_t {
     return sylvester_impl(h, p, p, Ar, Ai, lda, Ar, Ai, lda, true, Cr, Ci, ldc, Yr, Yi, ldy, o, res);
+  });
+}
+
+// ------------------------------------- iterated quadratic extensions (Section 2.4)
+namespace {
+
+// Elements of F_k^{n x n} (xi_j^2 = -tau_j, j < k) are 2^k contiguous real
+// planes of n x n (ld n), plane p the coefficient of xi^alpha with
+// alpha_j = bit j of p; the top generator xi_k splits an element into its
+// low and high halves (eq. (iterquadmat2)).
+struct Tower {
+  frob_handle* h;
+  hipStream_t s;
+  int n;
+  const double* tau;        // tau[0 .. m)
+  frob_opts_t o;
+  size_t lead;              // bytes of the region holding every tower buffer
+  frob_result_t r;          // result of the last base inversion
+  size_t nn() const { return (size_t)n * n; }
+};
+
+// temporaries (doubles) of a product / an inversion at level k
+size_t tower_mul_tmp(int k, size_t nn) { return k == 0 ? 0 : 3 * ((size_t)1 << (k - 1)) * nn + tower_mul_tmp(k - 1, nn); }
+size_t tower_inv_tmp(int k, size_t nn) {
+  if (k == 1) return nn;   // the scaled imaginary part
+  return 3 * ((size_t)1 << (k - 1)) * nn + std::max(tower_inv_tmp(k - 1, nn), tower_mul_tmp(k - 1, nn));
+}
+
+// Z = X Y at level k: Gauss's three products per level (Theorem 2.10 (i))
+void tower_mul(Tower& t, int k, const double* X, const double* Y, double* Z, double* tmp) {
+  const int n = t.n;
+  if (k == 0) {
+    gemm_f64(t.s, false, false, n, n, n, 1.0, DOp{X, n, nullptr}, TRI_NONE, DOp{Y, n, nullptr}, TRI_NONE, 0.0,
+             DOut{Z, n, nullptr, nullptr});
+    return;
+  }
+  const size_t half = ((size_t)1 << (k - 1)) * t.nn();
+  double *S = tmp, *U = tmp + half, *P3 = tmp + 2 * half, *rest = tmp + 3 * half;
+  tower_mul(t, k - 1, X, Y, Z, rest);                       // P1 = X0 Y0  (in Z0)
+  tower_mul(t, k - 1, X + half, Y + half, Z + half, rest);  // P2 = X1 Y1  (in Z1)
+  lincomb_f64(t.s, 1, (int)half, 1.0, X, (int)half, 1.0, X + half, (int)half, S, (int)half);
+  lincomb_f64(t.s, 1, (int)half, 1.0, Y, (int)half, 1.0, Y + half, (int)half, U, (int)half);
+  tower_mul(t, k - 1, S, U, P3, rest);                      // P3 = (X0 + X1)(Y0 + Y1)
+  gauss3_combine_f64(t.s, (long long)half, Z, Z + half, P3, t.tau[k - 1]);
+}
+
+// Xi = X^{-1} at level k >= 1: Algorithm 1 over x^2 + tau_k (eq. (lem:inverse)):
+//   X1 = A^{-1}, X2 = X1 B, X3 = A + tau B X2, X4 = X3^{-1}, X5 = X2 X4,
+//   X^{-1} = X4 - xi_k X5;  at k = 1 the inversion over C with xi = i sqrt(tau).
+frob_status_t tower_inv(Tower& t, int k, const double* X, double* Xi, double* tmp) {
+  const int n = t.n;
+  const size_t nn = t.nn();
+  if (k == 1) {
+    const double sq = std::sqrt(t.tau[0]);
+    const double* B = X + nn;
+    if (sq != 1.0) {
+      lincomb_f64(t.s, 1, (int)nn, sq, X + nn, (int)nn, 0.0, X + nn, (int)nn, tmp, (int)nn);
+      B = tmp;
+    }
+    frob_status_t st;
+    {
+      LeadScope ls(t.lead);
+      st = frob_inv_general(t.h, n, X, n, B, n, Xi, Xi + nn, n, &t.o, &t.r);
+    }
+    if (st == FROB_OK && sq != 1.0) axpby_f64(t.s, 1, (int)nn, 1.0 / sq, Xi + nn, (int)nn, 0.0, Xi + nn, (int)nn);
+    return st;
+  }
+  const size_t half = ((size_t)1 << (k - 1)) * nn;
+  const double *A = X, *B = X + half;
+  double *X1 = tmp, *X2 = tmp + half, *X3 = tmp + 2 * half, *rest = tmp + 3 * half;
+  frob_status_t st = tower_inv(t, k - 1, A, X1, rest);
+  if (st != FROB_OK) return st;
+  tower_mul(t, k - 1, X1, B, X2, rest);
+  tower_mul(t, k - 1, B, X2, X3, rest);
+  lincomb_f64(t.s, 1, (int)half, 1.0, A, (int)half, t.tau[k - 1], X3, (int)half, X3, (int)half);
+  st = tower_inv(t, k - 1, X3, Xi, rest);                  // X4 -> low half
+  if (st != FROB_OK) return st;
+  tower_mul(t, k - 1, X2, Xi, Xi + half, rest);             // X5 -> high half
+  axpby_f64(t.s, 1, (int)half, -1.0, Xi + half, (int)half, 0.0, Xi + half, (int)half);
+  return FROB_OK;
+}
+
+}  // namespace
+
+frob_status_t frob_inv_tower(frob_handle_t h, int m, int n, const double* tau, const double* const* C, int ldc,
+                             double* const* X, int ldx, const frob_opts_t* opts, frob_result_t* res) {
+  if (!h || m < 1 || m > 4 || !tau || !C || !X || bad_dims(n, ldc) || ldx < n) return FROB_E_ARG;
+  const int P = 1 << m;
+  for (int k = 0; k < m; ++k)
+    if (!(tau[k] > 0.0) || !std::isfinite(tau[k])) return FROB_E_ARG;
+  for (int p = 0; p < P; ++p)
+    if (!C[p] || !X[p]) return FROB_E_ARG;
+  if ((size_t)P * n * n > ((size_t)1 << 31)) return FROB_E_ARG;   // plane-flat element counts fit in int
+  const frob_opts_t o = opts_or_default(opts);
+  return guarded(h, [&]() -> frob_status_t {
+    Tower t{h, h->stream, n, tau, o, 0, {}};
+    const size_t nn = t.nn();
+    const size_t doubles = 2 * (size_t)P * nn + tower_inv_tmp(m, nn);
+    t.lead = lead_of(doubles);
+    double* base = (double*)ws_reserve(h, t.lead + 256 + general_ws(n, o.refine));
+    double* Xin = base;
+    double* Xout = base + (size_t)P * nn;
+    double* tmp = Xout + (size_t)P * nn;
+    for (int p = 0; p < P; ++p) copy_f64(t.s, n, n, C[p], ldc, nullptr, Xin + (size_t)p * nn, n);
+    const frob_status_t st = tower_inv(t, m, Xin, Xout, tmp);
+    if (st == FROB_OK) {
+      for (int p = 0; p < P; ++p) copy_f64(t.s, n, n, Xout + (size_t)p * nn, n, nullptr, X[p], ldx);
+      FROB_HIP(hipStreamSynchronize(t.s));
+    }
+    if (res) *res = t.r;
+    return st;
   });
 }
 

@@ -187,6 +187,9 @@ void sylvester_assemble(hipStream_t s, int p, int q, const double* Ar, const dou
 // Y = -(1/2) times the upper right p x q block of S (order p + q)
 void sylvester_extract(hipStream_t s, int p, int q, const double* Sr, const double* Si, double* Yr, double* Yi,
                        int ldy);
+// Gauss's scheme over x^2 + tau (Proposition 2.2): with P1 in Z0, P2 in Z1 and
+// P3 = (X0 + X1)(Y0 + Y1): Z0 <- P1 - tau P2, Z1 <- P3 - P1 - P2 (cnt elements)
+void gauss3_combine_f64(hipStream_t s, long long cnt, double* Z0, double* Z1, const double* P3, double tau);
 // Widen / round between FP32 and FP64 storage (m x n, leading dimensions)
 void convert_f32_f64(hipStream_t s, int m, int n, const float* src, int lds, double* dst, int ldd);
 void convert_f64_f32(hipStream_t s, int m, int n, const double* src, int lds, float* dst, int ldd);
