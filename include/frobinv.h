@@ -61,7 +61,16 @@ typedef enum {
 typedef enum {
   FROB_SHIFT_OFF = 0,   /* Algorithm 5 only; a singular A is reported as FROB_SINGULAR (stage 1)          */
   FROB_SHIFT_AUTO = 1,  /* Algorithm 5; if the LU of A meets an exact zero pivot, redo with Algorithm 6    */
-  FROB_SHIFT_ON = 2     /* always Algorithm 6                                                               */
+  FROB_SHIFT_ON = 2,    /* always Algorithm 6                                                               */
+  FROB_SHIFT_PHASE = 3, /* Algorithm 5 on e^{i theta} M (opts->theta), the inverse rotated back:
+                           M^{-1} = e^{i theta} (e^{i theta} M)^{-1}.  Real part cos(t) A - sin(t) B, imaginary
+                           part sin(t) A + cos(t) B; theta = atan(mu) is Algorithm 6, theta = -pi/2 gives the
+                           formula for invertible B of Section 2.3, M^{-1} = B^{-1}A (A B^{-1} A + B)^{-1}
+                           - i (A B^{-1} A + B)^{-1} (Algorithm 5 on B - iA)                              */
+  FROB_SHIFT_COND = 4   /* conditioning-aware: theta = 0, -pi/2, pi/4, -pi/4 in turn until
+                           u kappa_1(C_theta) <= opts->cond_tol (kappa_1(C) = ||C||_1 ||C^{-1}||_1, formed
+                           exactly from C and from Re of the rotated inverse, which is C^{-1}); keeps the
+                           inverse with the smallest kappa_1(C_theta); singular real parts are skipped     */
 } frob_shift_t;
 
 /* Operand precision of the matrix-core products inside the factorizations,
@@ -85,7 +94,9 @@ typedef struct {
   int prec;             /* frob_prec_t, default FROB_PREC_F64                                               */
   double refine_tol;    /* stop refining once ||I - M X||_F / sqrt(n) <= refine_tol (<= 0: 1e-14)            */
   int refine_flags;     /* FROB_REFINE_* bits, default 0                                                    */
-  int reserved[3];
+  double theta;         /* rotation angle for FROB_SHIFT_PHASE (radians)                                    */
+  double cond_tol;      /* target of FROB_SHIFT_COND for u kappa_1(C) (<= 0: 1e-10)                          */
+  int reserved[2];
 } frob_opts_t;
 
 /* refine_flags: when refinement ends at the step limit (opts.refine steps
@@ -99,6 +110,10 @@ typedef struct {
  * 6e-8 kappa(M) times that error: a step still contracts while
  * kappa(M) << 1e7.  Ignored when opts.prec is not FROB_PREC_F64. */
 #define FROB_REFINE_F32_CORRECTION 2
+/* refine_flags: report kappa_1(C) = ||C||_1 ||C^{-1}||_1 in result.cond1_C
+ * (two column-sum passes over n x n; C^{-1} is the real part of the inverse
+ * of the matrix inverted). */
+#define FROB_REPORT_COND 4
 
 typedef struct {
   int info;             /* 1-based column of the failing pivot, 0 if none                                   */
@@ -110,7 +125,9 @@ typedef struct {
   double resid;         /* the same for the returned inverse (refine > 0 only; NaN if skipped, see above)   */
   double norm2_est;     /* power-iteration estimate (a lower bound) of ||I - M X||_2 for the unrefined inverse,
                            formed only when ||I - M X||_F >= 1; 0 otherwise                                */
-  double reserved[1];
+  double cond1_C;       /* kappa_1(C) = ||C||_1 ||C^{-1}||_1 of the inversion used (FROB_SHIFT_COND, or with
+                           FROB_REPORT_COND); 0 otherwise                                                   */
+  double theta;         /* rotation used by FROB_SHIFT_PHASE / FROB_SHIFT_COND (0 otherwise)                 */
 } frob_result_t;
 
 /* Fill *opts with the defaults (FROB_SHIFT_AUTO, mu drawn, no refinement). */

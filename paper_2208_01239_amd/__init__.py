@@ -16,7 +16,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32_CORRECTION,  # noqa: F401
-                   FROB_REFINE_SKIP_FINAL_RESID,
+                   FROB_REFINE_SKIP_FINAL_RESID, FROB_REPORT_COND, FROB_SHIFT_COND, FROB_SHIFT_PHASE,
                    FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNoConvergenceError, FrobNotHPDError, FrobSingularError,
                    frob_opts_t, frob_result_t)
 
@@ -100,7 +100,8 @@ def _mat(t, n_rows, n_cols, name, dtype=None):
     return ctypes.c_void_p(t.data_ptr()), int(ld)
 
 
-def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32_correction=False):
+def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32_correction=False, theta=0.0,
+          cond_tol=0.0, report_cond=False):
     o = frob_opts_t()
     _lib.load().frob_default_opts(ctypes.byref(o))
     o.shift = int(shift)
@@ -110,7 +111,9 @@ def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32
     o.prec = int(prec)
     o.refine_tol = float(refine_tol)
     o.refine_flags = (0 if final_resid else FROB_REFINE_SKIP_FINAL_RESID) | \
-        (FROB_REFINE_F32_CORRECTION if f32_correction else 0)
+        (FROB_REFINE_F32_CORRECTION if f32_correction else 0) | (FROB_REPORT_COND if report_cond else 0)
+    o.theta = float(theta)
+    o.cond_tol = float(cond_tol)
     return o
 
 
@@ -126,7 +129,8 @@ def _fn32(name, A):
 
 
 def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0,
-                     prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True, f32_correction=False):
+                     prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True, f32_correction=False, theta=0.0,
+                     cond_tol=0.0, report_cond=False):
     """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting).
 
     prec: operand precision of the matrix-core products (FROB_PREC_F64/F32/BF16);
@@ -134,7 +138,11 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     final_resid=False: skip the residual of the returned inverse when the step
     limit ends refinement (result "resid" is then NaN);
     f32_correction=True: after FP64 factorizations, form each step's
-    correction X R with FP32 matrix-core operands (the residual stays FP64)."""
+    correction X R with FP32 matrix-core operands (the residual stays FP64);
+    shift=FROB_SHIFT_PHASE with theta: invert e^{i theta} M and rotate back
+    (theta = -pi/2: the formula for invertible B); shift=FROB_SHIFT_COND:
+    rotations tried until u kappa_1(C) <= cond_tol; report_cond: kappa_1(C)
+    in the result."""
     n = A.shape[0]
     name, dt = _fn32("frob_inv_general", A)
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
@@ -146,7 +154,8 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     if ldx != ldxi:
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
-    o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid, f32_correction), frob_result_t()
+    o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid, f32_correction, theta, cond_tol,
+                 report_cond), frob_result_t()
     st = getattr(_lib.load(), name)(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, name, r)
     return Xr, Xi, r.as_dict()

@@ -27,29 +27,34 @@ FROB_E_CAPTURE = -5
 FROB_SHIFT_OFF = 0
 FROB_SHIFT_AUTO = 1
 FROB_SHIFT_ON = 2
+FROB_SHIFT_PHASE = 3
+FROB_SHIFT_COND = 4
 FROB_PREC_F64 = 0
 FROB_PREC_F32 = 1
 FROB_PREC_BF16 = 2
 FROB_REFINE_SKIP_FINAL_RESID = 1
 FROB_REFINE_F32_CORRECTION = 2
+FROB_REPORT_COND = 4
 
 
 class frob_opts_t(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine", ctypes.c_int), ("prec", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("refine_flags", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("refine_flags", ctypes.c_int), ("theta", ctypes.c_double), ("cond_tol", ctypes.c_double),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class frob_result_t(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int), ("stage", ctypes.c_int), ("mu_used", ctypes.c_double),
                 ("shifts_tried", ctypes.c_int), ("refine_steps", ctypes.c_int),
                 ("resid0", ctypes.c_double), ("resid", ctypes.c_double), ("norm2_est", ctypes.c_double),
-                ("reserved", ctypes.c_double * 1)]
+                ("cond1_C", ctypes.c_double), ("theta", ctypes.c_double)]
 
     def as_dict(self):
         return {"info": self.info, "stage": self.stage, "mu_used": self.mu_used,
                 "shifts_tried": self.shifts_tried, "refine_steps": self.refine_steps,
-                "resid0": self.resid0, "resid": self.resid, "norm2_est": self.norm2_est}
+                "resid0": self.resid0, "resid": self.resid, "norm2_est": self.norm2_est,
+                "cond1_C": self.cond1_C, "theta": self.theta}
 
 
 class frob_newton_opts_t(ctypes.Structure):

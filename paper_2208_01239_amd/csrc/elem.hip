@@ -106,6 +106,43 @@ __global__ void k_rotate(int m, int n, double mu, const double* __restrict__ A, 
   X2[(long long)i * ld2 + j] = mu * a + b;
 }
 
+// (X1, X2) = (c A - s B, s A + c B)
+__global__ void k_rot(int m, int n, double c, double sn, const double* __restrict__ A, int lda,
+                      const double* __restrict__ B, int ldb, double* X1, int ld1, double* X2, int ld2) {
+  const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  const double a = A[(long long)i * lda + j], b = B[(long long)i * ldb + j];
+  X1[(long long)i * ld1 + j] = c * a - sn * b;
+  X2[(long long)i * ld2 + j] = sn * a + c * b;
+}
+
+// colsum[j] += sum over this block's rows of |a_ij|
+constexpr int COL_ROWS = 64;
+__global__ void k_colabs(int n, const double* __restrict__ a, int lda, double* colsum) {
+  const int j = blockIdx.x * EB + threadIdx.x;
+  if (j >= n) return;
+  const int i0 = blockIdx.y * COL_ROWS, i1 = min(n, i0 + COL_ROWS);
+  double acc = 0.0;
+  for (int i = i0; i < i1; ++i) acc += fabs(a[(long long)i * lda + j]);
+  atomicAdd(colsum + j, acc);
+}
+
+// *out = max_j colsum[j] (one block)
+__global__ void k_maxabs(int n, const double* __restrict__ v, double* out) {
+  double m = 0.0;
+  for (int j = threadIdx.x; j < n; j += EB) m = fmax(m, v[j]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ double part[EB / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < EB / 64; ++w) t = fmax(t, part[w]);
+    *out = t;
+  }
+}
+
 __global__ void k_permute_cols(int m, int n, const double* __restrict__ src, int lds, const int* __restrict__ perm,
                                double* __restrict__ dst, int ldd) {
   const int i = blockIdx.y, j = blockIdx.x * EB + threadIdx.x;
@@ -205,6 +242,21 @@ void rotate_f64(hipStream_t s, int m, int n, double mu, const double* A, int lda
                 double* X1, int ld1, double* X2, int ld2) {
   if (m <= 0 || n <= 0) return;
   hipLaunchKernelGGL(k_rotate, grid2d(m, n), dim3(EB), 0, s, m, n, mu, A, lda, B, ldb, X1, ld1, X2, ld2);
+  FROB_LAUNCH_CHECK();
+}
+
+void rot_f64(hipStream_t s, int m, int n, double c, double sn, const double* A, int lda, const double* B, int ldb,
+             double* X1, int ld1, double* X2, int ld2) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_rot, grid2d(m, n), dim3(EB), 0, s, m, n, c, sn, A, lda, B, ldb, X1, ld1, X2, ld2);
+  FROB_LAUNCH_CHECK();
+}
+
+void norm1_f64(hipStream_t s, int n, const double* a, int lda, double* colsum, double* out) {
+  fill_f64(s, 1, n, 0.0, colsum, n);
+  hipLaunchKernelGGL(k_colabs, dim3(ceil_div(n, EB), ceil_div(n, COL_ROWS)), dim3(EB), 0, s, n, a, lda, colsum);
+  FROB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_maxabs, dim3(1), dim3(EB), 0, s, n, colsum, out);
   FROB_LAUNCH_CHECK();
 }
 

@@ -184,6 +184,8 @@ bool bad_dims(int n, int lda) { return n < 1 || n > FROB_MAX_N || lda < n; }
 struct GenWs {
   double *F, *Y, *C, *W, *tmp;
   int *p1, *p2;
+  double* cond;   // n column sums, then ||C||_1 and ||C^{-1}||_1
+  bool want_cond;
   int ld;    // Y, W
   int ldF;   // F and C: n x 2n, room for the columns carried through their LU
   frob_handle* h;
@@ -195,6 +197,7 @@ size_t gen_ws_bytes(int n) {
   c.take<double>(2 * nn); c.take<double>(nn); c.take<double>(2 * nn); c.take<double>(nn);
   c.take<double>(solver_work_elems(n));
   c.take<int>(n); c.take<int>(n);
+  c.take<double>((size_t)n + 8);
   return c.off;
 }
 
@@ -204,6 +207,8 @@ GenWs gen_ws_carve(Carve& c, int n) {
   w.F = c.take<double>(2 * nn); w.Y = c.take<double>(nn); w.C = c.take<double>(2 * nn); w.W = c.take<double>(nn);
   w.tmp = c.take<double>(solver_work_elems(n));
   w.p1 = c.take<int>(n); w.p2 = c.take<int>(n);
+  w.cond = c.take<double>((size_t)n + 8);
+  w.want_cond = false;
   w.ld = n;
   w.ldF = 2 * n;
   w.h = nullptr;
@@ -233,11 +238,12 @@ Carve reserve_carve(frob_handle* h, size_t bytes) {
 }
 
 // Bytes of workspace of one call of each FP64 entry point.
-size_t general_ws(int n, int refine) {
+size_t general_ws(int n, int refine, bool keep = false) {
   const size_t nn = (size_t)n * n;
   Carve sz(nullptr);
   sz.take<char>(gen_ws_bytes(n));
   sz.take<double>(nn); sz.take<double>(nn);   // shifted A, B
+  if (keep) { sz.take<double>(nn); sz.take<double>(nn); }   // best inverse kept by FROB_SHIFT_COND
   sz.take<char>(ns_ws_bytes(n, refine));
   return sz.off;
 }
@@ -294,6 +300,7 @@ bool frob_lu_front(hipStream_t s, int n, const double* A, int lda, const double*
     gemm_f64(s, false, false, n, n, n, 1.0, DOp{B, ldb, nullptr}, TRI_NONE, DOp{w.Y, ld, nullptr}, TRI_NONE, 1.0,
              DOut{w.C, lf, nullptr, nullptr});
   }
+  if (w.want_cond) norm1_f64(s, n, w.C, lf, w.cond, w.cond + n);   // ||C||_1, before C is factored
   // step 4: P2 C = L2 U2   (a zero pivot here means M is singular, Lemma 2.3)
   const bool carry2 = carry && cinv;
   if (carry2) identity_f64(s, n, w.C + n, lf);
@@ -315,6 +322,7 @@ void frob_lu_pass(hipStream_t s, int n, const double* A, int lda, const double* 
     trsm_f64(s, true, TRI_LOWER_UNIT, false, n, n, LU2, DOut{w.W, ld, nullptr, nullptr}, w.tmp);
     permute_cols_f64(s, n, n, w.W, ld, w.p2, Xr, ldx);
   }
+  if (w.want_cond) norm1_f64(s, n, Xr, ldx, w.cond, w.cond + n + 1);   // ||C^{-1}||_1
   // step 5, second block row: Im X = -Y C^{-1}
   {
     ProfScope ps(w.h, PROF_GEMM_NNN, 2.0 * n * (double)n * n, nullptr, 24.0 * n * (double)n);
@@ -400,52 +408,115 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
                                double* Xi, int ldx, const frob_opts_t* opts, frob_result_t* res) {
   if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
-  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.refine < 0 || o.prec < FROB_PREC_F64 ||
-      o.prec > FROB_PREC_BF16)
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_COND || o.refine < 0 || o.prec < FROB_PREC_F64 ||
+      o.prec > FROB_PREC_BF16 || (o.shift == FROB_SHIFT_PHASE && !std::isfinite(o.theta)))
     return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
-    Carve c = reserve_carve(h, general_ws(n, o.refine));
+    const bool keep = o.shift == FROB_SHIFT_COND;
+    Carve c = reserve_carve(h, general_ws(n, o.refine, keep));
     GenWs w = gen_ws_carve(c, n);
     w.h = h;
+    w.want_cond = keep || (o.refine_flags & FROB_REPORT_COND);
     double* As = c.take<double>(nn);
     double* Bs = c.take<double>(nn);
+    double* Kr = keep ? c.take<double>(nn) : nullptr;
+    double* Ki = keep ? c.take<double>(nn) : nullptr;
     frob_result_t r;
     std::memset(&r, 0, sizeof(r));
     frob_status_t st = FROB_OK;
     bool done = false;
     LowPrecScope lp(o.prec);   // FP32 / BF16 operands in the products of the factorization passes
-    if (o.shift != FROB_SHIFT_ON) {
+    double hc[2] = {0.0, 0.0};
+    auto read_cond = [&]() {
+      if (!w.want_cond) return 0.0;
+      FROB_HIP(hipMemcpyAsync(hc, w.cond + n, sizeof(hc), hipMemcpyDeviceToHost, s));
+      FROB_HIP(hipStreamSynchronize(s));
+      return hc[0] * hc[1];
+    };
+    // One pass of Algorithm 5 on e^{i theta} M (theta = 0: M itself), the
+    // inverse rotated back; returns false if the real part is singular.
+    auto rotated_pass = [&](double theta) {
+      const double cs = std::cos(theta), sn = std::sin(theta);
+      const bool rot = theta != 0.0;
+      if (rot) rot_f64(s, n, n, cs, sn, A, lda, B, ldb, As, n, Bs, n);
       fill_i32(s, INFO_SLOTS, 0, h->dinfo);
-      frob_lu_pass(s, n, A, lda, B, ldb, Xr, Xi, ldx, w, h->dinfo);
+      frob_lu_pass(s, n, rot ? As : A, rot ? n : lda, rot ? Bs : B, rot ? n : ldb, Xr, Xi, ldx, w, h->dinfo);
       read_info(h);
-      if (h->hinfo[0] == 0) {
-        done = true;
-        if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; }
-      } else if (o.shift == FROB_SHIFT_OFF) {
-        done = true;
-        st = FROB_SINGULAR; r.info = h->hinfo[0]; r.stage = 1;
+      if (h->hinfo[0] != 0) { r.info = h->hinfo[0]; r.stage = 1; return false; }
+      if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; return true; }
+      if (rot) rot_f64(s, n, n, cs, sn, Xr, ldx, Xi, ldx, Xr, ldx, Xi, ldx);
+      r.info = 0; r.stage = 0; r.theta = theta;
+      return true;
+    };
+    if (o.shift == FROB_SHIFT_PHASE) {
+      done = rotated_pass(o.theta);
+      if (!done) st = FROB_SINGULAR;
+      if (st == FROB_OK) r.cond1_C = read_cond();
+    } else if (o.shift == FROB_SHIFT_COND) {
+      // theta = 0 (eq. (Finv)), -pi/2 (the formula for invertible B), then the diagonals
+      const double pi = 3.14159265358979323846;
+      const double thetas[4] = {0.0, -0.5 * pi, 0.25 * pi, -0.25 * pi};
+      const double tol = o.cond_tol > 0.0 ? o.cond_tol : 1e-10;
+      double best = INFINITY, best_theta = 0.0;
+      bool have = false, cur_is_best = false;
+      for (int t = 0; t < 4; ++t) {
+        st = FROB_OK;
+        r.shifts_tried++;
+        cur_is_best = false;
+        if (!rotated_pass(thetas[t]) || st != FROB_OK) { st = FROB_OK; continue; }
+        const double k1 = read_cond();
+        const bool meets = 0x1p-53 * k1 <= tol;
+        if (k1 < best) {
+          best = k1; best_theta = thetas[t]; have = true; cur_is_best = true;
+          if (!meets && t < 3) {   // kept while the next rotation is tried
+            copy_f64(s, n, n, Xr, ldx, nullptr, Kr, n);
+            copy_f64(s, n, n, Xi, ldx, nullptr, Ki, n);
+          }
+        }
+        if (meets) break;          // the first rotation that meets the target is also the best so far
       }
+      if (have && !cur_is_best) {   // restore the best-conditioned inverse
+        copy_f64(s, n, n, Kr, n, nullptr, Xr, ldx);
+        copy_f64(s, n, n, Ki, n, nullptr, Xi, ldx);
+      }
+      done = have;
+      st = have ? FROB_OK : FROB_SINGULAR;
+      if (have) { r.cond1_C = best; r.theta = best_theta; r.info = 0; r.stage = 0; }
+    } else {
+      if (o.shift != FROB_SHIFT_ON) {
+        fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+        frob_lu_pass(s, n, A, lda, B, ldb, Xr, Xi, ldx, w, h->dinfo);
+        read_info(h);
+        if (h->hinfo[0] == 0) {
+          done = true;
+          if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; }
+        } else if (o.shift == FROB_SHIFT_OFF) {
+          done = true;
+          st = FROB_SINGULAR; r.info = h->hinfo[0]; r.stage = 1;
+        }
+      }
+      // Algorithm 6: invert (1 + i mu) M, whose real part A - mu B is singular for
+      // at most n values of mu (Lemma 4.3), then multiply the inverse by (1 + i mu).
+      for (int attempt = 0; !done && attempt < 3; ++attempt) {
+        const double mu = (o.mu > 0.0 && attempt == 0) ? o.mu : draw_mu(h);
+        r.shifts_tried++;
+        rotate_f64(s, n, n, mu, A, lda, B, ldb, As, n, Bs, n);        // X1 = A - mu B, X2 = mu A + B
+        fill_i32(s, INFO_SLOTS, 0, h->dinfo);
+        frob_lu_pass(s, n, As, n, Bs, n, Xr, Xi, ldx, w, h->dinfo);   // X3 + i X4 = (X1 + i X2)^{-1}
+        read_info(h);
+        if (h->hinfo[0] != 0) { r.info = h->hinfo[0]; r.stage = 1; continue; }
+        done = true;
+        r.mu_used = mu;
+        if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; break; }
+        rotate_f64(s, n, n, mu, Xr, ldx, Xi, ldx, Xr, ldx, Xi, ldx);   // X5 = X3 - mu X4, X6 = mu X3 + X4
+        r.info = 0; r.stage = 0;
+      }
+      if (!done) st = FROB_SINGULAR;
+      if (st == FROB_OK) r.cond1_C = read_cond();
     }
-    // Algorithm 6: invert (1 + i mu) M, whose real part A - mu B is singular for
-    // at most n values of mu (Lemma 4.3), then multiply the inverse by (1 + i mu).
-    for (int attempt = 0; !done && attempt < 3; ++attempt) {
-      const double mu = (o.mu > 0.0 && attempt == 0) ? o.mu : draw_mu(h);
-      r.shifts_tried++;
-      rotate_f64(s, n, n, mu, A, lda, B, ldb, As, n, Bs, n);        // X1 = A - mu B, X2 = mu A + B
-      fill_i32(s, INFO_SLOTS, 0, h->dinfo);
-      frob_lu_pass(s, n, As, n, Bs, n, Xr, Xi, ldx, w, h->dinfo);   // X3 + i X4 = (X1 + i X2)^{-1}
-      read_info(h);
-      if (h->hinfo[0] != 0) { r.info = h->hinfo[0]; r.stage = 1; continue; }
-      done = true;
-      r.mu_used = mu;
-      if (h->hinfo[1]) { st = FROB_SINGULAR; r.info = h->hinfo[1]; r.stage = 2; break; }
-      rotate_f64(s, n, n, mu, Xr, ldx, Xi, ldx, Xr, ldx, Xi, ldx);   // X5 = X3 - mu X4, X6 = mu X3 + X4
-      r.info = 0; r.stage = 0;
-    }
-    if (!done) st = FROB_SINGULAR;
     if (st == FROB_OK && o.refine > 0) {
       LowPrecScope fp64(LP_NONE);   // the residual is formed in FP64
       st = ns_refine(h, n, A, lda, B, ldb, Xr, Xi, ldx, o.refine, o.refine_tol, o.prec, o.refine_flags, c, &r);
@@ -641,7 +712,7 @@ frob_status_t frob_inv_general_f32(frob_handle_t h, int n, const float* A, int l
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const size_t lead = 4 * lead_of(nn);
-    double* base = (double*)ws_reserve(h, lead + 256 + general_ws(n, o.refine));
+    double* base = (double*)ws_reserve(h, lead + 256 + general_ws(n, o.refine, o.shift == FROB_SHIFT_COND));
     double *A64 = base, *B64 = base + lead_of(nn) / 8, *Xr64 = base + 2 * lead_of(nn) / 8,
            *Xi64 = base + 3 * lead_of(nn) / 8;
     convert_f32_f64(s, n, n, A, lda, A64, n);
@@ -805,7 +876,7 @@ frob_status_t frob_sign(frob_handle_t h, int n, const double* Xr, const double* 
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const size_t lead = 4 * lead_of(nn) + 256;
-    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine));
+    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
     double* Wr = (double*)base;
     double* Wi = (double*)(base + lead_of(nn));
     double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -832,7 +903,7 @@ frob_status_t frob_polar(frob_handle_t h, int n, const double* Xr, const double*
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const size_t lead = 4 * lead_of(nn) + 256;
-    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine));
+    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
     double* Wr = (double*)base;
     double* Wi = (double*)(base + lead_of(nn));
     double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -863,7 +934,7 @@ frob_status_t sylvester_impl(frob_handle* h, int p, int q, const double* Ar, con
   const int N = p + q;
   const size_t nn = (size_t)N * N;
   const size_t lead = 4 * lead_of(nn) + 256;
-  char* base = (char*)ws_reserve(h, lead + 256 + general_ws(N, o.inv.refine));
+  char* base = (char*)ws_reserve(h, lead + 256 + general_ws(N, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
   double* Wr = (double*)base;
   double* Wi = (double*)(base + lead_of(nn));
   double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -1000,7 +1071,7 @@ frob_status_t frob_inv_tower(frob_handle_t h, int m, int n, const double* tau, c
     const size_t nn = t.nn();
     const size_t doubles = 2 * (size_t)P * nn + tower_inv_tmp(m, nn);
     t.lead = lead_of(doubles);
-    double* base = (double*)ws_reserve(h, t.lead + 256 + general_ws(n, o.refine));
+    double* base = (double*)ws_reserve(h, t.lead + 256 + general_ws(n, o.refine, o.shift == FROB_SHIFT_COND));
     double* Xin = base;
     double* Xout = base + (size_t)P * nn;
     double* tmp = Xout + (size_t)P * nn;

@@ -168,6 +168,11 @@ void acc_rot_f64(hipStream_t s, int m, int n, const double* P, int ldp, const do
 // (X1, X2) = (A - mu B, mu A + B): shift in; used in-place-safe on distinct buffers
 void rotate_f64(hipStream_t s, int m, int n, double mu, const double* A, int lda, const double* B, int ldb,
                 double* X1, int ld1, double* X2, int ld2);
+// (X1, X2) = (c A - s B, s A + c B): the parts of e^{i theta} (A + iB) for c = cos, s = sin
+void rot_f64(hipStream_t s, int m, int n, double c, double sn, const double* A, int lda, const double* B, int ldb,
+             double* X1, int ld1, double* X2, int ld2);
+// *out = ||a||_1 (largest column sum of |a|) for an n x n matrix; colsum holds n doubles
+void norm1_f64(hipStream_t s, int n, const double* a, int lda, double* colsum, double* out);
 // dst[:, perm[k]] = src[:, k]
 void permute_cols_f64(hipStream_t s, int m, int n, const double* src, int lds, const int* perm, double* dst,
                       int ldd);
