@@ -49,6 +49,8 @@ def _load():
     lib.orc_cmatmul.argtypes = [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_cmatmul.restype = None
     lib.orc_frob_chol_spd_pair.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_csolve_refined.argtypes = [i, i, _dp, _dp, _dp, _dp, i, _dp, _dp, _dp]
+    lib.orc_csolve_refined.restype = ctypes.c_int
     lib.orc_tower_mul.argtypes = [i, i, _dp, _dp, _dp, _dp]
     lib.orc_tower_mul.restype = None
     lib.orc_tower_inv.argtypes = [i, i, _dp, _dp, _dp]
@@ -260,3 +262,21 @@ def tower_inv(tau, C):
     X, px = _out(1 << m, n, n)
     info = lib.orc_tower_inv(m, n, pt, pc, px)
     return X, info
+
+
+def csolve_refined(Mr, Mi, Br, Bi, steps=3):
+    """x = M^{-1} b for n x p right-hand sides: complex GEPP plus refinement with
+    double-double residuals.  Returns (Xr, Xi, info, last) with last the
+    largest relative max-norm size of the final correction over the columns."""
+    lib = _load()
+    n = Mr.shape[0]
+    Br = np.asarray(Br, dtype=np.float64)
+    Bi = np.asarray(Bi, dtype=np.float64)
+    if Br.ndim == 1:
+        Br, Bi = Br[:, None], Bi[:, None]
+    p = Br.shape[1]
+    (Mr, a), (Mi, b), (Br, c), (Bi, d) = _c(Mr), _c(Mi), _c(Br), _c(Bi)
+    (Xr, xr), (Xi, xi) = _out(n, p), _out(n, p)
+    last = ctypes.c_double(0.0)
+    info = lib.orc_csolve_refined(n, p, a, b, c, d, int(steps), xr, xi, ctypes.byref(last))
+    return Xr, Xi, info, last.value

@@ -113,6 +113,15 @@ int orc_frob_chol_spd_pair(int n, const double *A, const double *B, double *Xr, 
  * pivoting; returns 0 or the 1-based zero-pivot index. */
 void orc_tower_mul(int m, int n, const double *tau, const double *X, const double *Y, double *Z);
 int orc_tower_inv(int m, int n, const double *tau, const double *C, double *Xinv);
+/* M x = b for p right-hand sides (b, x: n x p planar) by complex GEPP and
+ * `steps` steps of iterative refinement with the residual b - M x
+ * accumulated in double-double (error-free transformations, no fused
+ * multiply-add), each correction solved with the same factors.  A reference
+ * accurate to about the unit roundoff while u kappa(M) < 1.  *last (may be
+ * NULL) receives the largest relative size (max norm) of the final correction
+ * over the columns.  Returns 0 or the 1-based index of an exactly zero pivot. */
+int orc_csolve_refined(int n, int p, const double *Mr, const double *Mi, const double *Br, const double *Bi,
+                       int steps, double *Xr, double *Xi, double *last);
 int orc_num_threads(void);
 int orc_set_num_threads(int t);
 

@@ -21,6 +21,12 @@ of the paper (Section 5) and the synthetic configurations used for measurement:
 * ``spectrum_device`` -- the same recipe at large orders, drawn and assembled
                       with torch on a device (its own random stream), with
                       the inverse V diag(1/sigma) U^H from the same factors.
+* ``spectrum_rotations`` -- M = U diag(sigma) W (HPD: U diag(sigma) U^H)
+                      with U, W products of random 2 x 2 unitary rotations
+                      between random row permutations, built from row
+                      operations alone, so that numpy on a host and torch on
+                      a device produce the same bits (the input of the
+                      mixed-precision workloads at large order).
 * ``batch``        -- uneven batch: n ~ U{16..512}, kinds alternate general/HPD.
 * ``spd_pair``     -- A = G1 G1^T / n + I and B = G2 G2^T / n + I with G1, G2
                       iid N(0, 1): both symmetric positive definite (the class
@@ -164,6 +170,102 @@ def spectrum_device(n: int, kappa: float, kind: str = "general", seed: int = 302
         M = 0.5 * (M + M.conj().T)
         Minv = 0.5 * (Minv + Minv.conj().T)
     return (M.real.contiguous(), M.imag.contiguous(), Minv.real.contiguous(), Minv.imag.contiguous())
+
+
+def _rotation_levels(n: int, rng):
+    """Random levels of a unitary built from row operations: for each level a
+    row permutation and, for the row pairs (2m, 2m + 1) of the permuted
+    matrix, a 2 x 2 unitary [[alpha, beta], [-conj(beta), conj(alpha)]] with
+    alpha = c e^{ia}, beta = s e^{ib}.  Cosine, sine and the phases come from
+    the rational parametrisation ((1 - t^2), 2t) / (1 + t^2), so every
+    coefficient is a few correctly rounded operations on uniform draws and
+    the same on every machine."""
+    h = n // 2
+    levels = []
+    for _ in range(2 * max(1, int(np.ceil(np.log2(max(n, 2)))))):
+        perm = rng.permutation(n)
+        t, pa, pb = rng.uniform(-1.0, 1.0, (3, h))
+        sa, sb = (2.0 * rng.integers(0, 2, (2, h)) - 1.0)
+        den = 1.0 + t * t
+        c, s = (1.0 - t * t) / den, (2.0 * t) / den
+        da, db = 1.0 + pa * pa, 1.0 + pb * pb
+        ar, ai = c * (sa * ((1.0 - pa * pa) / da)), c * (sa * ((2.0 * pa) / da))
+        br, bi = s * (sb * ((1.0 - pb * pb) / db)), s * (sb * ((2.0 * pb) / db))
+        levels.append((perm, ar, ai, br, bi))
+    return levels
+
+
+def _mix_pairs(Xr, Xi, p, q, r, s):
+    """Rows (2m, 2m + 1) -> (p a + q b, r a + s b) with complex coefficient
+    vectors p, q, r, s given as (re, im) column vectors; plain products and
+    sums in a fixed order (no fused multiply-add)."""
+    h = Xr.shape[0] // 2
+    ar, ai = Xr[0:2 * h:2], Xi[0:2 * h:2]
+    br, bi = Xr[1:2 * h:2], Xi[1:2 * h:2]
+    nar = p[0] * ar - p[1] * ai + q[0] * br - q[1] * bi
+    nai = p[0] * ai + p[1] * ar + q[0] * bi + q[1] * br
+    nbr = r[0] * ar - r[1] * ai + s[0] * br - s[1] * bi
+    nbi = r[0] * ai + r[1] * ar + s[0] * bi + s[1] * br
+    Xr[0:2 * h:2], Xi[0:2 * h:2] = nar, nai
+    Xr[1:2 * h:2], Xi[1:2 * h:2] = nbr, nbi
+
+
+def _apply_unitary(Xr, Xi, levels, adjoint, to):
+    """X <- U X (adjoint: U^H X) for U = B_L P_L ... B_1 P_1, where P_k takes
+    row perm_k[i] to row i and B_k is the level's pair rotation."""
+    if not adjoint:
+        for perm, ar, ai, br, bi in levels:
+            idx = to(perm)
+            Xr, Xi = Xr[idx], Xi[idx]
+            a, b = (to(ar), to(ai)), (to(br), to(bi))
+            _mix_pairs(Xr, Xi, a, b, (-b[0], b[1]), (a[0], -a[1]))
+    else:
+        # U^H = P_1^T B_1^H ... P_L^T B_L^H, B^H = [[conj(alpha), -beta], [conj(beta), alpha]]
+        for perm, ar, ai, br, bi in reversed(levels):
+            a, b = (to(ar), to(ai)), (to(br), to(bi))
+            _mix_pairs(Xr, Xi, (a[0], -a[1]), (-b[0], -b[1]), (b[0], -b[1]), a)
+            idx = to(np.argsort(perm))
+            Xr, Xi = Xr[idx], Xi[idx]
+    return Xr, Xi
+
+
+def spectrum_rotations(n: int, kappa: float, kind: str = "general", seed: int = 302, device=None):
+    """M = U diag(sigma) W (general) or U diag(sigma) U^H made exactly
+    Hermitian (HPD), sigma_j = kappa^(-j/(n-1)), U and W random unitaries of
+    2 ceil(log2 n) levels each (``_rotation_levels``).  All random draws and
+    coefficients are made on the host with numpy; the matrix is assembled by
+    row permutations, pair rotations and row scalings only, elementwise IEEE
+    products and sums evaluated in one fixed order, either with numpy
+    (device None: numpy arrays) or with torch on ``device`` (torch tensors).
+    The two produce identical bits, so expected values computed on a host
+    for the numpy matrix apply to the device matrix.  The singular values of
+    M are sigma up to rounding (a few units of roundoff per level)."""
+    rng = np.random.default_rng(seed)
+    U = _rotation_levels(n, rng)
+    W = U if kind == "hpd" else _rotation_levels(n, rng)
+    # kappa ** x through the C library's pow on Python floats, not a vectorised power
+    sig = np.array([float(kappa) ** (-(j / max(n - 1, 1))) for j in range(n)])
+    if device is None:
+        def to(a):
+            return a[:, None] if a.ndim == 1 and a.dtype == np.float64 else a
+        Xr, Xi = np.eye(n), np.zeros((n, n))
+    else:
+        import torch
+
+        def to(a):
+            t = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+            return t[:, None] if a.ndim == 1 and a.dtype == np.float64 else t
+        Xr = torch.eye(n, dtype=torch.float64, device=device)
+        Xi = torch.zeros((n, n), dtype=torch.float64, device=device)
+    Xr, Xi = _apply_unitary(Xr, Xi, W, kind == "hpd", to)
+    s = to(sig)
+    Xr, Xi = Xr * s, Xi * s
+    Xr, Xi = _apply_unitary(Xr, Xi, U, False, to)
+    if kind == "hpd":
+        Xr, Xi = 0.5 * (Xr + Xr.T), 0.5 * (Xi - Xi.T)
+    if device is None:
+        return np.ascontiguousarray(Xr), np.ascontiguousarray(Xi)
+    return Xr.contiguous(), Xi.contiguous()
 
 
 def batch(count: int = 2048, seed: int = 4, n_lo: int = 16, n_hi: int = 512):

@@ -655,3 +655,74 @@ def test_tower_product_definition_and_inverse():
     target = np.zeros_like(one)
     target[0] = np.eye(6)
     assert np.abs(one - target).max() <= 1e-10
+
+
+# ---------------------------------------------------------------- refined reference solve
+def _exact_complex_solve(Mr, Mi, b):
+    """Exact solution over the rationals of the real 2n x 2n embedding
+    [[Mr, -Mi], [Mi, Mr]] [xr; xi] = [b; 0] (every FP64 input is a rational)."""
+    from fractions import Fraction as F
+    n = Mr.shape[0]
+    N = 2 * n
+    A = [[F(0)] * (N + 1) for _ in range(N)]
+    for i in range(n):
+        for j in range(n):
+            a, c = F(float(Mr[i, j])), F(float(Mi[i, j]))
+            A[i][j], A[i][n + j], A[n + i][j], A[n + i][n + j] = a, -c, c, a
+        A[i][N] = F(float(b[i]))
+    for k in range(N):
+        p = next(i for i in range(k, N) if A[i][k] != 0)
+        A[k], A[p] = A[p], A[k]
+        for i in range(k + 1, N):
+            f = A[i][k] / A[k][k]
+            if f:
+                for j in range(k, N + 1):
+                    A[i][j] -= f * A[k][j]
+    x = [F(0)] * N
+    for i in range(N - 1, -1, -1):
+        x[i] = (A[i][N] - sum(A[i][j] * x[j] for j in range(i + 1, N))) / A[i][i]
+    return np.array([float(v) for v in x[:n]]) + 1j * np.array([float(v) for v in x[n:]])
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_csolve_refined_exact(n):
+    """Hilbert real part with a small skew imaginary coupling (kappa 2.7e5 at
+    n = 6, 1.1e10 at n = 9): after refinement with double-double residuals the
+    solution is the exact rational solution rounded (within 2 u, normwise),
+    while plain GEPP is off by about u kappa."""
+    H = np.array([[1.0 / (i + j + 1) for j in range(n)] for i in range(n)])
+    Mi = np.zeros((n, n))
+    Mi[0, n - 1], Mi[n - 1, 0] = 0.125, -0.125
+    b = np.zeros(n)
+    b[2] = 1.0
+    xe = _exact_complex_solve(H, Mi, b)
+    x0r, x0i, info, _ = oracle.csolve_refined(H, Mi, b, np.zeros(n), steps=0)
+    assert info == 0
+    xr, xi, info, last = oracle.csolve_refined(H, Mi, b, np.zeros(n), steps=3)
+    e0 = np.abs(x0r[:, 0] + 1j * x0i[:, 0] - xe).max() / np.abs(xe).max()
+    e = np.abs(xr[:, 0] + 1j * xi[:, 0] - xe).max() / np.abs(xe).max()
+    assert e <= 2 * 2.0 ** -53
+    assert last <= 1e-15
+    if n == 9:
+        assert e0 > 1e-10   # the plain solve is not good enough: refinement is what pins the reference
+
+
+def test_csolve_refined_columns_of_inverse():
+    """Columns of the identity give columns of Algorithm 4's inverse."""
+    A, B = inputs.general(40, 41)
+    Xr, Xi, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    cols = np.array([0, 7, 39])
+    E = np.zeros((40, 3))
+    E[cols, np.arange(3)] = 1.0
+    xr, xi, info, last = oracle.csolve_refined(A, B, E, np.zeros_like(E), steps=2)
+    assert info == 0
+    assert np.abs(xr - Xr[:, cols]).max() + np.abs(xi - Xi[:, cols]).max() <= 1e-12 * np.abs(Xr).max()
+
+
+def test_csolve_refined_singular():
+    """An exactly zero pivot is reported (1-based) and nothing is refined."""
+    Mr = np.array([[1.0, 2.0], [2.0, 4.0]])
+    Mi = np.zeros((2, 2))
+    _, _, info, _ = oracle.csolve_refined(Mr, Mi, np.ones(2), np.zeros(2), steps=2)
+    assert info == 2
