@@ -28,6 +28,7 @@ namespace bat {
 constexpr int BT = 256;          // threads per workgroup
 constexpr int BNMAX = 512;       // largest order handled in-workgroup
 constexpr int PNB = 32;          // largest LU panel width
+constexpr int PP = PNB + 1;      // LDS pitch of panel rows (odd in 8-byte words: rows fall on different banks)
 constexpr int XNB = 16;          // diagonal blocks solved by register substitution (triangular solves, Cholesky)
 constexpr int GT = 64;           // GEMM output tile
 constexpr int GP = GT + 4;       // LDS pitch of a GEMM tile row
@@ -59,10 +60,15 @@ template <typename T>
 struct Smem {
   T ga[GKof<T>::v * GP];     // GEMM A tile, k-major
   T gb[GKof<T>::v * GP];     // GEMM B tile, k-major
-  T panel[BNMAX * PNB];      // LU panel / Cholesky diagonal block / triangular diagonal block
+  T panel[BNMAX * PP];       // LU panel / Cholesky diagonal block / triangular diagonal block
   T red_v[BT / 64];
   int red_i[BT / 64];
   int bcast[4];
+  int perm[BNMAX];           // LU: original row now at each row position
+  int cont[BNMAX];           // LU panel: panel row whose content each panel row now holds
+  int tl_dst[2 * PNB];       // LU panel: rows changed by the panel's interchanges,
+  int tl_src[2 * PNB];       //   and the rows their new content comes from
+  int tl_n;
 };
 
 // Scalar arguments of the out-of-line building blocks arrive in vector
@@ -148,6 +154,19 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
       }
       bb_sync();
     }
+    // epilogue: all reads of C are issued before any write (one round trip
+    // to memory per tile instead of one per element)
+    T cv[2][4][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int i = imin(tm + wm + 16 * a + Mfma<T>::row(lane, v), M - 1);
+          const int j = imin(tn + wn + 16 * b + (lane & 15), N - 1);
+          cv[a][v][b] = beta != T(0) ? C[(long long)i * ldc + j] : T(0);
+        }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -156,12 +175,7 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int j = tn + wn + 16 * b + (lane & 15);
-          if (i < M && j < N) {
-            T* cp = C + (long long)i * ldc + j;
-            T val = alpha * acc[a][b][v];
-            if (beta != T(0)) val += beta * *cp;
-            *cp = val;
-          }
+          if (i < M && j < N) C[(long long)i * ldc + j] = alpha * acc[a][b][v] + beta * cv[a][v][b];
         }
       }
   }
@@ -169,40 +183,49 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
 }
 
 // ------------------------------------------------------- triangular solves
-// op(L) X = B in place (B is n x nrhs).  L is lower triangular (unit or not);
-// op(L) = L (forward) or L^T (backward).
+// op(T) X = B in place (B is n x nrhs), op(T) triangular:
+//   mode 0: T lower, op(T) = T   (forward substitution; unit diagonal if `unit`)
+//   mode 1: T lower, op(T) = T^T (backward)
+//   mode 2: T upper, op(T) = T   (backward)
+// Leaves of nb <= 16 rows are solved by register substitution (one thread per
+// right-hand side); the updates follow the order of the recursive algorithm
+// (solve the first half, update the second half with a product of depth
+// n / 2, solve the second half), flattened: when a leaf completes a group of
+// g = lowbit(leaves done) leaves, the next g leaves' rows are updated by the
+// group's solution, a product of depth g * nb.  Every row of B is thus
+// rewritten about log2(n / nb) times instead of n / nb times, and the deep
+// products near the root do most of the work.
 template <typename T>
-BB_FN void wg_trsm_left(Smem<T>& sm, int n, int nrhs, const T* L, int ldl, bool unit, bool trans, T* B, int ldb,
-                        int nb) {
-  n = uni(n); nrhs = uni(nrhs); ldl = uni(ldl); ldb = uni(ldb); unit = uni(unit); trans = uni(trans);
+BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, bool unit, T* B, int ldb, int nb) {
+  mode = uni(mode); n = uni(n); nrhs = uni(nrhs); ldl = uni(ldl); ldb = uni(ldb); unit = uni(unit);
   const int tid = bb_tid();
-  nb = imin(uni(nb), XNB);
+  nb = imax(imin(uni(nb), XNB), 1);
   const int nblk = (n + nb - 1) / nb;
-  for (int s = 0; s < nblk; ++s) {
-    const int blk = trans ? nblk - 1 - s : s;
+  const bool fwd = mode == 0;
+  for (int t = 0; t < nblk; ++t) {
+    const int blk = fwd ? t : nblk - 1 - t;
     const int k0 = blk * nb, kb = imin(nb, n - k0);
-    // diagonal block of op(L) into LDS: D(i, k) = op(L)(k0 + i, k0 + k)
+    // diagonal block of op(T) into LDS: D(i, k) = op(T)(k0 + i, k0 + k)
     T* D = sm.panel;
     for (int e = tid; e < kb * kb; e += BT) {
       const int i = e / kb, k = e % kb;
-      const int r = trans ? k : i, c = trans ? i : k;      // stored coordinates within the block
-      D[i * PNB + k] = (c <= r) ? L[(long long)(k0 + r) * ldl + k0 + c] : T(0);
+      const int r = mode == 1 ? k : i, c = mode == 1 ? i : k;   // stored coordinates within the block
+      const bool in = mode == 2 ? c >= r : c <= r;
+      D[i * PP + k] = in ? L[(long long)(k0 + r) * ldl + k0 + c] : T(0);
     }
     bb_sync();
-    // substitution: one thread per right-hand side column (register indices
-    // are compile-time; rows at and beyond kb are masked)
     for (int j = tid; j < nrhs; j += BT) {
       T x[XNB];
 #pragma unroll
       for (int i = 0; i < XNB; ++i) x[i] = B[(long long)(k0 + imin(i, kb - 1)) * ldb + j];
-      if (!trans) {
+      if (fwd) {
 #pragma unroll
         for (int i = 0; i < XNB; ++i)
           if (i < kb) {
             T v = x[i];
 #pragma unroll
-            for (int k = 0; k < i; ++k) v -= D[i * PNB + k] * x[k];
-            x[i] = unit ? v : v / D[i * PNB + i];
+            for (int k = 0; k < i; ++k) v -= D[i * PP + k] * x[k];
+            x[i] = unit ? v : v / D[i * PP + i];
           }
       } else {
 #pragma unroll
@@ -211,8 +234,8 @@ BB_FN void wg_trsm_left(Smem<T>& sm, int n, int nrhs, const T* L, int ldl, bool 
             T v = x[i];
 #pragma unroll
             for (int k = i + 1; k < XNB; ++k)
-              if (k < kb) v -= D[i * PNB + k] * x[k];
-            x[i] = unit ? v : v / D[i * PNB + i];
+              if (k < kb) v -= D[i * PP + k] * x[k];
+            x[i] = unit ? v : v / D[i * PP + i];
           }
       }
 #pragma unroll
@@ -220,55 +243,25 @@ BB_FN void wg_trsm_left(Smem<T>& sm, int n, int nrhs, const T* L, int ldl, bool 
         if (i < kb) B[(long long)(k0 + i) * ldb + j] = x[i];
     }
     bb_sync();
-    // update the rest: forward B[k0+kb:] -= L[k0+kb:, blk] X_blk;  backward B[:k0] -= L[blk, :k0]^T X_blk
-    if (!trans) {
-      const int m = n - k0 - kb;
-      if (m > 0)
-        wg_gemm<T>(sm, m, nrhs, kb, T(-1), L + (long long)(k0 + kb) * ldl + k0, ldl, false,
-                   B + (long long)k0 * ldb, ldb, false, T(1), B + (long long)(k0 + kb) * ldb, ldb);
+    const int g = (t + 1) & -(t + 1);   // leaves in the group this leaf completes
+    if (fwd) {
+      // done: rows [c0, c1); next: rows [c1, r1) -= op(T)[c1:r1, c0:c1] X[c0:c1]
+      const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
+      if (c1 < n)
+        wg_gemm<T>(sm, r1 - c1, nrhs, c1 - c0, T(-1), L + (long long)c1 * ldl + c0, ldl, false,
+                   B + (long long)c0 * ldb, ldb, false, T(1), B + (long long)c1 * ldb, ldb);
     } else {
-      if (k0 > 0)
-        wg_gemm<T>(sm, k0, nrhs, kb, T(-1), L + (long long)k0 * ldl, ldl, true, B + (long long)k0 * ldb, ldb,
-                   false, T(1), B, ldb);
+      // done: rows [k0, c1); next: rows [r0, k0) -= op(T)[r0:k0, k0:c1] X[k0:c1]
+      const int c1 = imin(k0 + g * nb, n), r0 = imax(0, k0 - g * nb);
+      if (k0 > 0) {
+        if (mode == 1)
+          wg_gemm<T>(sm, k0 - r0, nrhs, c1 - k0, T(-1), L + (long long)k0 * ldl + r0, ldl, true,
+                     B + (long long)k0 * ldb, ldb, false, T(1), B + (long long)r0 * ldb, ldb);
+        else
+          wg_gemm<T>(sm, k0 - r0, nrhs, c1 - k0, T(-1), L + (long long)r0 * ldl + k0, ldl, false,
+                     B + (long long)k0 * ldb, ldb, false, T(1), B + (long long)r0 * ldb, ldb);
+      }
     }
-  }
-}
-
-// U X = B in place with U upper triangular (non-unit), backward blocks
-template <typename T>
-BB_FN void wg_trsm_upper(Smem<T>& sm, int n, int nrhs, const T* U, int ldu, T* B, int ldb, int nb) {
-  n = uni(n); nrhs = uni(nrhs); ldu = uni(ldu); ldb = uni(ldb);
-  const int tid = bb_tid();
-  nb = imin(uni(nb), XNB);
-  const int nblk = (n + nb - 1) / nb;
-  for (int blk = nblk - 1; blk >= 0; --blk) {
-    const int k0 = blk * nb, kb = imin(nb, n - k0);
-    T* D = sm.panel;
-    for (int e = tid; e < kb * kb; e += BT) {
-      const int i = e / kb, k = e % kb;
-      D[i * PNB + k] = (k >= i) ? U[(long long)(k0 + i) * ldu + k0 + k] : T(0);
-    }
-    bb_sync();
-    for (int j = tid; j < nrhs; j += BT) {
-      T x[XNB];
-#pragma unroll
-      for (int i = 0; i < XNB; ++i) x[i] = B[(long long)(k0 + imin(i, kb - 1)) * ldb + j];
-#pragma unroll
-      for (int i = XNB - 1; i >= 0; --i)
-        if (i < kb) {
-          T v = x[i];
-#pragma unroll
-          for (int k = i + 1; k < XNB; ++k)
-            if (k < kb) v -= D[i * PNB + k] * x[k];
-          x[i] = v / D[i * PNB + i];
-        }
-#pragma unroll
-      for (int i = 0; i < XNB; ++i)
-        if (i < kb) B[(long long)(k0 + i) * ldb + j] = x[i];
-    }
-    bb_sync();
-    if (k0 > 0)
-      wg_gemm<T>(sm, k0, nrhs, kb, T(-1), U + k0, ldu, false, B + (long long)k0 * ldb, ldb, false, T(1), B, ldb);
   }
 }
 
@@ -298,96 +291,142 @@ BB_IN int wg_argmax(Smem<T>& sm, T v, int idx) {
 }
 
 // ------------------------------------------------------------- LU (GEPP)
-// P A = L U in place, piv[k] = row exchanged with k (LAPACK ipiv, 0-based).
-// Returns the first zero pivot column + 1, or 0.  nb >= 1 (the caller clamps).
+// P A = L U in place; perm_out[r] = the row of A that row r of P A is.
+// Panels of nb columns factored in LDS (pivot search by wave reductions),
+// interchanges applied to the panel rows in LDS and recorded as a composite
+// map; the rows they change in the columns outside the panel are then
+// rewritten by one gather per column, all loads in flight before the stores.
+// Trailing updates in recursive order (below).  Returns the first zero pivot
+// column + 1, or 0.  nb >= 1 (the caller clamps).
 template <typename T>
-BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* piv, int nb) {
+BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
   n = uni(n); lda = uni(lda); nb = uni(nb);
   const int tid = bb_tid();
   int info = 0;
-  for (int k0 = 0; k0 < n; k0 += nb) {
+  for (int r = tid; r < n; r += BT) sm.perm[r] = r;
+  for (int k0 = 0, t = 0; k0 < n; k0 += nb, ++t) {
     const int kb = imin(nb, n - k0), m = n - k0;
     // panel (rows k0.., columns k0..k0+kb) into LDS: P[r][c]
     T* P = sm.panel;
     for (int e = tid; e < m * kb; e += BT) {
       const int r = e / kb, c = e % kb;
-      P[r * PNB + c] = A[(long long)(k0 + r) * lda + k0 + c];
+      P[r * PP + c] = A[(long long)(k0 + r) * lda + k0 + c];
     }
+    for (int r = tid; r < m; r += BT) sm.cont[r] = r;
+    if (tid == 0) sm.tl_n = 0;
     bb_sync();
     for (int j = 0; j < kb; ++j) {
       T best = T(-1);
       int bi = INT_MAX;
       for (int r = j + tid; r < m; r += BT) {
-        const T a = std::fabs(P[r * PNB + j]);
+        const T a = std::fabs(P[r * PP + j]);
         if (a > best) { best = a; bi = r; }
       }
       const int p = wg_argmax<T>(sm, best, bi);
       const int pr = (p == INT_MAX) ? j : p;      // an all-NaN column keeps row j
-      if (tid == 0) piv[k0 + j] = k0 + pr;
-      if (pr != j)
+      if (pr != j) {
         for (int c = tid; c < kb; c += BT) {
-          const T t = P[j * PNB + c];
-          P[j * PNB + c] = P[pr * PNB + c];
-          P[pr * PNB + c] = t;
+          const T t = P[j * PP + c];
+          P[j * PP + c] = P[pr * PP + c];
+          P[pr * PP + c] = t;
         }
+        if (tid == 0) {
+          const int t1 = sm.cont[j];
+          sm.cont[j] = sm.cont[pr];
+          sm.cont[pr] = t1;
+          const int t2 = sm.perm[k0 + j];
+          sm.perm[k0 + j] = sm.perm[k0 + pr];
+          sm.perm[k0 + pr] = t2;
+        }
+      }
       bb_sync();
-      const T d = P[j * PNB + j];
+      const T d = P[j * PP + j];
       if (d == T(0)) {
         if (!info) info = k0 + j + 1;
       } else {
+        // row segments pass through registers eight columns at a time, so
+        // the LDS reads of a chunk are in flight together before its writes
         const T rd = T(1) / d;
         for (int r = j + 1 + tid; r < m; r += BT) {
-          const T l = P[r * PNB + j] * rd;
-          P[r * PNB + j] = l;
-          for (int c = j + 1; c < kb; ++c) P[r * PNB + c] -= l * P[j * PNB + c];
+          const T l = P[r * PP + j] * rd;
+          P[r * PP + j] = l;
+          for (int c0 = j + 1; c0 < kb; c0 += 8) {
+            T rv[8], pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int c = imin(c0 + u, kb - 1);
+              rv[u] = P[r * PP + c];
+              pv[u] = P[j * PP + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (c0 + u < kb) P[r * PP + c0 + u] = rv[u] - l * pv[u];
+          }
         }
       }
       bb_sync();
     }
     for (int e = tid; e < m * kb; e += BT) {
       const int r = e / kb, c = e % kb;
-      A[(long long)(k0 + r) * lda + k0 + c] = P[r * PNB + c];
+      A[(long long)(k0 + r) * lda + k0 + c] = P[r * PP + c];
     }
-    // the panel's interchanges on the columns left and right of it
+    // the panel's interchanges on the columns left and right of it: each of
+    // its kb interchanges changes at most two rows, so at most 2 kb rows move
+    for (int r = tid; r < m; r += BT)
+      if (sm.cont[r] != r) {
+        const int e = bb_atomic_add(&sm.tl_n, 1);
+        sm.tl_dst[e] = k0 + r;
+        sm.tl_src[e] = k0 + sm.cont[r];
+      }
+    bb_sync();
+    // each thread moves its own columns, staged in the (now free) panel
+    // buffer: all loads of a column are issued before any of its stores
+    const int cnt = imin(uni(sm.tl_n), 2 * PNB);
     for (int c = tid; c < n; c += BT) {
       if (c >= k0 && c < k0 + kb) continue;
-      for (int j = 0; j < kb; ++j) {
-        const int r2 = piv[k0 + j];
-        if (r2 != k0 + j) {
-          T* a1 = A + (long long)(k0 + j) * lda + c;
-          T* a2 = A + (long long)r2 * lda + c;
-          const T t = *a1;
-          *a1 = *a2;
-          *a2 = t;
-        }
-      }
+      T* S = P;   // 2 PNB rows x BT columns <= BNMAX x PP; a thread's second column reuses its slots
+      for (int e = 0; e < cnt; ++e) S[e * BT + tid] = A[(long long)sm.tl_src[e] * lda + c];
+      for (int e = 0; e < cnt; ++e) A[(long long)sm.tl_dst[e] * lda + c] = S[e * BT + tid];
     }
     bb_sync();
-    const int rest = n - k0 - kb;
-    if (rest > 0) {
-      // U12 = L11^{-1} A12, then A22 -= L21 U12
-      wg_trsm_left<T>(sm, kb, rest, A + (long long)k0 * lda + k0, lda, true, false, A + (long long)k0 * lda + k0 + kb,
-                      lda, nb);
-      wg_gemm<T>(sm, rest, rest, kb, T(-1), A + (long long)(k0 + kb) * lda + k0, lda, false,
-                 A + (long long)k0 * lda + k0 + kb, lda, false, T(1), A + (long long)(k0 + kb) * lda + k0 + kb, lda);
+    // Updates in the order of the recursive algorithm (factor the left half,
+    // update the right half, factor the right half), flattened: panel t
+    // completes a group of g = lowbit(t + 1) panels, columns [c0, c1), whose
+    // interchanges every column has already received; the next g panels'
+    // columns [c1, r1) take U12 = L11^{-1} A12 on the group's rows and
+    // A22 -= L21 U12 below them, a product of depth c1 - c0.  Columns further
+    // right wait for a larger group, so the trailing matrix is rewritten about
+    // log2(n / nb) times instead of n / nb times.
+    const int g = (t + 1) & -(t + 1);
+    const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
+    if (c1 < n) {
+      wg_trsm<T>(sm, 0, c1 - c0, r1 - c1, A + (long long)c0 * lda + c0, lda, true, A + (long long)c0 * lda + c1, lda,
+                 nb);
+      wg_gemm<T>(sm, n - c1, r1 - c1, c1 - c0, T(-1), A + (long long)c1 * lda + c0, lda, false,
+                 A + (long long)c0 * lda + c1, lda, false, T(1), A + (long long)c1 * lda + c1, lda);
     }
   }
+  for (int r = tid; r < n; r += BT) perm_out[r] = sm.perm[r];
+  bb_sync();
   return info;
 }
 
-// apply the interchanges piv[0..n) to the rows of B (n x nrhs), in order
+// dst = P src: row r of dst is row perm[r] of src (n x ncols)
 template <typename T>
-BB_IN void wg_laswp(int n, int nrhs, T* B, int ldb, const int* piv) {
-  n = uni(n); nrhs = uni(nrhs);
-  for (int c = bb_tid(); c < nrhs; c += BT)
-    for (int k = 0; k < n; ++k) {
-      const int r2 = piv[k];
-      if (r2 != k) {
-        const T t = B[(long long)k * ldb + c];
-        B[(long long)k * ldb + c] = B[(long long)r2 * ldb + c];
-        B[(long long)r2 * ldb + c] = t;
-      }
-    }
+BB_IN void wg_gather_rows(int n, int ncols, const T* src, int lds, const int* perm, T* dst, int ldd) {
+  n = uni(n); ncols = uni(ncols); lds = uni(lds); ldd = uni(ldd);
+  for (int e = bb_tid(); e < n * ncols; e += BT) {
+    const int r = e / ncols, c = e % ncols;
+    dst[(long long)r * ldd + c] = src[(long long)perm[r] * lds + c];
+  }
+  bb_sync();
+}
+
+// dst = P (n x n): row r holds its one in column perm[r]
+template <typename T>
+BB_IN void wg_perm_matrix(int n, const int* perm, T* dst) {
+  n = uni(n);
+  for (int e = bb_tid(); e < n * n; e += BT) dst[e] = perm[e / n] == e % n ? T(1) : T(0);
   bb_sync();
 }
 
@@ -400,33 +439,33 @@ BB_FN int wg_potrf(Smem<T>& sm, int n, T* A, int lda, int nb) {
   const int tid = bb_tid();
   nb = imin(uni(nb), XNB);
   int bad = 0;
-  for (int k0 = 0; k0 < n; k0 += nb) {
+  for (int k0 = 0, t = 0; k0 < n; k0 += nb, ++t) {
     const int kb = imin(nb, n - k0);
     T* D = sm.panel;
     for (int e = tid; e < kb * kb; e += BT) {
       const int i = e / kb, k = e % kb;
-      D[i * PNB + k] = (k <= i) ? A[(long long)(k0 + i) * lda + k0 + k] : T(0);
+      D[i * PP + k] = (k <= i) ? A[(long long)(k0 + i) * lda + k0 + k] : T(0);
     }
     bb_sync();
     for (int j = 0; j < kb; ++j) {
-      const T d = D[j * PNB + j];
+      const T d = D[j * PP + j];
       // a non-positive pivot is recorded and the factorization runs on (its
       // square root is NaN): the control flow never depends on the data
       if (!bad && !(d > T(0))) bad = k0 + j + 1;
       const T ljj = std::sqrt(d);
       bb_sync();
-      if (tid == 0) D[j * PNB + j] = ljj;
-      for (int i = j + 1 + tid; i < kb; i += BT) D[i * PNB + j] /= ljj;
+      if (tid == 0) D[j * PP + j] = ljj;
+      for (int i = j + 1 + tid; i < kb; i += BT) D[i * PP + j] /= ljj;
       bb_sync();
       for (int e = tid; e < kb * kb; e += BT) {
         const int i = e / kb, c = e % kb;
-        if (i > j && c > j && c <= i) D[i * PNB + c] -= D[i * PNB + j] * D[c * PNB + j];
+        if (i > j && c > j && c <= i) D[i * PP + c] -= D[i * PP + j] * D[c * PP + j];
       }
       bb_sync();
     }
     for (int e = tid; e < kb * kb; e += BT) {
       const int i = e / kb, k = e % kb;
-      if (k <= i) A[(long long)(k0 + i) * lda + k0 + k] = D[i * PNB + k];
+      if (k <= i) A[(long long)(k0 + i) * lda + k0 + k] = D[i * PP + k];
     }
     bb_sync();
     const int rest = n - k0 - kb;
@@ -442,17 +481,23 @@ BB_FN int wg_potrf(Smem<T>& sm, int n, T* A, int lda, int nb) {
           if (i < kb) {
             T v = x[i];
 #pragma unroll
-            for (int k = 0; k < i; ++k) v -= D[i * PNB + k] * x[k];
-            x[i] = v / D[i * PNB + i];
+            for (int k = 0; k < i; ++k) v -= D[i * PP + k] * x[k];
+            x[i] = v / D[i * PP + i];
           }
 #pragma unroll
         for (int i = 0; i < XNB; ++i)
           if (i < kb) row[i] = x[i];
       }
       bb_sync();
-      // A22 -= L21 L21^T (full block; the upper part is never read)
-      wg_gemm<T>(sm, rest, rest, kb, T(-1), A + (long long)(k0 + kb) * lda + k0, lda, false,
-                 A + (long long)(k0 + kb) * lda + k0, lda, true, T(1), A + (long long)(k0 + kb) * lda + k0 + kb, lda);
+      // trailing update in the order of the recursive algorithm (as in
+      // wg_getrf): the group of g = lowbit(t + 1) finished block columns
+      // [c0, c1) updates the next g block columns [c1, r1) below the
+      // diagonal, A[c1:, c1:r1] -= L[c1:, c0:c1] L[c1:r1, c0:c1]^T (the
+      // entries above the diagonal of that block are updated too and never read)
+      const int g = (t + 1) & -(t + 1);
+      const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
+      wg_gemm<T>(sm, n - c1, r1 - c1, c1 - c0, T(-1), A + (long long)c1 * lda + c0, lda, false,
+                 A + (long long)c1 * lda + c0, lda, true, T(1), A + (long long)c1 * lda + c1, lda);
     }
   }
   return bad;
@@ -527,25 +572,23 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
     T* F = slot;            // factors of A
     T* Y = slot + nn;       // A^{-1} B
     T* Cm = slot + 2 * nn;  // C and its factors
-    int* piv = reinterpret_cast<int*>(slot + 3 * nn);
+    int* perm = reinterpret_cast<int*>(slot + 3 * nn);
     int info = 0;
     if (kind == 0) {
       // Algorithm 5
       wg_copy<T>(n, A, F);
-      const int i1 = bb_first(wg_getrf<T>(sm, n, F, n, piv, nb));
+      const int i1 = bb_first(wg_getrf<T>(sm, n, F, n, perm, nb));
       info = status_word(1, i1);
-      wg_copy<T>(n, B, Y);                                              // Y = A^{-1} B
-      wg_laswp<T>(n, n, Y, n, piv);
-      wg_trsm_left<T>(sm, n, n, F, n, true, false, Y, n, nb);
-      wg_trsm_upper<T>(sm, n, n, F, n, Y, n, nb);
+      wg_gather_rows<T>(n, n, B, n, perm, Y, n);                        // Y = A^{-1} B = U^{-1} L^{-1} P B
+      wg_trsm<T>(sm, 0, n, n, F, n, true, Y, n, nb);
+      wg_trsm<T>(sm, 2, n, n, F, n, false, Y, n, nb);
       wg_copy<T>(n, A, Cm);                                             // C = A + B Y
       wg_gemm<T>(sm, n, n, n, T(1), B, n, false, Y, n, false, T(1), Cm, n);
-      const int i2 = bb_first(wg_getrf<T>(sm, n, Cm, n, piv, nb));
+      const int i2 = bb_first(wg_getrf<T>(sm, n, Cm, n, perm, nb));
       if (!info) info = status_word(2, i2);
-      wg_identity<T>(n, Xr);                                            // Re X = C^{-1}
-      wg_laswp<T>(n, n, Xr, n, piv);
-      wg_trsm_left<T>(sm, n, n, Cm, n, true, false, Xr, n, nb);
-      wg_trsm_upper<T>(sm, n, n, Cm, n, Xr, n, nb);
+      wg_perm_matrix<T>(n, perm, Xr);                                   // Re X = C^{-1} = U^{-1} L^{-1} P
+      wg_trsm<T>(sm, 0, n, n, Cm, n, true, Xr, n, nb);
+      wg_trsm<T>(sm, 2, n, n, Cm, n, false, Xr, n, nb);
       wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
     } else {
       // Algorithm 7
@@ -553,17 +596,17 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
       const int i1 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
       info = status_word(1, i1);
       wg_copy<T>(n, B, Cm);                                             // X1 = R1^{-T} B (Cm as scratch)
-      wg_trsm_left<T>(sm, n, n, F, n, false, false, Cm, n, nb);
+      wg_trsm<T>(sm, 0, n, n, F, n, false, Cm, n, nb);
       wg_copy<T>(n, Cm, Y);                                             // Y = R1^{-1} X1
-      wg_trsm_left<T>(sm, n, n, F, n, false, true, Y, n, nb);
+      wg_trsm<T>(sm, 1, n, n, F, n, false, Y, n, nb);
       // C = A - X1^T X1 into F's place (F is no longer needed)
       wg_copy<T>(n, A, F);
       wg_gemm<T>(sm, n, n, n, T(-1), Cm, n, true, Cm, n, false, T(1), F, n);
       const int i2 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
       if (!info) info = status_word(2, i2);
       wg_identity<T>(n, Xr);                                            // Re X = R2^{-1} R2^{-T}
-      wg_trsm_left<T>(sm, n, n, F, n, false, false, Xr, n, nb);
-      wg_trsm_left<T>(sm, n, n, F, n, false, true, Xr, n, nb);
+      wg_trsm<T>(sm, 0, n, n, F, n, false, Xr, n, nb);
+      wg_trsm<T>(sm, 1, n, n, F, n, false, Xr, n, nb);
       wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
     }
     if (tid == 0) g.info[mi] = info;
