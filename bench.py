@@ -133,31 +133,49 @@ def bench_adjoint(fi, inputs, h, torch, np, log):
 
 
 def bench_mp_large(fi, inputs, h, torch, np, log, n):
-    """Mixed precision at order n (8192): M = U diag(sigma) V^H (HPD: V = U)
-    with kappa in {1e2, 1e4, 1e6}, drawn on the device.  For FP64, FP32 and
-    BF16 matrix-core operands, and FP64 with an FP32 Newton-Schulz
-    correction: the error of X against V diag(1/sigma) U^H without
-    refinement, and the time, step count, residual and error with up to
-    eight Newton-Schulz steps (FP64 residual)."""
+    """Mixed precision at order n (8192): M = U diag(sigma) W (HPD:
+    U diag(sigma) U^H) with kappa in {1e2, 1e4, 1e6}, U and W built from pair
+    rotations on the device (inputs.spectrum_rotations; bit-identical to the
+    host construction the oracle inverted).  For FP64, FP32 and BF16
+    matrix-core operands, and FP64 with an FP32 Newton-Schulz correction: the
+    error against the oracle's samples (tests/golden/n<n>_rot_*_band_samples
+    .npz: one column per 64-column band, 256 rows) without refinement, and the
+    time, step count, residual and error with up to eight Newton-Schulz steps
+    (FP64 residual)."""
+    import hashlib
     out = {}
     Xr = torch.empty((n, n), dtype=torch.float64, device="cuda")
     Xi = torch.empty_like(Xr)
-
-    def relf(Rr, Ri):
-        num = torch.sum((Xr - Rr) ** 2 + (Xi - Ri) ** 2)
-        return float(torch.sqrt(num / torch.sum(Rr ** 2 + Ri ** 2)))
-
-    for kind, fn in (("general", fi.frob_inv_general), ("hpd", fi.frob_inv_hpd)):
+    for kind, fn, base in (("general", fi.frob_inv_general, 300), ("hpd", fi.frob_inv_hpd, 400)):
         for kexp in (2, 4, 6):
             log(f"[bench] mp n={n} {kind} kappa=1e{kexp}: generating")
-            dA, dB, Rr, Ri = inputs.spectrum_device(n, 10.0 ** kexp, kind=kind, seed=302 + kexp)
+            dA, dB = inputs.spectrum_rotations(n, 10.0 ** kexp, kind, seed=base + kexp, device="cuda")
+            path = os.path.join(ROOT, "tests", "golden", f"n{n}_rot_{kind}_k1e{kexp}_band_samples.npz")
+            g = np.load(path, allow_pickle=False) if os.path.exists(path) else None
+            if g is not None:
+                same = all(hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest() == str(g[k])
+                           for t, k in ((dA, "sha_a"), (dB, "sha_b")))
+                if not same:
+                    log(f"[bench] mp {kind} 1e{kexp}: device input differs from the oracle's; errors not reported")
+                    g = None
+            if g is not None:
+                rows = torch.from_numpy(g["rows"]).cuda()
+                cols = torch.from_numpy(g["cols"]).cuda()
+
+            def relf():
+                if g is None:
+                    return None
+                xr = Xr.index_select(0, rows).index_select(1, cols).cpu().numpy()
+                xi = Xi.index_select(0, rows).index_select(1, cols).cpu().numpy()
+                return float(np.sqrt(np.sum((xr - g["xr"]) ** 2 + (xi - g["xi"]) ** 2)
+                                     / np.sum(g["xr"] ** 2 + g["xi"] ** 2)))
             for pname, prec, f32c in (("f64", fi.FROB_PREC_F64, False), ("f64_f32corr", fi.FROB_PREC_F64, True),
                                       ("f32", fi.FROB_PREC_F32, False), ("bf16", fi.FROB_PREC_BF16, False)):
                 key = f"mp{n}_{kind}_k1e{kexp}_{pname}"
-                entry = {}
+                entry = {"reference": "oracle band samples" if g is not None else None}
                 try:
                     fn(h, dA, dB, Xr, Xi, prec=prec)
-                    entry["relF_unrefined"] = relf(Rr, Ri)
+                    entry["relF_unrefined"] = relf()
                     res = {}
 
                     def run():
@@ -168,12 +186,13 @@ def bench_mp_large(fi, inputs, h, torch, np, log, n):
                     run()
                     torch.cuda.synchronize()
                     entry.update({"ms_refined": (time.perf_counter() - t0) * 1e3, "refine_steps": res["refine_steps"],
-                                  "resid0": res["resid0"], "resid": res["resid"], "relF_refined": relf(Rr, Ri)})
+                                  "resid0": res["resid0"], "resid": res["resid"], "norm2_est": res["norm2_est"],
+                                  "relF_refined": relf()})
                 except fi.FrobError as e:
                     entry["status"] = str(e)
                 out[key] = entry
                 log(f"[bench] {key}: {entry}")
-            del dA, dB, Rr, Ri
+            del dA, dB
             torch.cuda.empty_cache()
     return out
 
