@@ -30,11 +30,7 @@ constexpr int BNMAX = 512;       // largest order handled in-workgroup
 constexpr int PNB = 32;          // largest LU panel width
 constexpr int PP = PNB + 1;      // LDS pitch of panel rows (odd in 8-byte words: rows fall on different banks)
 constexpr int XNB = 16;          // diagonal blocks solved by register substitution (triangular solves, Cholesky)
-constexpr int GT = 64;           // GEMM output tile
-constexpr int GP = GT + 4;       // LDS pitch of a GEMM tile row
-// GEMM k-step: 32 in FP32, 16 in FP64 (keeps the FP64 panel plus tiles under 160 KiB of LDS)
-template <typename T>
-struct GKof { static constexpr int v = sizeof(T) == 8 ? 16 : 32; };
+constexpr int GK = 16;           // GEMM k-step
 
 BB_IN int imin(int a, int b) { return a < b ? a : b; }
 BB_IN int imax(int a, int b) { return a > b ? a : b; }
@@ -58,9 +54,8 @@ struct Mfma<float> {
 
 template <typename T>
 struct Smem {
-  T ga[GKof<T>::v * GP];     // GEMM A tile, k-major
-  T gb[GKof<T>::v * GP];     // GEMM B tile, k-major
-  T panel[BNMAX * PP];       // LU panel / Cholesky diagonal block / triangular diagonal block
+  T panel[BNMAX * PP];       // LU panel / Cholesky diagonal block / triangular diagonal block;
+                             // the GEMM's double-buffered operand tiles when none of those is live
   T red_v[BT / 64];
   int red_i[BT / 64];
   int bcast[4];
@@ -80,106 +75,149 @@ BB_IN int uni(int v) { return bb_first(v); }
 BB_IN bool uni(bool v) { return bb_first((int)v) != 0; }
 
 // ---------------------------------------------------------------- GEMM
-// C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K (A stored K x M if ta)
-template <typename T>
-BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B, int ldb,
-                   bool tb, T beta, T* C, int ldc) {
-  M = uni(M); N = uni(N); K = uni(K); lda = uni(lda); ldb = uni(ldb); ldc = uni(ldc); ta = uni(ta); tb = uni(tb);
+// C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K (A stored K x M if ta).
+// Output tiles of TM x TN = (WM * BA * 16) x (WN * BB * 16): 4 waves in a
+// WM x WN grid, each owning BA x BB blocks of 16 x 16 (16x16x4 matrix-core
+// products).  Operand tiles are staged k-major in LDS, double-buffered in the
+// panel buffer (the callers hold nothing live there during a product): the
+// next k-step's global loads are in flight during the current products and
+// one barrier separates the k-steps.  Edges: loads at clamped in-range
+// addresses, values outside the matrix zeroed when staged.
+template <typename T, int WM, int WN, int BA, int BB>
+BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B,
+                         int ldb, bool tb, T beta, T* C, int ldc) {
   typedef typename Mfma<T>::acc acc_t;
-  constexpr int GK = GKof<T>::v;
+  constexpr int TM = WM * BA * 16, TN = WN * BB * 16;
+  constexpr int PA = TM + 4, PB = TN + 4;          // LDS pitches of the k-major tiles
+  constexpr int BUF = GK * (PA + PB);              // one stage: A tile then B tile
+  static_assert(2 * BUF <= BNMAX * PP, "GEMM stages exceed the panel buffer");
+  constexpr int EA = (TM * GK + BT - 1) / BT, EB = (TN * GK + BT - 1) / BT;
   const int tid = bb_tid(), lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int tilesN = (N + GT - 1) / GT;
-  const int tiles = ((M + GT - 1) / GT) * tilesN;
-  constexpr int E = GT * GK / BT;   // elements per thread per operand tile
+  const int wm = (wave / WN) * (BA * 16), wn = (wave % WN) * (BB * 16);
+  const int tilesN = (N + TN - 1) / TN;
+  const int tiles = ((M + TM - 1) / TM) * tilesN;
+  const int nk = (K + GK - 1) / GK;
+  T* lds = sm.panel;
   for (int t = 0; t < tiles; ++t) {
-    const int tm = (t / tilesN) * GT, tn = (t % tilesN) * GT;
-    acc_t acc[2][2];
+    const int tm = (t / tilesN) * TM, tn = (t % tilesN) * TN;
+    acc_t acc[BA][BB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    T ra[E], rb[E];
+      for (int b = 0; b < BB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    T ra[EA], rb[EB];
     auto load = [&](int k0) {
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
-        const int e = tid + BT * u;
+      for (int u = 0; u < EA; ++u) {
+        const int e = imin(tid + BT * u, TM * GK - 1);
         int i, k;
-        if (!ta) { i = e / GK; k = e % GK; } else { k = e / GT; i = e % GT; }
+        if (!ta) { i = e / GK; k = e % GK; } else { k = e / TM; i = e % TM; }
         const int gi = imin(tm + i, M - 1), gk = imin(k0 + k, K - 1);
         ra[u] = ta ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk];
       }
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
-        const int e = tid + BT * u;
+      for (int u = 0; u < EB; ++u) {
+        const int e = imin(tid + BT * u, TN * GK - 1);
         int k, j;
-        if (!tb) { k = e / GT; j = e % GT; } else { j = e / GK; k = e % GK; }
+        if (!tb) { k = e / TN; j = e % TN; } else { j = e / GK; k = e % GK; }
         const int gk = imin(k0 + k, K - 1), gj = imin(tn + j, N - 1);
         rb[u] = tb ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj];
       }
     };
-    auto store = [&](int k0) {
+    auto store = [&](int k0, T* st) {
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
+      for (int u = 0; u < EA; ++u) {
         const int e = tid + BT * u;
-        int i, k;
-        if (!ta) { i = e / GK; k = e % GK; } else { k = e / GT; i = e % GT; }
-        sm.ga[k * GP + i] = (tm + i < M && k0 + k < K) ? ra[u] : T(0);
+        if (e < TM * GK) {
+          int i, k;
+          if (!ta) { i = e / GK; k = e % GK; } else { k = e / TM; i = e % TM; }
+          st[k * PA + i] = (tm + i < M && k0 + k < K) ? ra[u] : T(0);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
+      for (int u = 0; u < EB; ++u) {
         const int e = tid + BT * u;
-        int k, j;
-        if (!tb) { k = e / GT; j = e % GT; } else { j = e / GK; k = e % GK; }
-        sm.gb[k * GP + j] = (tn + j < N && k0 + k < K) ? rb[u] : T(0);
+        if (e < TN * GK) {
+          int k, j;
+          if (!tb) { k = e / TN; j = e % TN; } else { j = e / GK; k = e % GK; }
+          st[GK * PA + k * PB + j] = (tn + j < N && k0 + k < K) ? rb[u] : T(0);
+        }
       }
     };
-    const int nk = (K + GK - 1) / GK;
-    if (nk > 0) load(0);
+    if (nk > 0) {
+      load(0);
+      store(0, lds);
+    }
+    bb_sync();
     for (int it = 0; it < nk; ++it) {
-      store(it * GK);
-      bb_sync();
       if (it + 1 < nk) load((it + 1) * GK);
+      const T* sa = lds + (it & 1) * BUF;
+      const T* sb = sa + GK * PA;
 #pragma unroll
       for (int kk = 0; kk < GK; kk += 4) {
-        T fa[2], fb[2];
+        T fa[BA], fb[BB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) fa[a] = sm.ga[(kk + (lane >> 4)) * GP + wm + 16 * a + (lane & 15)];
+        for (int a = 0; a < BA; ++a) fa[a] = sa[(kk + (lane >> 4)) * PA + wm + 16 * a + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) fb[b] = sm.gb[(kk + (lane >> 4)) * GP + wn + 16 * b + (lane & 15)];
+        for (int b = 0; b < BB; ++b) fb[b] = sb[(kk + (lane >> 4)) * PB + wn + 16 * b + (lane & 15)];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < BA; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(fa[a], fb[b], acc[a][b]);
+          for (int b = 0; b < BB; ++b) acc[a][b] = Mfma<T>::op(fa[a], fb[b], acc[a][b]);
       }
+      if (it + 1 < nk) store((it + 1) * GK, lds + ((it + 1) & 1) * BUF);
       bb_sync();
     }
-    // epilogue: all reads of C are issued before any write (one round trip
-    // to memory per tile instead of one per element)
-    T cv[2][4][2];
+    // epilogue, one block row at a time: its reads of C are all issued
+    // before its writes
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BA; ++a) {
+      T cv[4][BB];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BB; ++b) {
           const int i = imin(tm + wm + 16 * a + Mfma<T>::row(lane, v), M - 1);
           const int j = imin(tn + wn + 16 * b + (lane & 15), N - 1);
-          cv[a][v][b] = beta != T(0) ? C[(long long)i * ldc + j] : T(0);
+          cv[v][b] = beta != T(0) ? C[(long long)i * ldc + j] : T(0);
         }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = tm + wm + 16 * a + Mfma<T>::row(lane, v);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BB; ++b) {
           const int j = tn + wn + 16 * b + (lane & 15);
-          if (i < M && j < N) C[(long long)i * ldc + j] = alpha * acc[a][b][v] + beta * cv[a][v][b];
+          if (i < M && j < N) C[(long long)i * ldc + j] = alpha * acc[a][b][v] + beta * cv[v][b];
         }
       }
+    }
   }
   bb_sync();
+}
+
+// The tile shape follows the product's shape: square tiles for full
+// products, wide ones for the short updates of the triangular solves, tall
+// ones for the narrow column updates of the factorizations.
+template <typename T>
+BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B, int ldb,
+                   bool tb, T beta, T* C, int ldc) {
+  M = uni(M); N = uni(N); K = uni(K); lda = uni(lda); ldb = uni(ldb); ldc = uni(ldc); ta = uni(ta); tb = uni(tb);
+  if (M <= 0 || N <= 0) {
+    bb_sync();
+    return;
+  }
+  if (M <= 16 && N > 64)
+    wg_gemm_tiles<T, 1, 4, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 16 x 256
+  else if (M <= 32 && N > 64)
+    wg_gemm_tiles<T, 2, 2, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 32 x 128
+  else if (N <= 16 && M > 64)
+    wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 256 x 16
+  else if (N <= 32 && M > 64)
+    wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 32
+  else if (M > 64 && N > 64)
+    wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 128
+  else
+    wg_gemm_tiles<T, 2, 2, 2, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 64 x 64
 }
 
 // ------------------------------------------------------- triangular solves
