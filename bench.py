@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-mp-large", action="store_true", help="skip the n = 8192 mixed-precision leg")
     ap.add_argument("--mp-n", type=int, default=8192)
     ap.add_argument("--no-large", action="store_true", help="skip the n = 8192 Frobenius / complex-LU comparison")
+    ap.add_argument("--no-newton", action="store_true", help="skip the sign / polar / Sylvester legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -129,6 +130,54 @@ def bench_adjoint(fi, inputs, h, torch, np, log):
                                  "backward_tflops_3m": 12.0 * b * n ** 3 / ms / 1e9}
         log(f"[bench] adjoint {tag}: forward {fwd_ms:.2f} ms, backward {ms:.3f} ms")
         del As, Bs, plan, Xr, Xi, Gr, Gi, dMr, dMi
+    return out
+
+
+def bench_newton(fi, inputs, h, torch, np, log, sizes=(2100, 4000)):
+    """The paper's Section 5 workloads at its smallest and largest orders:
+    matrix sign (n, tol 1e-3), polar decomposition (n, tol 1e-3) and the
+    Sylvester equation (p = q = n / 2, tol 1e-1), each with every inverse by
+    Frobenius inversion and by the complex-LU baseline (the comparison the
+    paper makes), synthetic inputs of the paper's recipes; time per solve
+    (one warm-up), Newton steps, and the relative max-norm error against the
+    constructed solution."""
+    out = {}
+
+    def relmax(Xr, Xi, R):
+        xr, xi = Xr.cpu().numpy(), Xi.cpu().numpy()
+        return float(max(np.abs(xr - R.real).max(), np.abs(xi - R.imag).max()) / np.abs(R).max())
+
+    def timed_call(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    for n in sizes:
+        log(f"[bench] newton workloads n={n}: generating")
+        Xr, Xi, Sr, Si = inputs.sign_problem(n, seed=50)
+        dXr, dXi = torch.from_numpy(Xr).cuda(), torch.from_numpy(Xi).cuda()
+        X, Q, P = inputs.polar_problem(n, seed=52)
+        dPr, dPi = torch.from_numpy(np.ascontiguousarray(X.real)).cuda(), torch.from_numpy(np.ascontiguousarray(X.imag)).cuda()
+        p = n // 2
+        A, B, C, Y = inputs.sylvester_problem(p, p, seed=51)
+        dev = [torch.from_numpy(np.ascontiguousarray(f(M))).cuda() for M in (A, B, C) for f in (np.real, np.imag)]
+        for tag, inv in (("frobenius", fi.FROB_NEWTON_FROBENIUS), ("complex_lu", fi.FROB_NEWTON_COMPLEX_LU)):
+            ms, r = timed_call(lambda: fi.frob_sign(h, dXr, dXi, tol=1e-3, inverse=inv))
+            out[f"newton_sign_n{n}_{tag}"] = {"ms": ms, "steps": r[2]["iterations"],
+                                             "relmax_vs_closed_form": relmax(r[0], r[1], Sr + 1j * Si)}
+            ms, r = timed_call(lambda: fi.frob_polar(h, dPr, dPi, tol=1e-3, inverse=inv))
+            out[f"newton_polar_n{n}_{tag}"] = {"ms": ms, "steps": r[4]["iterations"],
+                                              "relmax_Q": relmax(r[0], r[1], Q), "relmax_P": relmax(r[2], r[3], P)}
+            ms, r = timed_call(lambda: fi.frob_sylvester(h, *dev, tol=1e-1, inverse=inv))
+            out[f"newton_sylvester_p{p}_q{p}_{tag}"] = {"ms": ms, "steps": r[2]["iterations"],
+                                                       "relmax_vs_constructed": relmax(r[0], r[1], Y)}
+            for k in (f"newton_sign_n{n}_{tag}", f"newton_polar_n{n}_{tag}", f"newton_sylvester_p{p}_q{p}_{tag}"):
+                log(f"[bench] {k}: {out[k]}")
+        del dXr, dXi, dPr, dPi, dev
+        torch.cuda.empty_cache()
     return out
 
 
@@ -412,6 +461,8 @@ def main():
         del dAh, dBh
         extra.update(bench_batched(fi, inputs, h, torch, np, log))
         extra.update(bench_adjoint(fi, inputs, h, torch, np, log))
+        if not args.no_newton:
+            extra.update(bench_newton(fi, inputs, h, torch, np, log))
         if not args.no_mp_large or not args.no_large:
             del Xr, Xi
             torch.cuda.empty_cache()

@@ -249,10 +249,18 @@ frob_status_t frob_inv_tower(frob_handle_t handle, int m, int n, const double *t
  * stop when ||X_k - X_{k-1}||_max / ||X_k||_max <= tol, with the max norm of
  * eq. (maxnorm) (the largest |entry| over both parts), or after max_iter
  * steps. */
+/* Which inversion every Newton step uses: Frobenius inversion (Algorithm 5,
+ * frob_inv_general) or the complex-LU baseline (Algorithm 4, frob_cinv_lu in
+ * its getri form), the two the paper compares in Section 5. */
+#define FROB_NEWTON_FROBENIUS 0
+#define FROB_NEWTON_COMPLEX_LU 1
+
 typedef struct {
   double tol;           /* <= 0: 1e-3 (the paper's choice for sign and polar)                                */
   int max_iter;         /* <= 0: 100                                                                      */
-  frob_opts_t inv;      /* options of every inversion (shift, precision, refinement); zeroed = defaults     */
+  frob_opts_t inv;      /* options of every Frobenius inversion (shift, precision, refinement); zeroed =   */
+                        /* defaults; unused by the complex-LU baseline                                     */
+  int inverse;          /* FROB_NEWTON_FROBENIUS (0) or FROB_NEWTON_COMPLEX_LU; other values: FROB_E_ARG   */
 } frob_newton_opts_t;
 
 typedef struct {

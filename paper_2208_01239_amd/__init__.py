@@ -15,7 +15,8 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32_CORRECTION,  # noqa: F401
+from ._lib import (FROB_NEWTON_COMPLEX_LU, FROB_NEWTON_FROBENIUS,  # noqa: F401
+                   FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32_CORRECTION,
                    FROB_REFINE_SKIP_FINAL_RESID, FROB_REPORT_COND, FROB_SHIFT_COND, FROB_SHIFT_PHASE,
                    FROB_SHIFT_AUTO, FROB_SHIFT_OFF, FROB_SHIFT_ON, FrobError, FrobNoConvergenceError, FrobNotHPDError, FrobSingularError,
                    frob_opts_t, frob_result_t)
@@ -23,7 +24,7 @@ from ._lib import (FROB_PREC_BF16, FROB_PREC_F32, FROB_PREC_F64, FROB_REFINE_F32
 __all__ = ["Handle", "frob_inv_general", "frob_inv_hpd", "frob_solve", "frob_refine", "frob_cinv_lu", "frob_cinv_chol",
            "frob_inv_adjoint", "frob_inv_batched", "frob_batched_tune", "BatchedPlan",
            "FrobError", "FrobSingularError", "FrobNotHPDError", "FrobNoConvergenceError", "FROB_SHIFT_OFF",
-           "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
+           "FROB_SHIFT_AUTO", "FROB_SHIFT_ON", "FROB_NEWTON_FROBENIUS", "FROB_NEWTON_COMPLEX_LU", "FROB_PREC_F64", "FROB_PREC_F32", "FROB_PREC_BF16",
            "FROB_REFINE_SKIP_FINAL_RESID", "FROB_REFINE_F32_CORRECTION", "load_library", "frob_sign", "frob_polar",
            "frob_sylvester", "frob_lyapunov", "frob_inv_spd_pair", "frob_inv_tower"]
 
@@ -379,10 +380,13 @@ def frob_batched_tune(h: Handle, storage=FROB_PREC_F64):
 
 # ----------------------------------------------------------------- Newton iterations (Section 5)
 def _newton_opts(tol, max_iter, **inv):
+    """Options of a Newton driver; inverse=FROB_NEWTON_COMPLEX_LU takes every
+    inverse from the complex-LU baseline instead of Frobenius inversion."""
     o = _lib.frob_newton_opts_t()
     _lib.load().frob_default_newton_opts(ctypes.byref(o))
     o.tol = float(tol)
     o.max_iter = int(max_iter)
+    o.inverse = int(inv.pop("inverse", FROB_NEWTON_FROBENIUS))
     o.inv = _opts(inv.get("shift", FROB_SHIFT_AUTO), inv.get("mu", 0.0), inv.get("seed", 0), inv.get("refine", 0),
                   inv.get("prec", FROB_PREC_F64), inv.get("refine_tol", 0.0), inv.get("final_resid", True),
                   inv.get("f32_correction", False))

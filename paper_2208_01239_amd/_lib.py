@@ -24,6 +24,8 @@ FROB_E_HIP = -3
 FROB_E_INTERNAL = -4
 FROB_E_CAPTURE = -5
 
+FROB_NEWTON_FROBENIUS = 0
+FROB_NEWTON_COMPLEX_LU = 1
 FROB_SHIFT_OFF = 0
 FROB_SHIFT_AUTO = 1
 FROB_SHIFT_ON = 2
@@ -58,7 +60,7 @@ class frob_result_t(ctypes.Structure):
 
 
 class frob_newton_opts_t(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("inv", frob_opts_t)]
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("inv", frob_opts_t), ("inverse", ctypes.c_int)]
 
 
 class frob_newton_result_t(ctypes.Structure):

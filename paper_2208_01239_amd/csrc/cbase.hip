@@ -45,6 +45,15 @@ frob_status_t zguarded(frob_handle_t h, F&& f) {
 
 }  // namespace
 
+size_t frob::cinv_lu_ws(int n) {
+  const size_t nn = (size_t)n * n;
+  Carve sz(nullptr);
+  for (int k = 0; k < 4; ++k) sz.take<double>(nn);
+  sz.take<int>(n);
+  sz.take<double>(zsolver_work_elems(n));
+  return sz.off + 256;
+}
+
 extern "C" {
 
 frob_status_t frob_cinv_lu(frob_handle_t h, int n, const double* Mr, const double* Mi, int ldm, double* Xr,
@@ -54,11 +63,10 @@ frob_status_t frob_cinv_lu(frob_handle_t h, int n, const double* Mr, const doubl
   return zguarded(h, [&]() -> frob_status_t {
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
-    Carve sz(nullptr);
-    for (int k = 0; k < 4; ++k) sz.take<double>(nn);
-    sz.take<int>(n);
-    sz.take<double>(zsolver_work_elems(n));
-    Carve c((char*)ws_reserve(h, sz.off));
+    // behind whatever an enclosing call (a Newton driver) keeps at the front
+    const size_t lead = ws_lead();
+    Carve c((char*)ws_reserve(h, lead + cinv_lu_ws(n)));
+    c.off = lead;
     double* Fr = c.take<double>(nn);
     double* Fi = c.take<double>(nn);
     double* Wr = c.take<double>(nn);

@@ -822,6 +822,12 @@ void frob_default_newton_opts(frob_newton_opts_t* o) {
 
 namespace {
 
+// workspace of one inversion of the iteration, beyond the iterate's
+size_t newton_inv_ws(int n, const frob_newton_opts_t& o) {
+  return o.inverse == FROB_NEWTON_COMPLEX_LU ? cinv_lu_ws(n)
+                                             : general_ws(n, o.inv.refine, o.inv.shift == FROB_SHIFT_COND);
+}
+
 frob_newton_opts_t newton_opts_or_default(const frob_newton_opts_t* o) {
   frob_newton_opts_t d;
   frob_default_newton_opts(&d);
@@ -836,7 +842,8 @@ frob_newton_opts_t newton_opts_or_default(const frob_newton_opts_t* o) {
 }
 
 // The iteration X <- (X + op(X^{-1})) / 2 on X (n x n, ld n, at the front of
-// the workspace), each inverse by frob_inv_general into I (ld n).  `lead` is
+// the workspace), each inverse by frob_inv_general (or the complex-LU
+// baseline) into I (ld n).  `lead` is
 // the size of the region holding X, I and the two max-norm words.
 frob_status_t newton_iterate(frob_handle* h, int n, double* Xr, double* Xi, double* Ir, double* Ii,
                              unsigned long long* maxes, size_t lead, bool herm, const frob_newton_opts_t& o,
@@ -848,7 +855,8 @@ frob_status_t newton_iterate(frob_handle* h, int n, double* Xr, double* Xi, doub
   for (int k = 0; k < o.max_iter; ++k) {
     {
       LeadScope ls(lead);
-      st = frob_inv_general(h, n, Xr, n, Xi, n, Ir, Ii, n, &o.inv, &r.inv);
+      st = o.inverse == FROB_NEWTON_COMPLEX_LU ? frob_cinv_lu(h, n, Xr, Xi, n, Ir, Ii, n, 1, &r.inv)
+                                               : frob_inv_general(h, n, Xr, n, Xi, n, Ir, Ii, n, &o.inv, &r.inv);
     }
     if (st != FROB_OK && st != FROB_NO_CONVERGENCE) break;
     st = FROB_OK;
@@ -872,11 +880,12 @@ frob_status_t frob_sign(frob_handle_t h, int n, const double* Xr, const double* 
                         int lds, const frob_newton_opts_t* opts, frob_newton_result_t* res) {
   if (!h || !Xr || !Xi || !Sr || !Si || bad_dims(n, ldx) || lds < n) return FROB_E_ARG;
   const frob_newton_opts_t o = newton_opts_or_default(opts);
+  if (o.inverse != FROB_NEWTON_FROBENIUS && o.inverse != FROB_NEWTON_COMPLEX_LU) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const size_t lead = 4 * lead_of(nn) + 256;
-    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
+    char* base = (char*)ws_reserve(h, lead + 256 + newton_inv_ws(n, o));
     double* Wr = (double*)base;
     double* Wi = (double*)(base + lead_of(nn));
     double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -899,11 +908,12 @@ frob_status_t frob_polar(frob_handle_t h, int n, const double* Xr, const double*
                          frob_newton_result_t* res) {
   if (!h || !Xr || !Xi || !Qr || !Qi || !Pr || !Pi || bad_dims(n, ldx) || ldq < n || ldp < n) return FROB_E_ARG;
   const frob_newton_opts_t o = newton_opts_or_default(opts);
+  if (o.inverse != FROB_NEWTON_FROBENIUS && o.inverse != FROB_NEWTON_COMPLEX_LU) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
     const size_t lead = 4 * lead_of(nn) + 256;
-    char* base = (char*)ws_reserve(h, lead + 256 + general_ws(n, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
+    char* base = (char*)ws_reserve(h, lead + 256 + newton_inv_ws(n, o));
     double* Wr = (double*)base;
     double* Wi = (double*)(base + lead_of(nn));
     double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -934,7 +944,7 @@ frob_status_t sylvester_impl(frob_handle* h, int p, int q, const double* Ar, con
   const int N = p + q;
   const size_t nn = (size_t)N * N;
   const size_t lead = 4 * lead_of(nn) + 256;
-  char* base = (char*)ws_reserve(h, lead + 256 + general_ws(N, o.inv.refine, o.inv.shift == FROB_SHIFT_COND));
+  char* base = (char*)ws_reserve(h, lead + 256 + newton_inv_ws(N, o));
   double* Wr = (double*)base;
   double* Wi = (double*)(base + lead_of(nn));
   double* Ir = (double*)(base + 2 * lead_of(nn));
@@ -959,6 +969,7 @@ frob_status_t frob_sylvester(frob_handle_t h, int p, int q, const double* Ar, co
       lda < p || ldb < q || ldc < q || ldy < q)
     return FROB_E_ARG;
   const frob_newton_opts_t o = newton_opts_or_default(opts);
+  if (o.inverse != FROB_NEWTON_FROBENIUS && o.inverse != FROB_NEWTON_COMPLEX_LU) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     return sylvester_impl(h, p, q, Ar, Ai, lda, Br, Bi, ldb, false, Cr, Ci, ldc, Yr, Yi, ldy, o, res);
   });
@@ -970,6 +981,7 @@ frob_status_t frob_lyapunov(frob_handle_t h, int p, const double* Ar, const doub
   if (!h || !Ar || !Ai || !Cr || !Ci || !Yr || !Yi || p < 1 || 2 * p > FROB_MAX_N || lda < p || ldc < p || ldy < p)
     return FROB_E_ARG;
   const frob_newton_opts_t o = newton_opts_or_default(opts);
+  if (o.inverse != FROB_NEWTON_FROBENIUS && o.inverse != FROB_NEWTON_COMPLEX_LU) return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
     return sylvester_impl(h, p, p, Ar, Ai, lda, Ar, Ai, lda, true, Cr, Ci, ldc, Yr, Yi, ldy, o, res);
   });
@@ -1122,3 +1134,7 @@ const char* frob_status_string(frob_status_t s) {
 }
 
 }  // extern "C"
+
+// Bytes an enclosing call keeps ahead of the workspace on this thread (used
+// by the complex baselines when a Newton driver calls them).
+size_t frob::ws_lead() { return t_lead_bytes; }

@@ -82,6 +82,10 @@ struct CaptureGrowth {};
 
 uint64_t splitmix64(uint64_t& x);
 double draw_mu(frob_handle* h);
+// Bytes an enclosing call keeps at the front of the workspace (0 outside one).
+size_t ws_lead();
+// Workspace bytes of frob_cinv_lu at order n.
+size_t cinv_lu_ws(int n);
 // The handle's workspace, grown to at least `bytes`.  Growth while the
 // handle's stream is being captured throws CaptureGrowth (nothing is freed or
 // allocated then); a workspace that a captured launch references is retired,

@@ -132,3 +132,58 @@ def test_autograd_loss_gradient(h):
         Rr, Ri = oracle.adjoint(Xor, Xoi, ws[b][0].T.copy(), -ws[b][1].T.copy())
         e = relF(A.grad[b].cpu().numpy(), B.grad[b].cpu().numpy(), Rr, Ri)
         assert e <= 1e-10, (b, e)
+
+
+def test_autograd_forward_batched_precisions(h):
+    """The forward pass runs as one batched launch in the batch's precision:
+    an FP32 HPD batch (Algorithm 7) matches the oracle to the FP32 bound
+    16 u32 kappa_2(C), FP64 general members (Algorithm 5) to 1e-12; the
+    backward pass stays in the same precision (FP32 gradient within 1e-4 of
+    the oracle's: twice the forward error, about 1e-6 here, through the two
+    products, plus 8 n u32 = 3e-5 for their rounding)."""
+    import torch
+    from paper_2208_01239_amd import inputs
+    from paper_2208_01239_amd.autograd import frobenius_inverse
+    mats, ws = inputs.adjoint_batch(count=4, n=64, seed=9)
+    A = torch.from_numpy(np.stack([m[0] for m in mats])).float().cuda().requires_grad_(True)
+    B = torch.from_numpy(np.stack([m[1] for m in mats])).float().cuda().requires_grad_(True)
+    Xr, Xi = frobenius_inverse(A, B, h, hpd=True)
+    assert Xr.dtype == torch.float32
+    U32 = 2.0 ** -24
+    for b in range(4):
+        a64, b64 = (m.astype(np.float32).astype(np.float64) for m in mats[b])
+        Ror, Roi = oracle.cinv_chol(a64, b64)[:2]
+        kC = np.linalg.cond(a64 + b64 @ np.linalg.solve(a64, b64))
+        assert relF(Xr[b].detach().cpu().numpy(), Xi[b].detach().cpu().numpy(), Ror, Roi) <= 16 * U32 * kC
+    Wr = torch.from_numpy(np.stack([w[0] for w in ws])).float().cuda()
+    Wi = torch.from_numpy(np.stack([w[1] for w in ws])).float().cuda()
+    L = (Wr * Xr.transpose(1, 2)).sum() - (Wi * Xi.transpose(1, 2)).sum()
+    L.backward()
+    assert A.grad.dtype == torch.float32
+    for b in range(4):
+        a64, b64 = (m.astype(np.float32).astype(np.float64) for m in mats[b])
+        Xor, Xoi = oracle.cinv_chol(a64, b64)[:2]
+        Rr, Ri = oracle.adjoint(Xor, Xoi, ws[b][0].astype(np.float32).T.astype(np.float64).copy(),
+                                -ws[b][1].astype(np.float32).T.astype(np.float64).copy())
+        assert relF(A.grad[b].cpu().numpy(), B.grad[b].cpu().numpy(), Rr, Ri) <= 1e-4
+    G = [inputs.general(40, 900 + b) for b in range(3)]
+    Ag = torch.from_numpy(np.stack([g[0] for g in G])).cuda()
+    Bg = torch.from_numpy(np.stack([g[1] for g in G])).cuda()
+    Xr, Xi = frobenius_inverse(Ag, Bg, h)
+    for b in range(3):
+        Ror, Roi = oracle.cinv_lu(*G[b])[:2]
+        assert relF(Xr[b].cpu().numpy(), Xi[b].cpu().numpy(), Ror, Roi) <= 1e-12
+
+
+def test_autograd_forward_reports_failing_member(h):
+    """A member with a singular real part (the batched path has no shift)
+    raises, naming the member and the stage."""
+    import torch
+    import paper_2208_01239_amd as fi
+    from paper_2208_01239_amd.autograd import frobenius_inverse
+    A = torch.eye(3, dtype=torch.float64).repeat(2, 1, 1).cuda()
+    B = torch.zeros_like(A)
+    A[1, 0, 0] = 0.0
+    B[1, 0, 0] = 1.0      # member 1 is diag(i, 1, 1): invertible, but its real part is singular
+    with pytest.raises(fi.FrobSingularError, match="member 1, stage 1"):
+        frobenius_inverse(A, B, h)

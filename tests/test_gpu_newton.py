@@ -113,3 +113,35 @@ def test_newton_reports_singular_step(h):
     X = np.diag([1.0, 0.0, -2.0])
     with pytest.raises(fi.FrobSingularError):
         fi.frob_sign(h, to_dev(X), to_dev(np.zeros((3, 3))), tol=EPS)
+
+
+@pytest.mark.parametrize("n", [65, 1100])
+def test_newton_with_complex_lu_inverses(h, n):
+    """The comparison of Section 5: the same iterations with every inverse
+    from the complex-LU baseline (Algorithm 4) instead of Frobenius inversion
+    reach the same sign and polar factor (the oracle's iteration, and the
+    closed forms) in the same number of steps; the iterate lives ahead of the
+    baseline's workspace, so the two share the handle's workspace."""
+    import paper_2208_01239_amd as fi
+    Xr, Xi, Sr, Si = inputs.sign_problem(n, seed=600 + n)
+    Gr, Gi, res = fi.frob_sign(h, to_dev(Xr), to_dev(Xi), tol=EPS, max_iter=KMAX, inverse=fi.FROB_NEWTON_COMPLEX_LU)
+    Fr, Fi, resf = fi.frob_sign(h, to_dev(Xr), to_dev(Xi), tol=EPS, max_iter=KMAX)
+    Or, Oi, info, it = oracle.sign_newton(Xr, Xi, eps=EPS, kmax=KMAX)
+    assert info == 0
+    gr, gi = to_host(Gr), to_host(Gi)
+    print(f"sign n={n} with complex-LU inverses: {res['iterations']} steps (Frobenius {resf['iterations']}, "
+          f"oracle {it}), vs oracle {relmax(gr, gi, Or, Oi):.2e}, vs Frobenius "
+          f"{relmax(gr, gi, to_host(Fr), to_host(Fi)):.2e}")
+    assert relmax(gr, gi, Or, Oi) <= 1e-8 and relmax(gr, gi, Sr, Si) <= 1e-8
+    X, Q, P = inputs.polar_problem(n, seed=700 + n)
+    Qr, Qi, Pr, Pi, res = fi.frob_polar(h, to_dev(X.real), to_dev(X.imag), tol=EPS, max_iter=KMAX,
+                                        inverse=fi.FROB_NEWTON_COMPLEX_LU)
+    assert relmax(to_host(Qr), to_host(Qi), Q.real, Q.imag) <= 1e-8
+    assert relmax(to_host(Pr), to_host(Pi), P.real, P.imag) <= 1e-8
+
+
+def test_newton_rejects_unknown_inverse(h):
+    import paper_2208_01239_amd as fi
+    Xr, Xi, _, _ = inputs.sign_problem(8, seed=1)
+    with pytest.raises(fi.FrobError, match="FROB_E_ARG"):
+        fi.frob_sign(h, to_dev(Xr), to_dev(Xi), inverse=7)
