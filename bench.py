@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--mp-n", type=int, default=8192)
     ap.add_argument("--no-large", action="store_true", help="skip the n = 8192 Frobenius / complex-LU comparison")
     ap.add_argument("--no-newton", action="store_true", help="skip the sign / polar / Sylvester legs")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 2048-matrix batched leg with the default panel widths (for kernel profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -77,14 +79,17 @@ def _events_ms(torch, fn, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_batched(fi, inputs, h, torch, np, log):
-    """2048 matrices, n ~ U{16..512} (seed 4), kind = i mod 2: one persistent launch."""
+def bench_batched(fi, inputs, h, torch, np, log, tune=True, loop=True):
+    """2048 matrices, n ~ U{16..512} (seed 4), kind = i mod 2: one persistent
+    launch (panel widths autotuned first unless tune=False, then the default
+    table), and a per-matrix complex-LU / complex-Cholesky loop on a sample."""
     log("[bench] batched: generating 2048 matrices")
     ns, kinds, mats = inputs.batch(count=2048, seed=4)
     flops = float(np.sum(np.where(kinds == 0, 26.0 / 3.0, 19.0 / 3.0) * ns.astype(np.float64) ** 3))
     out = {}
-    fi.frob_batched_tune(h, fi.FROB_PREC_F64)
-    fi.frob_batched_tune(h, fi.FROB_PREC_F32)
+    if tune:
+        fi.frob_batched_tune(h, fi.FROB_PREC_F64)
+        fi.frob_batched_tune(h, fi.FROB_PREC_F32)
     for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
         As = [torch.from_numpy(A).to(dt).cuda() for A, _ in mats]
         Bs = [torch.from_numpy(B).to(dt).cuda() for _, B in mats]
@@ -95,6 +100,8 @@ def bench_batched(fi, inputs, h, torch, np, log):
                                  "nonzero_info": bad}
         log(f"[bench] batched {tag}: {ms:.2f} ms")
         del As, Bs, plan
+    if not loop:
+        return out
     # baseline: per-matrix complex-LU / complex-Cholesky loop on a sample, scaled to the batch
     idx = np.arange(0, 2048, 32)
     Ms = [(torch.from_numpy(mats[i][0]).cuda(), torch.from_numpy(mats[i][1]).cuda()) for i in idx]
@@ -327,6 +334,11 @@ def main():
 
     import paper_2208_01239_amd as fi
     from paper_2208_01239_amd import inputs
+
+    if args.batched_only:
+        h = fi.Handle(0)
+        print(json.dumps(bench_batched(fi, inputs, h, torch, np, log, tune=False, loop=False)), flush=True)
+        return
 
     n, K, W = args.n, args.steps, args.warmup
     torch.cuda.set_device(0)
