@@ -585,13 +585,23 @@ frob_status_t chol_path(frob_handle* h, int n, const double* A, int lda, const d
     gemm_f64(s, true, false, n, n, n, 1.0, DOp{Wm, ld, nullptr}, TRI_UPPER, DOp{Wm, ld, nullptr}, TRI_LOWER, 0.0,
              DOut{Xr, ldx, nullptr, nullptr}, true);
     mirror_lower_f64(s, n, Xr, ldx, 1.0);
-    // step 9: Im X = -Y C^{-1}
+    // step 9: Im X = -Y C^{-1}.  The inverse of an HPD M is Hermitian (Im X
+    // skew) and that of a complex symmetric M symmetric, so without
+    // refinement only the lower triangle is formed and mirrored with the
+    // matching sign (half the product).  The mirrored half carries the same
+    // forward error, but it no longer matches the factors the way the
+    // computed product does: the residual I - M X grows by about kappa(M)
+    // times that error, so a refined call (which starts from that residual)
+    // forms the whole product.
     if (la) FROB_HIP(hipStreamWaitEvent(s, la->ev[4], 0));
+    const bool half = o.refine == 0;
     {
-      ProfScope ps(h, PROF_GEMM_NNN, 2.0 * n * (double)n * n, nullptr, 24.0 * n * (double)n);
+      ProfScope ps(h, PROF_GEMM_NNN, half ? (double)n * (n + 1.0) * n : 2.0 * n * (double)n * n, nullptr,
+                   (half ? 20.0 : 24.0) * n * (double)n);
       gemm_f64(s, false, false, n, n, n, -1.0, DOp{Y, ld, nullptr}, TRI_NONE, DOp{Xr, ldx, nullptr}, TRI_NONE, 0.0,
-               DOut{Xi, ldx, nullptr, nullptr});
+               DOut{Xi, ldx, nullptr, nullptr}, half);
     }
+    if (half) mirror_lower_f64(s, n, Xi, ldx, step5_sign < 0.0 ? -1.0 : 1.0);
     lp.reset();
     read_info(h);
     frob_result_t r;

@@ -366,14 +366,19 @@ __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_ge
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
+  // A lower-triangle-only product leaves the tiles above the diagonal idle.
+  // Contiguous per-XCD ranges of the grouped order would then give the XCDs
+  // of the first tile-rows almost nothing to do; interleaving hands XCD x
+  // tile-row x of every group instead (all its columns, so its A rows stay
+  // in its L2), and the live tiles spread evenly.
   if (!PERSIST) {
-    const int t = (bid & 7) * per + (bid >> 3);
+    const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
     if (t >= tiles) return;
     gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
   } else {
     const int step = gridDim.x >> 3;
     for (int li = bid >> 3; li < per; li += step) {
-      const int t = (bid & 7) * per + li;
+      const int t = g.lowerOnly ? 8 * li + (bid & 7) : (bid & 7) * per + li;
       if (t >= tiles) break;
       gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
       // a next tile reuses the LDS ring: the tile's last k-step ended with a

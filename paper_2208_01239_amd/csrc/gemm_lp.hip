@@ -52,7 +52,9 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
-  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous ranges of tile indices
+  // XCD-contiguous ranges of tile indices; interleaved for lower-only products
+  // (the idle tiles above the diagonal would otherwise leave whole XCDs idle)
+  const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
   if (t >= tiles) return;
   // tile indices run through groups of eight tile-rows column by column
   const int gsz = 8 * g.tilesN;
@@ -252,7 +254,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lp32(GemmLpParams<TS> g) {
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
-  const int t = (bid & 7) * per + (bid >> 3);        // XCD-contiguous ranges of tile indices
+  // XCD-contiguous ranges of tile indices; interleaved for lower-only products
+  // (the idle tiles above the diagonal would otherwise leave whole XCDs idle)
+  const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
   if (t >= tiles) return;
   const int gsz = 8 * g.tilesN;
   const int grp = t / gsz;
