@@ -96,7 +96,10 @@ typedef struct {
   int refine_flags;     /* FROB_REFINE_* bits, default 0                                                    */
   double theta;         /* rotation angle for FROB_SHIFT_PHASE (radians)                                    */
   double cond_tol;      /* target of FROB_SHIFT_COND for u kappa_1(C) (<= 0: 1e-10)                          */
-  int reserved[2];
+  int panel;            /* panel width of the look-ahead LUs of A and C (orders >= 1024): 0 = 64 (measured
+                           fastest at n = 4096); 16, 32, 48 or 64; other values FROB_E_ARG.  Ignored below
+                           order 1024 and by the HPD, complex and batched paths                            */
+  int reserved;
 } frob_opts_t;
 
 /* refine_flags: when refinement ends at the step limit (opts.refine steps

@@ -102,7 +102,7 @@ def _mat(t, n_rows, n_cols, name, dtype=None):
 
 
 def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32_correction=False, theta=0.0,
-          cond_tol=0.0, report_cond=False):
+          cond_tol=0.0, report_cond=False, panel=0):
     o = frob_opts_t()
     _lib.load().frob_default_opts(ctypes.byref(o))
     o.shift = int(shift)
@@ -115,6 +115,7 @@ def _opts(shift, mu, seed, refine, prec=0, refine_tol=0.0, final_resid=True, f32
         (FROB_REFINE_F32_CORRECTION if f32_correction else 0) | (FROB_REPORT_COND if report_cond else 0)
     o.theta = float(theta)
     o.cond_tol = float(cond_tol)
+    o.panel = int(panel)
     return o
 
 
@@ -131,7 +132,7 @@ def _fn32(name, A):
 
 def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, refine=0,
                      prec=FROB_PREC_F64, refine_tol=0.0, final_resid=True, f32_correction=False, theta=0.0,
-                     cond_tol=0.0, report_cond=False):
+                     cond_tol=0.0, report_cond=False, panel=0):
     """(A + iB)^{-1} = Xr + i Xi by Algorithm 5 (and 6 when shifting).
 
     prec: operand precision of the matrix-core products (FROB_PREC_F64/F32/BF16);
@@ -143,7 +144,8 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
     shift=FROB_SHIFT_PHASE with theta: invert e^{i theta} M and rotate back
     (theta = -pi/2: the formula for invertible B); shift=FROB_SHIFT_COND:
     rotations tried until u kappa_1(C) <= cond_tol; report_cond: kappa_1(C)
-    in the result."""
+    in the result; panel: panel width of the look-ahead LUs (0 = 64; 16, 32,
+    48 or 64) from order 1024."""
     n = A.shape[0]
     name, dt = _fn32("frob_inv_general", A)
     Xr = _empty_like_sq(A, n) if Xr is None else Xr
@@ -156,7 +158,7 @@ def frob_inv_general(h: Handle, A, B, Xr=None, Xi=None, *, shift=FROB_SHIFT_AUTO
         raise ValueError("Xr and Xi must share a leading dimension")
     h.bind_stream()
     o, r = _opts(shift, mu, seed, refine, prec, refine_tol, final_resid, f32_correction, theta, cond_tol,
-                 report_cond), frob_result_t()
+                 report_cond, panel), frob_result_t()
     st = getattr(_lib.load(), name)(h.ptr, n, pa, lda, pb, ldb, pr, pi, ldx, ctypes.byref(o), ctypes.byref(r))
     _lib.check(st, name, r)
     return Xr, Xi, r.as_dict()
@@ -221,9 +223,10 @@ def frob_refine(h: Handle, A, B, Xr, Xi, *, refine=4, prec=FROB_PREC_F64, refine
     return r.as_dict()
 
 
-def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0):
+def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, mu=0.0, seed=0, panel=0):
     """Solve (A + iB)(x + iy) = c + id for n x p right-hand sides (Algorithm 3).
-    float32 operands use the FP32-storage twin (FP64 arithmetic)."""
+    float32 operands use the FP32-storage twin (FP64 arithmetic); panel as
+    for frob_inv_general."""
     import torch
     n = A.shape[0]
     p = c.shape[1]
@@ -239,7 +242,7 @@ def frob_solve(h: Handle, A, B, c, d, x=None, y=None, *, shift=FROB_SHIFT_AUTO, 
     if ldc != ldd or ldx != ldy:
         raise ValueError("c/d and x/y must share leading dimensions")
     h.bind_stream()
-    o, r = _opts(shift, mu, seed, 0), frob_result_t()
+    o, r = _opts(shift, mu, seed, 0, panel=panel), frob_result_t()
     st = getattr(_lib.load(), name)(h.ptr, n, p, pa, lda, pb, ldb, pc, pd, ldc, px, py, ldx, ctypes.byref(o),
                                     ctypes.byref(r))
     _lib.check(st, name, r)

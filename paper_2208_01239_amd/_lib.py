@@ -43,7 +43,7 @@ class frob_opts_t(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine", ctypes.c_int), ("prec", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("refine_flags", ctypes.c_int), ("theta", ctypes.c_double), ("cond_tol", ctypes.c_double),
-                ("reserved", ctypes.c_int * 2)]
+                ("panel", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 class frob_result_t(ctypes.Structure):

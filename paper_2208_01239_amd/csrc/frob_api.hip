@@ -148,6 +148,18 @@ void prof_resolve(frob_handle* h) {
 
 namespace {
 
+// opts.panel: 0 (the default width) or 16, 32, 48, 64
+bool panel_ok(int p) { return p == 0 || (p >= 16 && p <= LA_NB && p % 16 == 0); }
+
+// The look-ahead LUs of one call use the caller's panel width; the handle's
+// setting is restored when the call returns.
+struct PanelScope {
+  frob_handle* h;
+  int prev;
+  PanelScope(frob_handle* hh, int p) : h(hh), prev(hh->la.nb) { h->la.nb = p ? p : LA_NB; }
+  ~PanelScope() { h->la.nb = prev; }
+};
+
 frob_opts_t opts_or_default(const frob_opts_t* o) {
   frob_opts_t d;
   frob_default_opts(&d);
@@ -409,9 +421,10 @@ frob_status_t frob_inv_general(frob_handle_t h, int n, const double* A, int lda,
   if (!h || !A || !B || !Xr || !Xi || bad_dims(n, lda) || ldb < n || ldx < n) return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
   if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_COND || o.refine < 0 || o.prec < FROB_PREC_F64 ||
-      o.prec > FROB_PREC_BF16 || (o.shift == FROB_SHIFT_PHASE && !std::isfinite(o.theta)))
+      o.prec > FROB_PREC_BF16 || (o.shift == FROB_SHIFT_PHASE && !std::isfinite(o.theta)) || !panel_ok(o.panel))
     return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
+    PanelScope pw(h, o.panel);
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;
@@ -637,8 +650,10 @@ frob_status_t frob_solve(frob_handle_t h, int n, int nrhs, const double* A, int 
       ldxy < nrhs)
     return FROB_E_ARG;
   const frob_opts_t o = opts_or_default(opts);
-  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.prec != FROB_PREC_F64) return FROB_E_ARG;
+  if (o.shift < FROB_SHIFT_OFF || o.shift > FROB_SHIFT_ON || o.prec != FROB_PREC_F64 || !panel_ok(o.panel))
+    return FROB_E_ARG;
   return guarded(h, [&]() -> frob_status_t {
+    PanelScope pw(h, o.panel);
     if (o.seed) h->rng = o.seed;
     hipStream_t s = h->stream;
     const size_t nn = (size_t)n * n;

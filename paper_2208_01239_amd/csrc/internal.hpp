@@ -114,6 +114,7 @@ struct LookAhead {
   hipStream_t s1 = nullptr;
   hipEvent_t ev[8] = {};
   frob_handle* prof = nullptr;   // times the second stream's trailing-update GEMMs when profiling is on
+  int nb = 64;                   // panel width of the real LU (16, 32, 48 or 64; set per call)
 };
 // Panel widths (real, complex): the next panel's update is then one
 // recursion-node launch (real nodes up to 64 columns, complex up to 32).

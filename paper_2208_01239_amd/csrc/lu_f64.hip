@@ -624,7 +624,7 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
   getrf_rec(s, a, lda, perm, k0 + n1, m, n2, info, work, cnt, snap, sfrom);
 }
 
-// Panels of LA_NB columns with a look-ahead of one panel (see internal.hpp),
+// Panels of la.nb (default LA_NB) columns with a look-ahead of one panel (see internal.hpp),
 // grouped into super-panels of LA_SUPER panels.
 // Row interchanges only permute `perm` among the trailing positions, so a
 // trailing update may run while a later panel pivots, provided it addresses
@@ -648,7 +648,10 @@ void getrf_rec(hipStream_t s, double* a, int lda, int* perm, int k0, int m, int 
 void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm, int* info, double* work, int* cnt,
                      const LookAhead& la) {
   const int nt = n + q;   // the q columns right of the matrix take every update and no pivot search
-  constexpr int SW = LA_NB * LA_SUPER;   // super-panel width
+  // panel width: the caller's choice (a multiple of 16 up to LA_NB, the width
+  // the scratch below is sized for)
+  const int PW = (la.nb >= 16 && la.nb <= LA_NB && la.nb % 16 == 0) ? la.nb : LA_NB;
+  const int SW = PW * LA_SUPER;   // super-panel width
   hipStream_t s1 = la.s1;
   double* work0 = work;
   double* work1 = work0 + trsm_work_elems(n / 2 + 8);
@@ -677,10 +680,10 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
                  8.0 * ((double)m * nb + (double)nb * w + 2.0 * m * w));
     gemm_f64(st, false, false, m, w, nb, -1.0, L21, TRI_NONE, U12, TRI_NONE, 1.0, A22);
   };
-  const int np = ceil_div(n, LA_NB);
+  const int np = ceil_div(n, PW);
   int last_r = -1, last_g = -1;
   for (int j = 0; j < np; ++j) {
-    const int k0 = j * LA_NB, nb = min(LA_NB, n - k0);
+    const int k0 = j * PW, nb = min(PW, n - k0);
     const int r0 = k0 + nb;
     const int sp = j / LA_SUPER;
     const int K0 = sp * SW;                        // first column of this super-panel
@@ -691,7 +694,7 @@ void getrf_lookahead(hipStream_t s0, int n, int q, double* a, int lda, int* perm
     getrf_rec(s0, a, lda, perm, k0, n, nb, info, work0, cnt, r0 < n ? sn : nullptr, r0);
     if (!last_in_sp) {
       FROB_HIP(hipEventRecord(evF(j), s0));
-      const int c1 = r0, w1 = min(LA_NB, spend - c1);
+      const int c1 = r0, w1 = min(PW, spend - c1);
       if (j >= 1 && last_r == j - 1) FROB_HIP(hipStreamWaitEvent(s0, evR(j - 1), 0));
       // the next panel's update is a recursion node (solve and update in one launch)
       if (nb <= NODE_MAX && w1 <= NODE_MAX) launch_node(s0, a, lda, perm, k0, n - k0, nb, w1, cnt);

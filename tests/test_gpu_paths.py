@@ -385,3 +385,36 @@ def test_spd_pair_rejects_indefinite_real_part(h):
     with pytest.raises(fi.FrobNotHPDError) as ex:
         fi.frob_inv_spd_pair(h, to_dev(-A), to_dev(B))
     assert ex.value.result.stage == 1
+
+
+# ------------------------------------------------------------------ panel width option
+@pytest.mark.parametrize("panel", [16, 32, 48, 64])
+def test_panel_width_option(h, panel):
+    """opts.panel sets the look-ahead LUs' panel width (n = 1100: 1100 is a
+    multiple of none of them, so every width ends on a ragged panel): the
+    inverse and a solve match the oracle for each width; other widths are
+    refused."""
+    import paper_2208_01239_amd as fi
+    n = 1100
+    A, B = inputs.general(n, 4100)
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    C = A + B @ np.linalg.solve(A, B)
+    tol = max(TOL, 16 * np.finfo(float).eps / 2 * np.linalg.cond(C))
+    Xr, Xi, _ = fi.frob_inv_general(h, to_dev(A), to_dev(B), panel=panel)
+    e = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    rng = np.random.default_rng(panel)
+    c, d = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    x, y, _ = fi.frob_solve(h, to_dev(A), to_dev(B), to_dev(c), to_dev(d), panel=panel)
+    z = (Rr + 1j * Ri) @ (c + 1j * d)
+    es = relF(to_host(x), to_host(y), z.real, z.imag)
+    print(f"panel {panel}: inverse relF {e:.2e}, solve relF {es:.2e} (tol {tol:.1e})")
+    assert e <= tol and es <= tol
+
+
+@pytest.mark.parametrize("panel", [8, 17, 80, -16])
+def test_panel_width_rejected(h, panel):
+    import paper_2208_01239_amd as fi
+    A, B = inputs.general(8, 1)
+    with pytest.raises(fi.FrobError, match="FROB_E_ARG"):
+        fi.frob_inv_general(h, to_dev(A), to_dev(B), panel=panel)
