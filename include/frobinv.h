@@ -368,9 +368,10 @@ frob_status_t frob_inv_batched(frob_handle_t handle, int count, int nmax, const 
  * nmax x nmax matrices) in a fixed device array of 128 MiB that the library
  * holds on every GPU it runs on until the process ends.  Nothing is
  * allocated or freed and the handle's workspace is not used.  Limits:
- * count <= 1048576, nmax <= 512; the persistent grid is the number of compute
- * units or the number of slots that fit, whichever is smaller (at least 20;
- * all 256 for nmax <= 147 in FP64 and nmax <= 208 in FP32).  Returns FROB_E_ARG
+ * count <= 1048576, nmax <= 512; the persistent grid is two workgroups per
+ * compute unit, the number of slots that fit, or count, whichever is smallest
+ * (at least 20 slots fit; all 512 for nmax <= 102 in FP64 and nmax <= 145 in
+ * FP32).  Returns FROB_E_ARG
  * beyond the limits.  Calls that overlap on one GPU (concurrent streams,
  * handles or threads) share the array and race: order them.  Each call
  * rewrites the queue head and order before its kernel reads them. */

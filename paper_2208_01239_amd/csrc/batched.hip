@@ -1,25 +1,24 @@
 // batched.hip -- many Frobenius inversions of uneven order in one persistent
 // launch (the batching line of growth).
 //
-// One workgroup (256 threads) inverts one matrix at a time, start to finish:
-// it takes the next matrix index from an atomic queue whose order (largest
-// order first, the longest-processing-time rule) is prepared on the device,
-// and runs Algorithm 5 (general) or Algorithm 7 (Hermitian positive definite)
-// with blocked in-workgroup building blocks:
-//   - GEMM: 64x64 output tiles, k-step 32, operands staged in LDS, 16x16x4
-//     matrix-core products (FP64, or FP32 with FP32 accumulation), next
-//     k-step's global loads in flight during the current products;
-//   - LU with partial pivoting: right-looking, panels of NB columns factored in
-//     LDS (pivot search by wave reductions plus an LDS reduction), physical row
-//     interchanges, triangular solve of the block row, GEMM trailing update;
-//   - Cholesky: NB x NB diagonal blocks in LDS, row-wise substitution for the
-//     block column, GEMM trailing update;
-//   - triangular solves: NB x NB diagonal blocks by substitution (one thread
-//     per right-hand side), GEMM updates in between.
-// The matrices stay in global memory (L2-resident at these orders); each
-// workgroup owns a private slot of workspace (three n_max x n_max matrices and
-// the pivot indices).  Panel width NB per size class comes from the caller's
-// table (autotuned by frob_batched_tune).
+// One workgroup (256 threads) inverts one matrix at a time, start to finish,
+// two workgroups per compute unit: it takes the next matrix index from an
+// atomic queue whose order (largest order first, the longest-processing-time
+// rule) is prepared on the device, and runs Algorithm 5 (general) or
+// Algorithm 7 (Hermitian positive definite) with the in-workgroup building
+// blocks of batched_dev.hpp:
+//   - GEMM: tile shape chosen per product (128x128 down to 16x256 / 256x16),
+//     16x16x4 matrix-core products (FP64, or FP32 with FP32 accumulation),
+//     operand tiles double-buffered in LDS;
+//   - LU with partial pivoting: panels of NB columns factored in LDS (pivot
+//     search by wave reductions), interchanges applied as one composite row
+//     map, updates in the order of the recursive algorithm;
+//   - Cholesky and triangular solves: NB x NB diagonal blocks by substitution,
+//     updates in the same recursive order.
+// The matrices stay in global memory; each workgroup owns a private slot of
+// workspace (three n_max x n_max matrices and the row map).  Panel width NB
+// per size class comes from the caller's table (autotuned by
+// frob_batched_tune).
 #include <algorithm>
 #include <climits>
 #include <mutex>
@@ -61,7 +60,9 @@ using bat::BT;
 using bat::Smem;
 
 template <typename T>
-__global__ __launch_bounds__(BT, 1) void k_batched_inv(BatchArgs g) {
+// Two workgroups per compute unit (LDS and registers are sized for it): while
+// one waits on memory or a barrier, the other computes.
+__global__ __launch_bounds__(BT, 2) void k_batched_inv(BatchArgs g) {
   __shared__ Smem<T> sm;
   bat::batched_worker<T>(g, sm, blockIdx.x);
 }
@@ -82,7 +83,7 @@ size_t batched_ws_bytes(int grid, int nmax, int count, int storage) {
 int batched_grid(frob_handle* h) {
   int cus = 0;
   FROB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-  return cus > 0 ? cus : 256;
+  return 2 * (cus > 0 ? cus : 256);   // two workgroups per compute unit
 }
 
 size_t batched_slot_elems(int nmax, int storage) {
@@ -115,7 +116,7 @@ static void batched_enqueue(frob_handle* h, int grid, int* counter, int* order, 
 // counter | order[count] | per-workgroup slots, in the handle's workspace
 void batched_launch(frob_handle* h, int count, int nmax, const int* n_dev, const int* kind_dev, const void* const* A,
                     const void* const* B, void* const* Xr, void* const* Xi, int* info_dev, int storage) {
-  const int grid = batched_grid(h);
+  const int grid = std::min(batched_grid(h), std::max(count, 1));   // no idle workgroups sharing a CU
   char* ws = (char*)ws_reserve(h, batched_ws_bytes(grid, nmax, count, storage));
   mark_ws_captured(h);   // a captured launch keeps this workspace alive
   int* counter = reinterpret_cast<int*>(ws);
@@ -232,7 +233,7 @@ extern "C" frob_status_t frob_inv_batched_noalloc(frob_handle_t h, int count, in
     const size_t el = storage == FROB_PREC_F32 ? sizeof(float) : sizeof(double);
     const size_t slot_bytes = batched_slot_elems(nmax, storage) * el;
     const size_t fit = (NOALLOC_SCRATCH_BYTES - head) / slot_bytes;   // >= 20 for every accepted shape
-    const int grid = (int)std::min<size_t>((size_t)batched_grid(h), fit);
+    const int grid = (int)std::min<size_t>(std::min<size_t>((size_t)batched_grid(h), fit), (size_t)std::max(count, 1));
     if (grid < 1) return FROB_E_ARG;
     batched_enqueue(h, grid, reinterpret_cast<int*>(base), reinterpret_cast<int*>(base + 256), base + head, count,
                     nmax, n_dev, kind_dev, A_dev, B_dev, Xr_dev, Xi_dev, info_dev, storage);
@@ -249,7 +250,7 @@ extern "C" frob_status_t frob_batched_tune(frob_handle_t h, int storage, int tab
   const int si = storage == FROB_PREC_F32 ? 1 : 0;
   const size_t el = storage == FROB_PREC_F32 ? sizeof(float) : sizeof(double);
   static const int class_n[4] = {64, 128, 256, 512};
-  static const int cands[3] = {8, 16, 32};
+  static const int cands[3] = {4, 8, 16};
   char *A = nullptr, *B = nullptr, *Xr = nullptr, *Xi = nullptr, *meta = nullptr;
   frob_status_t st = FROB_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;

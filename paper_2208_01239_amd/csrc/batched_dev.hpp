@@ -27,8 +27,14 @@ namespace bat {
 
 constexpr int BT = 256;          // threads per workgroup
 constexpr int BNMAX = 512;       // largest order handled in-workgroup
-constexpr int PNB = 32;          // largest LU panel width
+constexpr int PNB = 16;          // largest LU panel width
 constexpr int PP = PNB + 1;      // LDS pitch of panel rows (odd in 8-byte words: rows fall on different banks)
+// The panel buffer holds an LU panel (BNMAX x PP), a triangular or Cholesky
+// diagonal block, the staged interchange gather (2 PNB x BT), or the GEMM's two
+// operand stages of the widest tile (16 x (20 + 260) each); 70 KiB in FP64,
+// so that two workgroups fit a compute unit's 160 KiB of LDS.
+constexpr int PANEL_ELEMS = 8960;
+static_assert(PANEL_ELEMS >= BNMAX * PP && PANEL_ELEMS >= 2 * PNB * BT, "panel buffer too small");
 constexpr int XNB = 16;          // diagonal blocks solved by register substitution (triangular solves, Cholesky)
 constexpr int GK = 16;           // GEMM k-step
 
@@ -54,7 +60,7 @@ struct Mfma<float> {
 
 template <typename T>
 struct Smem {
-  T panel[BNMAX * PP];       // LU panel / Cholesky diagonal block / triangular diagonal block;
+  T panel[PANEL_ELEMS];      // LU panel / Cholesky diagonal block / triangular diagonal block;
                              // the GEMM's double-buffered operand tiles when none of those is live
   T red_v[BT / 64];
   int red_i[BT / 64];
@@ -90,7 +96,7 @@ BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, 
   constexpr int TM = WM * BA * 16, TN = WN * BB * 16;
   constexpr int PA = TM + 4, PB = TN + 4;          // LDS pitches of the k-major tiles
   constexpr int BUF = GK * (PA + PB);              // one stage: A tile then B tile
-  static_assert(2 * BUF <= BNMAX * PP, "GEMM stages exceed the panel buffer");
+  static_assert(2 * BUF <= PANEL_ELEMS, "GEMM stages exceed the panel buffer");
   constexpr int EA = (TM * GK + BT - 1) / BT, EB = (TN * GK + BT - 1) / BT;
   const int tid = bb_tid(), lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WN) * (BA * 16), wn = (wave % WN) * (BB * 16);
@@ -422,7 +428,7 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
     const int cnt = imin(uni(sm.tl_n), 2 * PNB);
     for (int c = tid; c < n; c += BT) {
       if (c >= k0 && c < k0 + kb) continue;
-      T* S = P;   // 2 PNB rows x BT columns <= BNMAX x PP; a thread's second column reuses its slots
+      T* S = P;   // 2 PNB rows x BT columns fit the buffer; a thread's second column reuses its slots
       for (int e = 0; e < cnt; ++e) S[e * BT + tid] = A[(long long)sm.tl_src[e] * lda + c];
       for (int e = 0; e < cnt; ++e) A[(long long)sm.tl_dst[e] * lda + c] = S[e * BT + tid];
     }
