@@ -201,9 +201,10 @@ BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, 
   bb_sync();
 }
 
-// The tile shape follows the product's shape: square tiles for full
-// products, wide ones for the short updates of the triangular solves, tall
-// ones for the narrow column updates of the factorizations.
+// The tile shape follows the product's shape: large tiles for full products
+// (128 x 128 in FP32, 128 x 64 in FP64), wide ones for the short updates of
+// the triangular solves, tall ones for the narrow column updates of the
+// factorizations.
 template <typename T>
 BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B, int ldb,
                    bool tb, T beta, T* C, int ldc) {
@@ -220,6 +221,10 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
     wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 256 x 16
   else if (N <= 32 && M > 64)
     wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 32
+  else if (M > 64 && N > 64 && sizeof(T) == 8)
+    // FP64: 128 x 64; the 128 x 128 tile's accumulators and prefetch registers
+    // exceed the register share of two waves per SIMD and spill in the k-loop
+    wg_gemm_tiles<T, 2, 2, 4, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
   else if (M > 64 && N > 64)
     wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 128
   else
