@@ -91,7 +91,7 @@ BB_IN bool uni(bool v) { return bb_first((int)v) != 0; }
 // addresses, values outside the matrix zeroed when staged.
 template <typename T, int WM, int WN, int BA, int BB>
 BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B,
-                         int ldb, bool tb, T beta, T* C, int ldc) {
+                         int ldb, bool tb, T beta, T* C, int ldc, bool lower) {
   typedef typename Mfma<T>::acc acc_t;
   constexpr int TM = WM * BA * 16, TN = WN * BB * 16;
   constexpr int PA = TM + 4, PB = TN + 4;          // LDS pitches of the k-major tiles
@@ -106,6 +106,7 @@ BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, 
   T* lds = sm.panel;
   for (int t = 0; t < tiles; ++t) {
     const int tm = (t / tilesN) * TM, tn = (t % tilesN) * TN;
+    if (lower && tn > tm + TM - 1) continue;   // entirely above the diagonal (uniform)
     acc_t acc[BA][BB];
 #pragma unroll
     for (int a = 0; a < BA; ++a)
@@ -205,30 +206,33 @@ BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, 
 // (128 x 128 in FP32, 128 x 64 in FP64), wide ones for the short updates of
 // the triangular solves, tall ones for the narrow column updates of the
 // factorizations.
+// lower: only tiles that meet the lower triangle (diagonal included) are
+// formed; entries above the diagonal in those tiles are written too.
 template <typename T>
 BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B, int ldb,
-                   bool tb, T beta, T* C, int ldc) {
+                   bool tb, T beta, T* C, int ldc, bool lower = false) {
   M = uni(M); N = uni(N); K = uni(K); lda = uni(lda); ldb = uni(ldb); ldc = uni(ldc); ta = uni(ta); tb = uni(tb);
+  lower = uni(lower);
   if (M <= 0 || N <= 0) {
     bb_sync();
     return;
   }
   if (M <= 16 && N > 64)
-    wg_gemm_tiles<T, 1, 4, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 16 x 256
+    wg_gemm_tiles<T, 1, 4, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 16 x 256
   else if (M <= 32 && N > 64)
-    wg_gemm_tiles<T, 2, 2, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 32 x 128
+    wg_gemm_tiles<T, 2, 2, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 32 x 128
   else if (N <= 16 && M > 64)
-    wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 256 x 16
+    wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 256 x 16
   else if (N <= 32 && M > 64)
-    wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 32
+    wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 128 x 32
   else if (M > 64 && N > 64 && sizeof(T) == 8)
     // FP64: 128 x 64; the 128 x 128 tile's accumulators and prefetch registers
     // exceed the register share of two waves per SIMD and spill in the k-loop
-    wg_gemm_tiles<T, 2, 2, 4, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+    wg_gemm_tiles<T, 2, 2, 4, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);
   else if (M > 64 && N > 64)
-    wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 128 x 128
+    wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 128 x 128
   else
-    wg_gemm_tiles<T, 2, 2, 2, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);      // 64 x 64
+    wg_gemm_tiles<T, 2, 2, 2, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 64 x 64
 }
 
 // ------------------------------------------------------- triangular solves
@@ -236,6 +240,8 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
 //   mode 0: T lower, op(T) = T   (forward substitution; unit diagonal if `unit`)
 //   mode 1: T lower, op(T) = T^T (backward)
 //   mode 2: T upper, op(T) = T   (backward)
+// idrhs (mode 0 only): B holds the identity on entry, so the solution T^{-1}
+// is lower triangular and only the columns left of each block are touched.
 // Leaves of nb <= 16 rows are solved by register substitution (one thread per
 // right-hand side); the updates follow the order of the recursive algorithm
 // (solve the first half, update the second half with a product of depth
@@ -245,8 +251,10 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
 // rewritten about log2(n / nb) times instead of n / nb times, and the deep
 // products near the root do most of the work.
 template <typename T>
-BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, bool unit, T* B, int ldb, int nb) {
+BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, bool unit, T* B, int ldb, int nb,
+                   bool idrhs = false) {
   mode = uni(mode); n = uni(n); nrhs = uni(nrhs); ldl = uni(ldl); ldb = uni(ldb); unit = uni(unit);
+  idrhs = uni(idrhs) && mode == 0;
   const int tid = bb_tid();
   nb = imax(imin(uni(nb), XNB), 1);
   const int nblk = (n + nb - 1) / nb;
@@ -263,7 +271,10 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
       D[i * PP + k] = in ? L[(long long)(k0 + r) * ldl + k0 + c] : T(0);
     }
     bb_sync();
-    for (int j = tid; j < nrhs; j += BT) {
+    // B = I (idrhs): the solution is lower triangular, so rows k0 .. k0 + kb
+    // have nonzeros only in the columns left of k0 + kb
+    const int jend = idrhs ? imin(nrhs, k0 + kb) : nrhs;
+    for (int j = tid; j < jend; j += BT) {
       T x[XNB];
 #pragma unroll
       for (int i = 0; i < XNB; ++i) x[i] = B[(long long)(k0 + imin(i, kb - 1)) * ldb + j];
@@ -297,7 +308,7 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
       // done: rows [c0, c1); next: rows [c1, r1) -= op(T)[c1:r1, c0:c1] X[c0:c1]
       const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
       if (c1 < n)
-        wg_gemm<T>(sm, r1 - c1, nrhs, c1 - c0, T(-1), L + (long long)c1 * ldl + c0, ldl, false,
+        wg_gemm<T>(sm, r1 - c1, idrhs ? imin(nrhs, c1) : nrhs, c1 - c0, T(-1), L + (long long)c1 * ldl + c0, ldl, false,
                    B + (long long)c0 * ldb, ldb, false, T(1), B + (long long)c1 * ldb, ldb);
     } else {
       // done: rows [k0, c1); next: rows [r0, k0) -= op(T)[r0:k0, k0:c1] X[k0:c1]
@@ -471,11 +482,14 @@ BB_IN void wg_gather_rows(int n, int ncols, const T* src, int lds, const int* pe
   bb_sync();
 }
 
-// dst = P (n x n): row r holds its one in column perm[r]
+// dst = src P (n x n): column perm[r] of dst is column r of src
 template <typename T>
-BB_IN void wg_perm_matrix(int n, const int* perm, T* dst) {
+BB_IN void wg_scatter_cols(int n, const T* src, const int* perm, T* dst) {
   n = uni(n);
-  for (int e = bb_tid(); e < n * n; e += BT) dst[e] = perm[e / n] == e % n ? T(1) : T(0);
+  for (int e = bb_tid(); e < n * n; e += BT) {
+    const int i = e / n, r = e % n;
+    dst[(long long)i * n + perm[r]] = src[e];
+  }
   bb_sync();
 }
 
@@ -635,9 +649,13 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
       wg_gemm<T>(sm, n, n, n, T(1), B, n, false, Y, n, false, T(1), Cm, n);
       const int i2 = bb_first(wg_getrf<T>(sm, n, Cm, n, perm, nb));
       if (!info) info = status_word(2, i2);
-      wg_perm_matrix<T>(n, perm, Xr);                                   // Re X = C^{-1} = U^{-1} L^{-1} P
-      wg_trsm<T>(sm, 0, n, n, Cm, n, true, Xr, n, nb);
-      wg_trsm<T>(sm, 2, n, n, Cm, n, false, Xr, n, nb);
+      // Re X = C^{-1} = U^{-1} L^{-1} P: L^{-1} by a solve against I (lower
+      // triangular, n^3 / 3), then U^{-1} (n^3), then the column permutation;
+      // the factors of A in F are no longer needed
+      wg_identity<T>(n, F);
+      wg_trsm<T>(sm, 0, n, n, Cm, n, true, F, n, nb, true);
+      wg_trsm<T>(sm, 2, n, n, Cm, n, false, F, n, nb);
+      wg_scatter_cols<T>(n, F, perm, Xr);
       wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
     } else {
       // Algorithm 7
@@ -650,11 +668,11 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
       wg_trsm<T>(sm, 1, n, n, F, n, false, Y, n, nb);
       // C = A - X1^T X1 into F's place (F is no longer needed)
       wg_copy<T>(n, A, F);
-      wg_gemm<T>(sm, n, n, n, T(-1), Cm, n, true, Cm, n, false, T(1), F, n);
+      wg_gemm<T>(sm, n, n, n, T(-1), Cm, n, true, Cm, n, false, T(1), F, n, true);   // lower triangle only
       const int i2 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
       if (!info) info = status_word(2, i2);
       wg_identity<T>(n, Xr);                                            // Re X = R2^{-1} R2^{-T}
-      wg_trsm<T>(sm, 0, n, n, F, n, false, Xr, n, nb);
+      wg_trsm<T>(sm, 0, n, n, F, n, false, Xr, n, nb, true);           // R2^{-T}, lower triangular
       wg_trsm<T>(sm, 1, n, n, F, n, false, Xr, n, nb);
       wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
     }
