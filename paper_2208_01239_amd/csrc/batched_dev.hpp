@@ -493,6 +493,17 @@ BB_IN void wg_scatter_cols(int n, const T* src, const int* perm, T* dst) {
   bb_sync();
 }
 
+// a[j][i] = -a[i][j] above the diagonal (i > j), from the lower triangle
+template <typename T>
+BB_IN void wg_mirror_skew(int n, T* a) {
+  n = uni(n);
+  for (int e = bb_tid(); e < n * n; e += BT) {
+    const int i = e / n, j = e % n;
+    if (j < i) a[(long long)j * n + i] = -a[e];
+  }
+  bb_sync();
+}
+
 // ------------------------------------------------------------ Cholesky
 // A = L L^T in place (lower triangle).  Returns the first non-positive pivot's
 // column (1-based), or 0.  nb >= 1 (the caller clamps).
@@ -674,7 +685,9 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
       wg_identity<T>(n, Xr);                                            // Re X = R2^{-1} R2^{-T}
       wg_trsm<T>(sm, 0, n, n, F, n, false, Xr, n, nb, true);           // R2^{-T}, lower triangular
       wg_trsm<T>(sm, 1, n, n, F, n, false, Xr, n, nb);
-      wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n);   // Im X = -Y C^{-1}
+      // Im X = -Y C^{-1} is skew (X is Hermitian): the lower triangle, mirrored
+      wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n, true);
+      wg_mirror_skew<T>(n, Xi);
     }
     if (tid == 0) g.info[mi] = info;
     bb_sync();
