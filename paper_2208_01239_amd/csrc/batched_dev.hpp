@@ -37,6 +37,11 @@ constexpr int PANEL_ELEMS = 8960;
 static_assert(PANEL_ELEMS >= BNMAX * PP && PANEL_ELEMS >= 2 * PNB * BT, "panel buffer too small");
 constexpr int XNB = 16;          // diagonal blocks solved by register substitution (triangular solves, Cholesky)
 constexpr int GK = 16;           // GEMM k-step
+// Element-wise passes keep SU loads per thread in flight before their stores:
+// the matrices are reached through generic pointers, so the compiler cannot
+// move a load above an earlier store, and a pass of dependent load-store
+// pairs would wait one memory latency per element.
+constexpr int SU = 8;
 
 BB_IN int imin(int a, int b) { return a < b ? a : b; }
 BB_IN int imax(int a, int b) { return a > b ? a : b; }
@@ -62,11 +67,12 @@ template <typename T>
 struct Smem {
   T panel[PANEL_ELEMS];      // LU panel / Cholesky diagonal block / triangular diagonal block;
                              // the GEMM's double-buffered operand tiles when none of those is live
-  T red_v[BT / 64];
-  int red_i[BT / 64];
+  T slot_v[2][BT / 64];       // LU panel: each wave's pivot candidate by column parity: |value|,
+  int slot_p[2][BT / 64];     //   position,
+  int slot_q[2][BT / 64];     //   and row in the panel buffer
   int bcast[4];
   int perm[BNMAX];           // LU: original row now at each row position
-  int cont[BNMAX];           // LU panel: panel row whose content each panel row now holds
+  int rowpos[BNMAX];         // LU panel: final position of each panel row
   int tl_dst[2 * PNB];       // LU panel: rows changed by the panel's interchanges,
   int tl_src[2 * PNB];       //   and the rows their new content comes from
   int tl_n;
@@ -325,128 +331,190 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
   }
 }
 
-// ------------------------------------------------------------ reductions
-// (value, index) with the largest value; lowest index on ties; returns to all threads
-template <typename T>
-BB_IN int wg_argmax(Smem<T>& sm, T v, int idx) {
-  const int lane = bb_tid() & 63, wave = bb_tid() >> 6;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const T ov = bb_shfl_xor(v, off);
-    const int oi = bb_shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
-  if (lane == 0) { sm.red_v[wave] = v; sm.red_i[wave] = idx; }
-  bb_sync();
-  T bv = sm.red_v[0];
-  int bi = sm.red_i[0];
-#pragma unroll
-  for (int w = 1; w < BT / 64; ++w) {
-    const T ov = sm.red_v[w];
-    const int oi = sm.red_i[w];
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-  }
-  bb_sync();
-  return bi;
-}
-
 // ------------------------------------------------------------- LU (GEPP)
 // P A = L U in place; perm_out[r] = the row of A that row r of P A is.
-// Panels of nb columns factored in LDS (pivot search by wave reductions),
-// interchanges applied to the panel rows in LDS and recorded as a composite
-// map; the rows they change in the columns outside the panel are then
-// rewritten by one gather per column, all loads in flight before the stores.
-// Trailing updates in recursive order (below).  Returns the first zero pivot
-// column + 1, or 0.  nb >= 1 (the caller clamps).
+// Panels of nb <= PNB columns are factored in LDS.  Thread t owns the panel
+// rows q = t + s BT (s < PR): only it writes them, and each row keeps its
+// place in LDS while its logical position pos within the panel lives in the
+// owner's registers (GEPP's interchanges act on these integers only).  Per
+// column j, one barrier:
+//   - every thread takes its best candidate (largest |a_qj| among its rows
+//     with pos >= j, lowest pos on ties, NaN below every number), the wave
+//     reduces (value, pos) by lane exchanges, and the lane holding the winner
+//     publishes (value, pos, row) in the wave's slot (double-buffered by
+//     column parity);
+//   - after the barrier every thread reduces the slots the same way,
+//     exchanges positions j and p, and updates its rows with pos > j from the
+//     pivot row, read in place (its owner never writes it again).
+// The panel is then written to its rows' final positions; the rows the
+// panel's interchanges change in the columns outside it are rewritten by one
+// gather per column, loads in flight before the stores.  Trailing updates in
+// recursive order (below).  Returns the first zero pivot column + 1, or 0.
+// nb >= 1 (the caller clamps).
+constexpr int PR = BNMAX / BT;   // panel rows per thread
 template <typename T>
 BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
-  n = uni(n); lda = uni(lda); nb = uni(nb);
-  const int tid = bb_tid();
+  n = uni(n); lda = uni(lda); nb = imin(uni(nb), PNB);
+  const int tid = bb_tid(), lane = tid & 63, wave = tid >> 6;
   int info = 0;
   for (int r = tid; r < n; r += BT) sm.perm[r] = r;
   for (int k0 = 0, t = 0; k0 < n; k0 += nb, ++t) {
     const int kb = imin(nb, n - k0), m = n - k0;
     // panel (rows k0.., columns k0..k0+kb) into LDS: P[r][c]
     T* P = sm.panel;
-    for (int e = tid; e < m * kb; e += BT) {
-      const int r = e / kb, c = e % kb;
-      P[r * PP + c] = A[(long long)(k0 + r) * lda + k0 + c];
+    const int pe = m * kb;
+    for (int base = tid; base < pe; base += SU * BT) {
+      T v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int e = imin(base + u * BT, pe - 1), r = e / kb;
+        v[u] = A[(long long)(k0 + r) * lda + k0 + (e - r * kb)];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int e = base + u * BT, r = e / kb;
+        if (e < pe) P[r * PP + (e - r * kb)] = v[u];
+      }
     }
-    for (int r = tid; r < m; r += BT) sm.cont[r] = r;
+    int pos[PR];
+#pragma unroll
+    for (int s = 0; s < PR; ++s) pos[s] = tid + s * BT < m ? tid + s * BT : -1;
     if (tid == 0) sm.tl_n = 0;
     bb_sync();
     for (int j = 0; j < kb; ++j) {
-      T best = T(-1);
-      int bi = INT_MAX;
-      for (int r = j + tid; r < m; r += BT) {
-        const T a = std::fabs(P[r * PP + j]);
-        if (a > best) { best = a; bi = r; }
+      const int par = j & 1;
+      // candidate among this thread's rows
+      T bv = T(-2);
+      int bp = INT_MAX, bq = 0;
+#pragma unroll
+      for (int s = 0; s < PR; ++s)
+        if (pos[s] >= j) {
+          const int q = tid + s * BT;
+          const T a0 = std::fabs(P[q * PP + j]);
+          const T a = a0 == a0 ? a0 : T(-1);
+          if (a > bv || (a == bv && pos[s] < bp)) { bv = a; bp = pos[s]; bq = q; }
+        }
+      // wave reduction; the lane holding the winner publishes it
+      T wv = bv;
+      int wp = bp;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const T ov = bb_shfl_xor(wv, off);
+        const int op = bb_shfl_xor(wp, off);
+        if (ov > wv || (ov == wv && op < wp)) { wv = ov; wp = op; }
       }
-      const int p = wg_argmax<T>(sm, best, bi);
-      const int pr = (p == INT_MAX) ? j : p;      // an all-NaN column keeps row j
-      if (pr != j) {
-        for (int c = tid; c < kb; c += BT) {
-          const T t = P[j * PP + c];
-          P[j * PP + c] = P[pr * PP + c];
-          P[pr * PP + c] = t;
+      if (wp == INT_MAX) {
+        if (lane == 0) {
+          sm.slot_v[par][wave] = T(-2);
+          sm.slot_p[par][wave] = INT_MAX;
         }
-        if (tid == 0) {
-          const int t1 = sm.cont[j];
-          sm.cont[j] = sm.cont[pr];
-          sm.cont[pr] = t1;
-          const int t2 = sm.perm[k0 + j];
-          sm.perm[k0 + j] = sm.perm[k0 + pr];
-          sm.perm[k0 + pr] = t2;
-        }
+      } else if (bp == wp) {   // positions are distinct: exactly one lane
+        sm.slot_v[par][wave] = wv;
+        sm.slot_p[par][wave] = wp;
+        sm.slot_q[par][wave] = bq;
       }
       bb_sync();
-      const T d = P[j * PP + j];
+      T gv = sm.slot_v[par][0];
+      int gp = sm.slot_p[par][0], gq = sm.slot_q[par][0];
+#pragma unroll
+      for (int w = 1; w < BT / 64; ++w) {
+        const T ov = sm.slot_v[par][w];
+        const int op = sm.slot_p[par][w];
+        if (ov > gv || (ov == gv && op < gp)) { gv = ov; gp = op; gq = sm.slot_q[par][w]; }
+      }
+      // the row at position j is always a candidate, so gp < INT_MAX
+      const int p = gp;
+#pragma unroll
+      for (int s = 0; s < PR; ++s) pos[s] = pos[s] == p ? j : (pos[s] == j ? p : pos[s]);
+      const T* prow = P + gq * PP;
+      const T d = prow[j];
       if (d == T(0)) {
         if (!info) info = k0 + j + 1;
       } else {
         // row segments pass through registers eight columns at a time, so
         // the LDS reads of a chunk are in flight together before its writes
         const T rd = T(1) / d;
-        for (int r = j + 1 + tid; r < m; r += BT) {
-          const T l = P[r * PP + j] * rd;
-          P[r * PP + j] = l;
-          for (int c0 = j + 1; c0 < kb; c0 += 8) {
-            T rv[8], pv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int c = imin(c0 + u, kb - 1);
-              rv[u] = P[r * PP + c];
-              pv[u] = P[j * PP + c];
+        for (int s = 0; s < PR; ++s)
+          if (pos[s] > j) {
+            T* row = P + (tid + s * BT) * PP;
+            const T l = row[j] * rd;
+            row[j] = l;
+            for (int c0 = j + 1; c0 < kb; c0 += 8) {
+              T rv[8], pv[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int c = imin(c0 + u, kb - 1);
+                rv[u] = row[c];
+                pv[u] = prow[c];
+              }
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                if (c0 + u < kb) row[c0 + u] = rv[u] - l * pv[u];
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (c0 + u < kb) P[r * PP + c0 + u] = rv[u] - l * pv[u];
           }
+      }
+    }
+    // final positions: the store below reads them; the permutation and the
+    // list of moved rows (at most 2 kb) follow from them
+    int op[PR];
+#pragma unroll
+    for (int s = 0; s < PR; ++s) op[s] = pos[s] >= 0 ? sm.perm[k0 + tid + s * BT] : 0;
+#pragma unroll
+    for (int s = 0; s < PR; ++s)
+      if (pos[s] >= 0) sm.rowpos[tid + s * BT] = pos[s];
+    bb_sync();
+#pragma unroll
+    for (int s = 0; s < PR; ++s) {
+      const int q = tid + s * BT;
+      if (pos[s] >= 0 && pos[s] != q) {
+        sm.perm[k0 + pos[s]] = op[s];
+        const int e = bb_atomic_add(&sm.tl_n, 1);
+        if (e < 2 * PNB) {
+          sm.tl_dst[e] = k0 + pos[s];
+          sm.tl_src[e] = k0 + q;
         }
       }
-      bb_sync();
     }
-    for (int e = tid; e < m * kb; e += BT) {
-      const int r = e / kb, c = e % kb;
-      A[(long long)(k0 + r) * lda + k0 + c] = P[r * PP + c];
-    }
-    // the panel's interchanges on the columns left and right of it: each of
-    // its kb interchanges changes at most two rows, so at most 2 kb rows move
-    for (int r = tid; r < m; r += BT)
-      if (sm.cont[r] != r) {
-        const int e = bb_atomic_add(&sm.tl_n, 1);
-        sm.tl_dst[e] = k0 + r;
-        sm.tl_src[e] = k0 + sm.cont[r];
+    for (int base = tid; base < pe; base += SU * BT) {
+      T v[SU];
+      int dr[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int e = imin(base + u * BT, pe - 1), r = e / kb;
+        v[u] = P[r * PP + (e - r * kb)];
+        dr[u] = sm.rowpos[r];
       }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int e = base + u * BT, r = e / kb;
+        if (e < pe) A[(long long)(k0 + dr[u]) * lda + k0 + (e - r * kb)] = v[u];
+      }
+    }
     bb_sync();
     // each thread moves its own columns, staged in the (now free) panel
-    // buffer: all loads of a column are issued before any of its stores
+    // buffer: all loads of a column are issued, SU at a time, before any of
+    // its stores
     const int cnt = imin(uni(sm.tl_n), 2 * PNB);
     for (int c = tid; c < n; c += BT) {
       if (c >= k0 && c < k0 + kb) continue;
       T* S = P;   // 2 PNB rows x BT columns fit the buffer; a thread's second column reuses its slots
-      for (int e = 0; e < cnt; ++e) S[e * BT + tid] = A[(long long)sm.tl_src[e] * lda + c];
-      for (int e = 0; e < cnt; ++e) A[(long long)sm.tl_dst[e] * lda + c] = S[e * BT + tid];
+      for (int e0 = 0; e0 < cnt; e0 += SU) {
+        T v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) v[u] = A[(long long)sm.tl_src[imin(e0 + u, cnt - 1)] * lda + c];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+          if (e0 + u < cnt) S[(e0 + u) * BT + tid] = v[u];
+      }
+      for (int e0 = 0; e0 < cnt; e0 += SU) {
+        T v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) v[u] = S[imin(e0 + u, cnt - 1) * BT + tid];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+          if (e0 + u < cnt) A[(long long)sm.tl_dst[e0 + u] * lda + c] = v[u];
+      }
     }
     bb_sync();
     // Updates in the order of the recursive algorithm (factor the left half,
@@ -475,9 +543,19 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
 template <typename T>
 BB_IN void wg_gather_rows(int n, int ncols, const T* src, int lds, const int* perm, T* dst, int ldd) {
   n = uni(n); ncols = uni(ncols); lds = uni(lds); ldd = uni(ldd);
-  for (int e = bb_tid(); e < n * ncols; e += BT) {
-    const int r = e / ncols, c = e % ncols;
-    dst[(long long)r * ldd + c] = src[(long long)perm[r] * lds + c];
+  const int total = n * ncols;
+  for (int base = bb_tid(); base < total; base += SU * BT) {
+    T v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = imin(base + u * BT, total - 1), r = e / ncols;
+      v[u] = src[(long long)perm[r] * lds + (e - r * ncols)];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = base + u * BT, r = e / ncols;
+      if (e < total) dst[(long long)r * ldd + (e - r * ncols)] = v[u];
+    }
   }
   bb_sync();
 }
@@ -486,20 +564,43 @@ BB_IN void wg_gather_rows(int n, int ncols, const T* src, int lds, const int* pe
 template <typename T>
 BB_IN void wg_scatter_cols(int n, const T* src, const int* perm, T* dst) {
   n = uni(n);
-  for (int e = bb_tid(); e < n * n; e += BT) {
-    const int i = e / n, r = e % n;
-    dst[(long long)i * n + perm[r]] = src[e];
+  const int total = n * n;
+  for (int base = bb_tid(); base < total; base += SU * BT) {
+    T v[SU];
+    int pc[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = imin(base + u * BT, total - 1);
+      v[u] = src[e];
+      pc[u] = perm[e % n];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = base + u * BT;
+      if (e < total) dst[(long long)(e / n) * n + pc[u]] = v[u];
+    }
   }
   bb_sync();
 }
 
-// a[j][i] = -a[i][j] above the diagonal (i > j), from the lower triangle
+// a[j][i] = -a[i][j] above the diagonal (i > j), from the lower triangle (the
+// entries read and the entries written are disjoint)
 template <typename T>
 BB_IN void wg_mirror_skew(int n, T* a) {
   n = uni(n);
-  for (int e = bb_tid(); e < n * n; e += BT) {
-    const int i = e / n, j = e % n;
-    if (j < i) a[(long long)j * n + i] = -a[e];
+  const int total = n * n;
+  for (int base = bb_tid(); base < total; base += SU * BT) {
+    T v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = imin(base + u * BT, total - 1), i = e / n;
+      v[u] = e - i * n < i ? a[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = base + u * BT, i = e / n, j = e - i * n;
+      if (e < total && j < i) a[(long long)j * n + i] = -v[u];
+    }
   }
   bb_sync();
 }
@@ -580,7 +681,15 @@ BB_FN int wg_potrf(Smem<T>& sm, int n, T* A, int lda, int nb) {
 template <typename T>
 BB_IN void wg_copy(int n, const T* src, T* dst) {
   n = uni(n);
-  for (int e = bb_tid(); e < n * n; e += BT) dst[e] = src[e];
+  const int total = n * n;
+  for (int base = bb_tid(); base < total; base += SU * BT) {
+    T v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) v[u] = src[imin(base + u * BT, total - 1)];
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+      if (base + u * BT < total) dst[base + u * BT] = v[u];
+  }
   bb_sync();
 }
 template <typename T>

@@ -148,6 +148,21 @@ def test_emulated_batch_matches_oracle(emu, dtype):
             assert e <= tol, (A.shape[0], kinds[i], nb, e)
 
 
+def test_emulated_tall_panels_match_oracle(emu):
+    """Orders above the workgroup size: every thread holds two rows of each LU
+    panel (one of them padding for the ragged last rows), and panels of the
+    default width 16 end in a ragged 12-column panel."""
+    mats = [inputs.general(300, 7), inputs.hpd(300, 8), inputs.general(257, 9)]
+    kinds = [0, 1, 0]
+    err, Xr, Xi, info, bars = run(emu, mats, kinds, dtype=np.float64, grid=2, nb=16)
+    assert err == 0, ERR[err]
+    assert np.all(info == 0)
+    for i, (A, B) in enumerate(mats):
+        r = oracle.cinv_lu(A, B) if kinds[i] == 0 else oracle.cinv_chol(A, B)
+        kC = np.linalg.cond(A + B @ np.linalg.solve(A, B))
+        assert relF(Xr[i], Xi[i], r[0], r[1]) <= max(1e-10, 16 * U64 * kC), i
+
+
 def test_checker_catches_known_defects(emu):
     """The emulation is not vacuous: a skipped barrier, a half-wave lane
     exchange and a wave that leaves before a barrier are each reported."""
