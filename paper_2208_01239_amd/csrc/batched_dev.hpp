@@ -352,6 +352,7 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
 // recursive order (below).  Returns the first zero pivot column + 1, or 0.
 // nb >= 1 (the caller clamps).
 constexpr int PR = BNMAX / BT;   // panel rows per thread
+constexpr int RG = BT / PNB;     // rows moved together by the panel load and store
 template <typename T>
 BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
   n = uni(n); lda = uni(lda); nb = imin(uni(nb), PNB);
@@ -360,21 +361,18 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
   for (int r = tid; r < n; r += BT) sm.perm[r] = r;
   for (int k0 = 0, t = 0; k0 < n; k0 += nb, ++t) {
     const int kb = imin(nb, n - k0), m = n - k0;
-    // panel (rows k0.., columns k0..k0+kb) into LDS: P[r][c]
+    // panel (rows k0.., columns k0..k0+kb) into LDS: P[r][c]; thread t
+    // moves column t % PNB of rows t / PNB + i RG
     T* P = sm.panel;
-    const int pe = m * kb;
-    for (int base = tid; base < pe; base += SU * BT) {
+    const int pc = tid % PNB, pr0 = tid / PNB;
+    const bool pcol = pc < kb;
+    for (int rb = pr0; rb < m; rb += SU * RG) {
       T v[SU];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int e = imin(base + u * BT, pe - 1), r = e / kb;
-        v[u] = A[(long long)(k0 + r) * lda + k0 + (e - r * kb)];
-      }
+      for (int u = 0; u < SU; ++u) v[u] = A[(long long)(k0 + imin(rb + u * RG, m - 1)) * lda + k0 + imin(pc, kb - 1)];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int e = base + u * BT, r = e / kb;
-        if (e < pe) P[r * PP + (e - r * kb)] = v[u];
-      }
+      for (int u = 0; u < SU; ++u)
+        if (pcol && rb + u * RG < m) P[(rb + u * RG) * PP + pc] = v[u];
     }
     int pos[PR];
 #pragma unroll
@@ -392,7 +390,10 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
           const int q = tid + s * BT;
           const T a0 = std::fabs(P[q * PP + j]);
           const T a = a0 == a0 ? a0 : T(-1);
-          if (a > bv || (a == bv && pos[s] < bp)) { bv = a; bp = pos[s]; bq = q; }
+          const bool take = (a > bv) | ((a == bv) & (pos[s] < bp));
+          bv = take ? a : bv;
+          bp = take ? pos[s] : bp;
+          bq = take ? q : bq;
         }
       // wave reduction; the lane holding the winner publishes it
       T wv = bv;
@@ -401,7 +402,9 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
       for (int off = 32; off >= 1; off >>= 1) {
         const T ov = bb_shfl_xor(wv, off);
         const int op = bb_shfl_xor(wp, off);
-        if (ov > wv || (ov == wv && op < wp)) { wv = ov; wp = op; }
+        const bool take = (ov > wv) | ((ov == wv) & (op < wp));
+        wv = take ? ov : wv;
+        wp = take ? op : wp;
       }
       if (wp == INT_MAX) {
         if (lane == 0) {
@@ -419,8 +422,11 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
 #pragma unroll
       for (int w = 1; w < BT / 64; ++w) {
         const T ov = sm.slot_v[par][w];
-        const int op = sm.slot_p[par][w];
-        if (ov > gv || (ov == gv && op < gp)) { gv = ov; gp = op; gq = sm.slot_q[par][w]; }
+        const int op = sm.slot_p[par][w], oq = sm.slot_q[par][w];
+        const bool take = (ov > gv) | ((ov == gv) & (op < gp));
+        gv = take ? ov : gv;
+        gp = take ? op : gp;
+        gq = take ? oq : gq;
       }
       // the row at position j is always a candidate, so gp < INT_MAX
       const int p = gp;
@@ -476,20 +482,18 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
         }
       }
     }
-    for (int base = tid; base < pe; base += SU * BT) {
+    for (int rb = pr0; rb < m; rb += SU * RG) {
       T v[SU];
       int dr[SU];
 #pragma unroll
       for (int u = 0; u < SU; ++u) {
-        const int e = imin(base + u * BT, pe - 1), r = e / kb;
-        v[u] = P[r * PP + (e - r * kb)];
+        const int r = imin(rb + u * RG, m - 1);
+        v[u] = P[r * PP + pc];
         dr[u] = sm.rowpos[r];
       }
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int e = base + u * BT, r = e / kb;
-        if (e < pe) A[(long long)(k0 + dr[u]) * lda + k0 + (e - r * kb)] = v[u];
-      }
+      for (int u = 0; u < SU; ++u)
+        if (pcol && rb + u * RG < m) A[(long long)(k0 + dr[u]) * lda + k0 + pc] = v[u];
     }
     bb_sync();
     // each thread moves its own columns, staged in the (now free) panel
