@@ -276,6 +276,18 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
       const bool in = mode == 2 ? c >= r : c <= r;
       D[i * PP + k] = in ? L[(long long)(k0 + r) * ldl + k0 + c] : T(0);
     }
+    // A leaf that completes a group of one (t even) also applies its update
+    // to the next leaf's rows, a product of depth kb, in registers: each
+    // thread subtracts E x from the next rows of its columns, with
+    // E(i, k) = op(T)(e0 + i, k0 + k) staged after the diagonal block.
+    const bool g1 = (t & 1) == 0;
+    const int e0 = fwd ? k0 + kb : imax(0, k0 - nb);
+    const int ne = !g1 ? 0 : fwd ? imin(nb, n - e0) : k0 - e0;
+    T* E = sm.panel + XNB * PP;
+    for (int e = tid; e < ne * kb; e += BT) {
+      const int i = e / kb, k = e % kb;
+      E[i * PP + k] = mode == 1 ? L[(long long)(k0 + k) * ldl + e0 + i] : L[(long long)(e0 + i) * ldl + k0 + k];
+    }
     bb_sync();
     // B = I (idrhs): the solution is lower triangular, so rows k0 .. k0 + kb
     // have nonzeros only in the columns left of k0 + kb
@@ -307,9 +319,24 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
 #pragma unroll
       for (int i = 0; i < XNB; ++i)
         if (i < kb) B[(long long)(k0 + i) * ldb + j] = x[i];
+      for (int i0 = 0; i0 < ne; i0 += 4) {   // four rows at a time (registers)
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = B[(long long)(e0 + imin(i0 + u, ne - 1)) * ldb + j];
+#pragma unroll
+        for (int k = 0; k < XNB; ++k)
+          if (k < kb) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] -= E[imin(i0 + u, ne - 1) * PP + k] * x[k];
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < ne) B[(long long)(e0 + i0 + u) * ldb + j] = v[u];
+      }
     }
     bb_sync();
     const int g = (t + 1) & -(t + 1);   // leaves in the group this leaf completes
+    if (g == 1) continue;               // applied above
     if (fwd) {
       // done: rows [c0, c1); next: rows [c1, r1) -= op(T)[c1:r1, c0:c1] X[c0:c1]
       const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
