@@ -358,6 +358,68 @@ BB_FN void wg_trsm(Smem<T>& sm, int mode, int n, int nrhs, const T* L, int ldl, 
   }
 }
 
+// The update of the next nb <= PNB columns [c1, c1 + n2) by a finished LU
+// panel [k0, k0 + kb) (a group of one in the recursive order), on the vector
+// units: U12 = L11^{-1} A12 (L11 unit lower) on the panel's rows, then
+// A22 -= L21 U12 below them.  Inline: an out-of-line product call would save
+// and restore the callee-saved registers for a depth-kb update.
+template <typename T>
+BB_IN void wg_lu_update1(Smem<T>& sm, int n, T* A, int lda, int k0, int kb, int c1, int n2) {
+  const int tid = bb_tid();
+  T* Ls = sm.panel;               // L11, pitch PP
+  T* Us = sm.panel + PNB * PP;    // A12, then U12
+  {
+    const int i = tid / PNB, c = tid % PNB;   // kb x PNB <= BT entries: one per thread
+    if (i < kb) {
+      if (c < kb) Ls[i * PP + c] = A[(long long)(k0 + i) * lda + k0 + c];
+      if (c < n2) Us[i * PP + c] = A[(long long)(k0 + i) * lda + c1 + c];
+    }
+  }
+  bb_sync();
+  if (tid < n2) {
+    T x[PNB];
+#pragma unroll
+    for (int i = 0; i < PNB; ++i) x[i] = Us[imin(i, kb - 1) * PP + tid];
+#pragma unroll
+    for (int i = 0; i < PNB; ++i)
+      if (i < kb) {
+        T v = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= Ls[i * PP + k] * x[k];
+        x[i] = v;
+      }
+#pragma unroll
+    for (int i = 0; i < PNB; ++i)
+      if (i < kb) {
+        Us[i * PP + tid] = x[i];
+        A[(long long)(k0 + i) * lda + c1 + tid] = x[i];
+      }
+  }
+  bb_sync();
+  for (int r = c1 + tid; r < n; r += BT) {
+    T l[PNB];
+    const T* lrow = A + (long long)r * lda + k0;
+#pragma unroll
+    for (int k = 0; k < PNB; ++k) l[k] = lrow[imin(k, kb - 1)];
+    T* arow = A + (long long)r * lda + c1;
+    for (int cb = 0; cb < n2; cb += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = arow[imin(cb + u, n2 - 1)];
+#pragma unroll
+      for (int k = 0; k < PNB; ++k)
+        if (k < kb) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] -= l[k] * Us[k * PP + imin(cb + u, n2 - 1)];
+        }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (cb + u < n2) arow[cb + u] = v[u];
+    }
+  }
+  bb_sync();
+}
+
 // ------------------------------------------------------------- LU (GEPP)
 // P A = L U in place; perm_out[r] = the row of A that row r of P A is.
 // Panels of nb <= PNB columns are factored in LDS.  Thread t owns the panel
@@ -558,7 +620,9 @@ BB_FN int wg_getrf(Smem<T>& sm, int n, T* A, int lda, int* perm_out, int nb) {
     // log2(n / nb) times instead of n / nb times.
     const int g = (t + 1) & -(t + 1);
     const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
-    if (c1 < n) {
+    if (c1 < n && g == 1) {
+      wg_lu_update1<T>(sm, n, A, lda, k0, kb, c1, r1 - c1);
+    } else if (c1 < n) {
       wg_trsm<T>(sm, 0, c1 - c0, r1 - c1, A + (long long)c0 * lda + c0, lda, true, A + (long long)c0 * lda + c1, lda,
                  nb);
       wg_gemm<T>(sm, n - c1, r1 - c1, c1 - c0, T(-1), A + (long long)c1 * lda + c0, lda, false,
@@ -636,6 +700,43 @@ BB_IN void wg_mirror_skew(int n, T* a) {
   bb_sync();
 }
 
+// The update of the next nb <= XNB block column [c1, c1 + n2) by a finished
+// Cholesky block column [k0, k0 + kb) (a group of one in the recursive order),
+// on the vector units: A[c1:, c1:c1+n2] -= L[c1:, k0:c1] L[c1:c1+n2, k0:c1]^T
+// (entries above the diagonal included, never read).
+template <typename T>
+BB_IN void wg_chol_update1(Smem<T>& sm, int n, T* A, int lda, int k0, int kb, int c1, int n2) {
+  const int tid = bb_tid();
+  T* Lb = sm.panel;   // L[c1 + c][k0 + k] at Lb[c * PP + k]
+  {
+    const int c = tid / XNB, k = tid % XNB;   // n2 x XNB <= BT entries: one per thread
+    if (c < n2 && k < kb) Lb[c * PP + k] = A[(long long)(c1 + c) * lda + k0 + k];
+  }
+  bb_sync();
+  for (int r = c1 + tid; r < n; r += BT) {
+    T l[XNB];
+    const T* lrow = A + (long long)r * lda + k0;
+#pragma unroll
+    for (int k = 0; k < XNB; ++k) l[k] = lrow[imin(k, kb - 1)];
+    T* arow = A + (long long)r * lda + c1;
+    for (int cb = 0; cb < n2; cb += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = arow[imin(cb + u, n2 - 1)];
+#pragma unroll
+      for (int k = 0; k < XNB; ++k)
+        if (k < kb) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] -= l[k] * Lb[imin(cb + u, n2 - 1) * PP + k];
+        }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (cb + u < n2) arow[cb + u] = v[u];
+    }
+  }
+  bb_sync();
+}
+
 // ------------------------------------------------------------ Cholesky
 // A = L L^T in place (lower triangle).  Returns the first non-positive pivot's
 // column (1-based), or 0.  nb >= 1 (the caller clamps).
@@ -702,8 +803,11 @@ BB_FN int wg_potrf(Smem<T>& sm, int n, T* A, int lda, int nb) {
       // entries above the diagonal of that block are updated too and never read)
       const int g = (t + 1) & -(t + 1);
       const int c1 = k0 + kb, c0 = c1 - imin(g * nb, c1), r1 = imin(c1 + g * nb, n);
-      wg_gemm<T>(sm, n - c1, r1 - c1, c1 - c0, T(-1), A + (long long)c1 * lda + c0, lda, false,
-                 A + (long long)c1 * lda + c0, lda, true, T(1), A + (long long)c1 * lda + c1, lda);
+      if (g == 1)
+        wg_chol_update1<T>(sm, n, A, lda, k0, kb, c1, r1 - c1);
+      else
+        wg_gemm<T>(sm, n - c1, r1 - c1, c1 - c0, T(-1), A + (long long)c1 * lda + c0, lda, false,
+                   A + (long long)c1 * lda + c0, lda, true, T(1), A + (long long)c1 * lda + c1, lda);
     }
   }
   return bad;
