@@ -182,7 +182,34 @@ BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, 
       bb_sync();
     }
     // epilogue, one block row at a time: its reads of C are all issued
-    // before its writes
+    // before its writes.  Interior tiles take branch-free code: a store under
+    // a per-lane condition sits in a block of its own, and the compiler then
+    // waits for every earlier memory operation before it.
+    if (tm + TM <= M && tn + TN <= N) {   // uniform
+#pragma unroll
+      for (int a = 0; a < BA; ++a) {
+        T cv[4][BB];
+        if (beta != T(0)) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < BB; ++b)
+              cv[v][b] = C[(long long)(tm + wm + 16 * a + Mfma<T>::row(lane, v)) * ldc + tn + wn + 16 * b + (lane & 15)];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < BB; ++b) cv[v][b] = T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int b = 0; b < BB; ++b)
+            C[(long long)(tm + wm + 16 * a + Mfma<T>::row(lane, v)) * ldc + tn + wn + 16 * b + (lane & 15)] =
+                alpha * acc[a][b][v] + beta * cv[v][b];
+      }
+      continue;
+    }
 #pragma unroll
     for (int a = 0; a < BA; ++a) {
       T cv[4][BB];
