@@ -33,6 +33,7 @@ namespace frob {
 namespace bat {
 #define BB_FN __device__ __noinline__
 #define BB_IN __device__ __forceinline__
+#define BB_GLOBAL __attribute__((address_space(1)))
 __device__ __forceinline__ int bb_tid() { return threadIdx.x; }
 __device__ __forceinline__ void bb_sync() { __syncthreads(); }
 template <class V>

@@ -13,6 +13,9 @@
 //   d4   bb_mfma(double a, double b, d4 c)   16x16x4 FP64 matrix-core product
 //   f4   bb_mfma(float a, float b, f4 c)     16x16x4 FP32 matrix-core product
 //   int  bb_atomic_add(int* p, int v)        atomic fetch-and-add
+//   BB_GLOBAL                  address-space qualifier of device-memory pointers
+//                              (global memory on the GPU: loads and stores of
+//                              their own kind, counted apart from LDS accesses)
 // and the vector types frob::d4 / frob::f4.  batched.hip maps them to the
 // gfx950 intrinsics; the test suite maps them to a cooperative CPU emulation of
 // one or more workgroups that checks every barrier is reached by every thread
@@ -96,8 +99,8 @@ BB_IN bool uni(bool v) { return bb_first((int)v) != 0; }
 // one barrier separates the k-steps.  Edges: loads at clamped in-range
 // addresses, values outside the matrix zeroed when staged.
 template <typename T, int WM, int WN, int BA, int BB>
-BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int lda, bool ta, const T* B,
-                         int ldb, bool tb, T beta, T* C, int ldc, bool lower) {
+BB_FN void wg_gemm_tiles(Smem<T>& sm, int M, int N, int K, T alpha, BB_GLOBAL const T* A, int lda, bool ta,
+                         BB_GLOBAL const T* B, int ldb, bool tb, T beta, BB_GLOBAL T* C, int ldc, bool lower) {
   typedef typename Mfma<T>::acc acc_t;
   constexpr int TM = WM * BA * 16, TN = WN * BB * 16;
   constexpr int PA = TM + 4, PB = TN + 4;          // LDS pitches of the k-major tiles
@@ -246,26 +249,32 @@ BB_FN void wg_gemm(Smem<T>& sm, int M, int N, int K, T alpha, const T* A, int ld
                    bool tb, T beta, T* C, int ldc, bool lower = false) {
   M = uni(M); N = uni(N); K = uni(K); lda = uni(lda); ldb = uni(ldb); ldc = uni(ldc); ta = uni(ta); tb = uni(tb);
   lower = uni(lower);
+  // device-memory pointers for the tiles: their loads and stores are then
+  // global accesses, counted apart from the LDS accesses of the k-loop, so
+  // the next k-step's loads stay in flight while its fragments are read
+  BB_GLOBAL const T* gA = (BB_GLOBAL const T*)A;
+  BB_GLOBAL const T* gB = (BB_GLOBAL const T*)B;
+  BB_GLOBAL T* gC = (BB_GLOBAL T*)C;
   if (M <= 0 || N <= 0) {
     bb_sync();
     return;
   }
   if (M <= 16 && N > 64)
-    wg_gemm_tiles<T, 1, 4, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 16 x 256
+    wg_gemm_tiles<T, 1, 4, 1, 4>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 16 x 256
   else if (M <= 32 && N > 64)
-    wg_gemm_tiles<T, 2, 2, 1, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 32 x 128
+    wg_gemm_tiles<T, 2, 2, 1, 4>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 32 x 128
   else if (N <= 16 && M > 64)
-    wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 256 x 16
+    wg_gemm_tiles<T, 4, 1, 4, 1>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 256 x 16
   else if (N <= 32 && M > 64)
-    wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 128 x 32
+    wg_gemm_tiles<T, 2, 2, 4, 1>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 128 x 32
   else if (M > 64 && N > 64 && sizeof(T) == 8)
     // FP64: 128 x 64; the 128 x 128 tile's accumulators and prefetch registers
     // exceed the register share of two waves per SIMD and spill in the k-loop
-    wg_gemm_tiles<T, 2, 2, 4, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);
+    wg_gemm_tiles<T, 2, 2, 4, 2>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);
   else if (M > 64 && N > 64)
-    wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 128 x 128
+    wg_gemm_tiles<T, 2, 2, 4, 4>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 128 x 128
   else
-    wg_gemm_tiles<T, 2, 2, 2, 2>(sm, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, lower);      // 64 x 64
+    wg_gemm_tiles<T, 2, 2, 2, 2>(sm, M, N, K, alpha, gA, lda, ta, gB, ldb, tb, beta, gC, ldc, lower);      // 64 x 64
 }
 
 // ------------------------------------------------------- triangular solves

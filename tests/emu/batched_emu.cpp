@@ -194,6 +194,7 @@ namespace frob {
 namespace bat {
 #define BB_FN __attribute__((noinline))
 #define BB_IN inline
+#define BB_GLOBAL
 inline int bb_tid() { return emu::M->f[emu::M->cur].tid; }
 __attribute__((noinline)) void bb_sync() {
   emu::Fiber& me = emu::M->f[emu::M->cur];
