@@ -64,8 +64,10 @@ constexpr int gemm_min_blocks(int BM, int BN, int BK, bool TA, bool TB) {
 }
 
 // One output tile t (an index in the XCD-contiguous, grouped order) of the
-// product; smem holds gemm_lds_bytes(BM, BN, BK, TA, TB) bytes.
-template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK>
+// product; smem holds gemm_lds_bytes(BM, BN, BK, TA, TB) bytes.  PLAIN: no
+// triangular operand and no row or column indirection (known at compile time,
+// so the k-loop carries none of their masking and index loads).
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PLAIN = false>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, double* __restrict__ smem) {
   constexpr int KP = BK / 2;       // 16-byte pairs per row of a row-band tile
   constexpr int RP = 256 / KP;     // rows of a row-band tile per pass
@@ -100,16 +102,17 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
   const double* __restrict__ Ap = g.A.p + z * g.sA;
   const double* __restrict__ Bp = g.B.p + z * g.sB;
   double* __restrict__ Cp = g.C.p + z * g.sC;
-  const int* __restrict__ rA = g.A.rows ? g.A.rows + z * g.rsA : nullptr;
-  const int* __restrict__ rB = g.B.rows ? g.B.rows + z * g.rsB : nullptr;
-  const int* __restrict__ rC = g.C.rows ? g.C.rows + z * g.rsC : nullptr;
+  const int* __restrict__ rA = !PLAIN && g.A.rows ? g.A.rows + z * g.rsA : nullptr;
+  const int* __restrict__ rB = !PLAIN && g.B.rows ? g.B.rows + z * g.rsB : nullptr;
+  const int* __restrict__ rC = !PLAIN && g.C.rows ? g.C.rows + z * g.rsC : nullptr;
+  const int triA = PLAIN ? TRI_NONE : g.triA, triB = PLAIN ? TRI_NONE : g.triB;
   const int M = g.M, N = g.N;
 
   int kbeg = 0, kend = g.K;
-  if (g.triA == TRI_UPPER || g.triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
-  if (g.triA == TRI_LOWER || g.triA == TRI_LOWER_UNIT) kend = min(kend, bm0 + BM);
-  if (g.triB == TRI_LOWER || g.triB == TRI_LOWER_UNIT) kbeg = max(kbeg, bn0);
-  if (g.triB == TRI_UPPER || g.triB == TRI_UPPER_UNIT) kend = min(kend, bn0 + BN);
+  if (triA == TRI_UPPER || triA == TRI_UPPER_UNIT) kbeg = max(kbeg, bm0);
+  if (triA == TRI_LOWER || triA == TRI_LOWER_UNIT) kend = min(kend, bm0 + BM);
+  if (triB == TRI_LOWER || triB == TRI_LOWER_UNIT) kbeg = max(kbeg, bn0);
+  if (triB == TRI_UPPER || triB == TRI_UPPER_UNIT) kend = min(kend, bn0 + BN);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 
   const int tid = threadIdx.x;
@@ -171,6 +174,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
   const int* rBs = rB ? rB : reinterpret_cast<const int*>(Bp);
   int ixa[KA], ixb[KB];
   auto load_index = [&](int kt) {
+    if constexpr (PLAIN) return;
     if (TA) {
       constexpr int TPR = BM / 2, RPP = 256 / TPR;
 #pragma unroll
@@ -235,9 +239,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
       }
       double x = (ok && gi < M && gk < kend) ? ra[p][0] : 0.0;
       double y = (ok && gi + di < M && gk + dk < kend) ? ra[p][1] : 0.0;
-      if (g.triA) {
-        x = tri_mask(x, g.triA, gi, gk);
-        y = tri_mask(y, g.triA, gi + di, gk + dk);
+      if (triA) {
+        x = tri_mask(x, triA, gi, gk);
+        y = tri_mask(y, triA, gi + di, gk + dk);
       }
       *reinterpret_cast<double2*>(As + off) = double2{x, y};
     }
@@ -261,9 +265,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
       }
       double x = (ok && gj < N && gk < kend) ? rb[p][0] : 0.0;
       double y = (ok && gj + dj < N && gk + dk < kend) ? rb[p][1] : 0.0;
-      if (g.triB) {
-        x = tri_mask(x, g.triB, gk, gj);
-        y = tri_mask(y, g.triB, gk + dk, gj + dj);
+      if (triB) {
+        x = tri_mask(x, triB, gk, gj);
+        y = tri_mask(y, triB, gk + dk, gj + dj);
       }
       *reinterpret_cast<double2*>(Bs + off) = double2{x, y};
     }
@@ -322,7 +326,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
     const int jc = min(bn0 + wn0 + b * 16 + (lane & 15), N - 1);
-    pc[b] = g.C.cols ? g.C.cols[jc] : jc;
+    pc[b] = !PLAIN && g.C.cols ? g.C.cols[jc] : jc;
   }
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
@@ -360,7 +364,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
 // tile.  PERSIST: a capped grid (GridCapScope) whose blocks take several
 // tiles, in steps of the number of blocks per XCD, and leave compute units
 // free for concurrent work.
-template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PERSIST>
+template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PERSIST, bool PLAIN = false>
 __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_gemm_f64(GemmF64Params g) {
   __shared__ __attribute__((aligned(16))) double smem[gemm_lds_bytes(BM, BN, BK, TA, TB) / 8];
   const int tiles = g.tilesM * g.tilesN;
@@ -374,13 +378,13 @@ __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_ge
   if (!PERSIST) {
     const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
     if (t >= tiles) return;
-    gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
+    gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, smem);
   } else {
     const int step = gridDim.x >> 3;
     for (int li = bid >> 3; li < per; li += step) {
       const int t = g.lowerOnly ? 8 * li + (bid & 7) : (bid & 7) * per + li;
       if (t >= tiles) break;
-      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK>(g, t, smem);
+      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, smem);
       // a next tile reuses the LDS ring: the tile's last k-step ended with a
       // barrier after its last LDS read, and the epilogue reads no LDS
     }
@@ -409,6 +413,15 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
       else
         hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK, true>), dim3(cap, 1, batch), dim3(256), 0,
                            s, p);
+      FROB_LAUNCH_CHECK();
+      return;
+    }
+  }
+  const bool plain = !p.triA && !p.triB && !p.A.rows && !p.B.rows && !p.C.rows && !p.C.cols;
+  if constexpr (BM == 128 && BN == 128) {
+    if (vec && plain) {
+      hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false, true>), dim3(grid, 1, batch), dim3(256),
+                         0, s, p);
       FROB_LAUNCH_CHECK();
       return;
     }
