@@ -714,10 +714,10 @@ BB_IN void wg_scatter_cols(int n, const T* src, const int* perm, T* dst) {
   bb_sync();
 }
 
-// a[j][i] = -a[i][j] above the diagonal (i > j), from the lower triangle (the
-// entries read and the entries written are disjoint)
+// a[j][i] = sign a[i][j] above the diagonal (i > j), from the lower triangle
+// (the entries read and the entries written are disjoint)
 template <typename T>
-BB_IN void wg_mirror_skew(int n, T* a) {
+BB_IN void wg_mirror(int n, T* a, T sign) {
   n = uni(n);
   const int total = n * n;
   for (int base = bb_tid(); base < total; base += SU * BT) {
@@ -730,7 +730,7 @@ BB_IN void wg_mirror_skew(int n, T* a) {
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int e = base + u * BT, i = e / n, j = e - i * n;
-      if (e < total && j < i) a[(long long)j * n + i] = -v[u];
+      if (e < total && j < i) a[(long long)j * n + i] = sign * v[u];
     }
   }
   bb_sync();
@@ -962,12 +962,16 @@ BB_IN void batched_worker(const BatchArgs& g, Smem<T>& sm, int block) {
       wg_gemm<T>(sm, n, n, n, T(-1), Cm, n, true, Cm, n, false, T(1), F, n, true);   // lower triangle only
       const int i2 = bb_first(wg_potrf<T>(sm, n, F, n, nb));
       if (!info) info = status_word(2, i2);
-      wg_identity<T>(n, Xr);                                            // Re X = R2^{-1} R2^{-T}
-      wg_trsm<T>(sm, 0, n, n, F, n, false, Xr, n, nb, true);           // R2^{-T}, lower triangular
-      wg_trsm<T>(sm, 1, n, n, F, n, false, Xr, n, nb);
+      // Re X = C^{-1} = R2^{-1} R2^{-T} = W^T W with W = R2^{-T} (lower
+      // triangular, a solve against the identity into Cm, whose X1 is no
+      // longer needed): one product for the lower triangle, mirrored
+      wg_identity<T>(n, Cm);
+      wg_trsm<T>(sm, 0, n, n, F, n, false, Cm, n, nb, true);
+      wg_gemm<T>(sm, n, n, n, T(1), Cm, n, true, Cm, n, false, T(0), Xr, n, true);
+      wg_mirror<T>(n, Xr, T(1));
       // Im X = -Y C^{-1} is skew (X is Hermitian): the lower triangle, mirrored
       wg_gemm<T>(sm, n, n, n, T(-1), Y, n, false, Xr, n, false, T(0), Xi, n, true);
-      wg_mirror_skew<T>(n, Xi);
+      wg_mirror<T>(n, Xi, T(-1));
     }
     if (tid == 0) g.info[mi] = info;
     bb_sync();
