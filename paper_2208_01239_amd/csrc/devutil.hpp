@@ -32,21 +32,28 @@ __device__ __forceinline__ int wave_max_key(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 // Exact argmax over the lanes in `cand` of (val desc, key asc); returns the
-// winning lane.  Rare path (several lanes share the FP32 maximum).
+// winning lane, the same in every lane.  Keys of candidates are distinct.
+// Called with the whole wave active when several lanes share the FP32
+// maximum: a butterfly of lane exchanges over (value, key, lane), so its cost
+// does not grow with the number of tied lanes (a wave of exactly-zero rows
+// ties on every lane).
 __device__ __forceinline__ int exact_argmax(unsigned long long cand, double val, int key) {
-  int wl = -1;
-  double bv = -1.0;
-  int bk = INT_MAX;
-  while (cand) {
-    const int l = __ffsll((long long)cand) - 1;
-    cand &= cand - 1;
-    const double lv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(val), l),
-                                       __builtin_amdgcn_readlane(__double2loint(val), l));
-    const int lk = __builtin_amdgcn_readlane(key, l);
-    if (lv > bv || (lv == bv && lk < bk)) { bv = lv; bk = lk; wl = l; }
+  const int lane = __lane_id();
+  const bool in = (cand >> lane) & 1ull;
+  double v = in ? val : -1.0;
+  int k = in ? key : INT_MAX;
+  int l = in ? lane : 64;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int ok = __shfl_xor(k, off);
+    const int ol = __shfl_xor(l, off);
+    const bool take = (ov > v) | ((ov == v) & (ok < k));
+    v = take ? ov : v;
+    k = take ? ok : k;
+    l = take ? ol : l;
   }
-  return wl;
+  return __builtin_amdgcn_readfirstlane(l);
 }
-
 
 }  // namespace frob

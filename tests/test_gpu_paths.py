@@ -1,7 +1,8 @@
 """GPU parity of paths that the basic size sweeps do not reach: stage-2 status
 codes (Lemma 2.3, Lemma 4.5), the shifted linear solve (Algorithms 3 and 6),
 the benchmarked refined configuration at n = 4096, determinism of the
-two-stream look-ahead, full-matrix parity at an order whose LU panels use the
+two-stream look-ahead, exact ties in the pivot search (a zero block),
+full-matrix parity at an order whose LU panels use the
 tallest fused leaves, a residual check of every 64-column band at full size,
 the Newton-Schulz convergence control on constructed starts, and the
 mixed-precision path at orders that take the look-ahead LU."""
@@ -219,6 +220,38 @@ def test_determinism_lookahead_n1300(h):
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a, b))
+
+
+# ------------------------------------------------------------------ exact ties in the pivot search
+def test_block_triangular_zero_block_n1100(h):
+    """A block upper-triangular M = [[M11, M12], [0, M22]] (the shape of the
+    Sylvester iteration's matrix): in the first half of the columns whole
+    waves of the LU leaves hold exactly-zero rows, so every lane of such a wave
+    ties in the FP32-keyed pivot search and the exact tie-break runs each
+    column.  Every entry of the inverse against the oracle: plain Frobenius at
+    16 u kappa_2(C), the complex-LU baseline at 16 u kappa_2(M)."""
+    import paper_2208_01239_amd as fi
+    n, p = 1100, 550
+    A11, B11 = inputs.general(p, 31)
+    A22, B22 = inputs.general(n - p, 32)
+    A12, B12 = inputs.general(p, 33)
+    A = np.block([[A11, A12[:, : n - p]], [np.zeros((n - p, p)), A22]])
+    B = np.block([[B11, B12[:, : n - p]], [np.zeros((n - p, p)), B22]])
+    Rr, Ri, info, _, _ = oracle.cinv_lu(A, B)
+    assert info == 0
+    dA, dB = to_dev(A), to_dev(B)
+    C = A + B @ np.linalg.solve(A, B)
+    tol0 = max(TOL, 16 * U64 * np.linalg.cond(C))
+    Xr, Xi, r = fi.frob_inv_general(h, dA, dB)
+    e0 = relF(to_host(Xr), to_host(Xi), Rr, Ri)
+    tolz = max(TOL, 16 * U64 * np.linalg.cond(A + 1j * B))
+    ez = []
+    for form in (1, 0):
+        Zr, Zi, _ = fi.frob_cinv_lu(h, dA, dB, form=form)
+        ez.append(relF(to_host(Zr), to_host(Zi), Rr, Ri))
+    print(f"block triangular n={n}: frobenius {e0:.2e} (tol {tol0:.1e}), complex LU {ez} (tol {tolz:.1e})")
+    assert r["shifts_tried"] == 0
+    assert e0 <= tol0 and max(ez) <= tolz
 
 
 # ------------------------------------------------------------------ full parity through the tallest fused leaves
