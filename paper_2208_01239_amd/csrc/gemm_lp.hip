@@ -13,9 +13,10 @@
 // 32.  A tile is read from HBM with one batch of unconditional loads at
 // clamped addresses (the next k-step's batch is in flight while the current
 // one is multiplied; row indices are fetched a k-step earlier still),
-// rounded, and written to LDS k-major, which is the
-// order the MFMA fragments read (16 consecutive lanes, 16 consecutive
-// floats).  Fragment layouts (lane l): A[l % 16][k] / B[k][l % 16] with
+// rounded, and written to LDS: FP32 k-major, the order the MFMA fragments
+// read (16 consecutive lanes, 16 consecutive floats); BF16 row by row with k
+// contiguous, so that each lane's eight values are one 16-byte read.
+// Fragment layouts (lane l): A[l % 16][k] / B[k][l % 16] with
 // k = l / 16 (FP32, one value) or k = 8 (l / 16) + 0..7 (BF16, eight values);
 // the 16x16 result holds D[4 (l / 16) + v][l % 16] in accumulator v.
 #include "common.hpp"
@@ -46,8 +47,15 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   constexpr int PA = BM + 4, PB = BN + 4;            // LDS row pitch (floats)
   constexpr int EA = BM * LBK / 256, EB = BN * LBK / 256;
   constexpr int FM = BM / 32, FN = BN / 32;          // 16x16 tiles per wave
-  __shared__ float As[LBK * PA];
-  __shared__ float Bs[LBK * PB];
+  // FP32 operands are staged k-major as floats; BF16 operands are converted
+  // once when staged and kept k-contiguous per row (pitch PH), so that a
+  // lane's fragment of eight consecutive k is one aligned 16-byte read
+  constexpr bool HB = MODE == LP_BF16;
+  constexpr int PH = LBK + 8;
+  __shared__ float As[HB ? 1 : LBK * PA];
+  __shared__ float Bs[HB ? 1 : LBK * PB];
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[HB ? BM * PH : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[HB ? BN * PH : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles = g.tilesM * g.tilesN;
   const int per = (tiles + 7) / 8;
@@ -135,7 +143,8 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
       int i, k;
       if (!TA) { i = e / LBK; k = e % LBK; } else { k = e / BM; i = e % BM; }
       const bool ok = bm0 + i < M && k0 + k < K;
-      As[k * PA + i] = ok ? (float)ra[u] : 0.0f;
+      if constexpr (HB) Ah[i * PH + k] = (__bf16)(ok ? (float)ra[u] : 0.0f);
+      else As[k * PA + i] = ok ? (float)ra[u] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
@@ -143,7 +152,8 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
       int k, j;
       if (!TB) { k = e / BN; j = e % BN; } else { j = e / LBK; k = e % LBK; }
       const bool ok = bn0 + j < N && k0 + k < K;
-      Bs[k * PB + j] = ok ? (float)rb[u] : 0.0f;
+      if constexpr (HB) Bh[j * PH + k] = (__bf16)(ok ? (float)rb[u] : 0.0f);
+      else Bs[k * PB + j] = ok ? (float)rb[u] : 0.0f;
     }
   };
 
@@ -181,15 +191,14 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
           for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
       }
     } else {
+      // lane l supplies A(l % 16, 8 (l / 16) + q) and B(8 (l / 16) + q, l % 16), q < 8
       bf16x8 fa[FM], fb[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) fa[a][q] = (__bf16)As[(8 * (lane >> 4) + q) * PA + wm0 + a * 16 + (lane & 15)];
+        fa[a] = *reinterpret_cast<const bf16x8*>(&Ah[(wm0 + a * 16 + (lane & 15)) * PH + 8 * (lane >> 4)]);
 #pragma unroll
       for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) fb[b][q] = (__bf16)Bs[(8 * (lane >> 4) + q) * PB + wn0 + b * 16 + (lane & 15)];
+        fb[b] = *reinterpret_cast<const bf16x8*>(&Bh[(wn0 + b * 16 + (lane & 15)) * PH + 8 * (lane >> 4)]);
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
