@@ -65,8 +65,10 @@ constexpr int gemm_min_blocks(int BM, int BN, int BK, bool TA, bool TB) {
 
 // One output tile t (an index in the XCD-contiguous, grouped order) of the
 // product; smem holds gemm_lds_bytes(BM, BN, BK, TA, TB) bytes.  PLAIN: no
-// triangular operand and no row or column indirection (known at compile time,
-// so the k-loop carries none of their masking and index loads).
+// triangular operand, no output indirection and no row indices on a k-band
+// operand (known at compile time, so the k-loop carries none of their masking
+// and index loads); row indices of a row-band operand (A untransposed, B
+// transposed) are looked up once per tile and stay allowed.
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PLAIN = false>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, double* __restrict__ smem) {
   constexpr int KP = BK / 2;       // 16-byte pairs per row of a row-band tile
@@ -102,8 +104,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
   const double* __restrict__ Ap = g.A.p + z * g.sA;
   const double* __restrict__ Bp = g.B.p + z * g.sB;
   double* __restrict__ Cp = g.C.p + z * g.sC;
-  const int* __restrict__ rA = !PLAIN && g.A.rows ? g.A.rows + z * g.rsA : nullptr;
-  const int* __restrict__ rB = !PLAIN && g.B.rows ? g.B.rows + z * g.rsB : nullptr;
+  const int* __restrict__ rA = (!PLAIN || !TA) && g.A.rows ? g.A.rows + z * g.rsA : nullptr;
+  const int* __restrict__ rB = (!PLAIN || TB) && g.B.rows ? g.B.rows + z * g.rsB : nullptr;
   const int* __restrict__ rC = !PLAIN && g.C.rows ? g.C.rows + z * g.rsC : nullptr;
   const int triA = PLAIN ? TRI_NONE : g.triA, triB = PLAIN ? TRI_NONE : g.triB;
   const int M = g.M, N = g.N;
@@ -417,7 +419,8 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
       return;
     }
   }
-  const bool plain = !p.triA && !p.triB && !p.A.rows && !p.B.rows && !p.C.rows && !p.C.cols;
+  const bool plain =
+      !p.triA && !p.triB && !p.C.rows && !p.C.cols && (TA ? !p.A.rows : true) && (TB ? true : !p.B.rows);
   if constexpr (BM == 128 && BN == 128) {
     if (vec && plain) {
       hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false, true>), dim3(grid, 1, batch), dim3(256),
