@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-newton", action="store_true", help="skip the sign / polar / Sylvester legs")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 2048-matrix batched leg with the default panel widths (for kernel profiles)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint leg (256 HPD matrices of order 256; for kernel profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -338,6 +340,10 @@ def main():
     if args.batched_only:
         h = fi.Handle(0)
         print(json.dumps(bench_batched(fi, inputs, h, torch, np, log, tune=False, loop=False)), flush=True)
+        return
+    if args.adjoint_only:
+        h = fi.Handle(0)
+        print(json.dumps(bench_adjoint(fi, inputs, h, torch, np, log)), flush=True)
         return
 
     n, K, W = args.n, args.steps, args.warmup

@@ -28,15 +28,24 @@ __global__ void k_axpy_flat(long long count, const T* __restrict__ x, double s, 
   if (i < count) out[i] = (T)((double)x[i] + s * (double)y[i]);
 }
 
-// (a, b, w) = (M1, M2, M3)  ->  re = sg (M1 - M2 + M3), im = sg (M2 + M3)
+// (a, b, w) = (M1, M2, M3)  ->  a = re = sg (M1 - M2 + M3), im = sg (M2 + M3)
+// written to `im` (b or w: each element is read before it is written).  With
+// d1, d2: also the factors of the next product's M1, d1 = xr + xi and
+// d2 = re + im (from the stored, rounded re and im).
 template <typename T>
-__global__ void k_combine3m(long long count, T* __restrict__ a, T* __restrict__ b, const T* __restrict__ w,
-                            double sg) {
+__global__ void k_combine3m(long long count, T* a, T* b, const T* w, T* im, double sg, const T* xr, const T* xi,
+                            T* d1, T* d2) {
   const long long i = (long long)blockIdx.x * AB + threadIdx.x;
   if (i >= count) return;
   const double m1 = a[i], m2 = b[i], m3 = w[i];
-  a[i] = (T)(sg * (m1 - m2 + m3));
-  b[i] = (T)(sg * (m2 + m3));
+  const T re = (T)(sg * (m1 - m2 + m3));
+  const T ie = (T)(sg * (m2 + m3));
+  a[i] = re;
+  im[i] = ie;
+  if (d1) {
+    d1[i] = (T)((double)xr[i] + (double)xi[i]);
+    d2[i] = (T)((double)re + (double)ie);
+  }
 }
 
 template <typename T>
@@ -45,8 +54,10 @@ void axpy_flat(hipStream_t s, long long count, const T* x, double sc, const T* y
   FROB_LAUNCH_CHECK();
 }
 template <typename T>
-void combine3m(hipStream_t s, long long count, T* a, T* b, const T* w, double sg) {
-  hipLaunchKernelGGL(k_combine3m<T>, dim3((unsigned)((count + AB - 1) / AB)), dim3(AB), 0, s, count, a, b, w, sg);
+void combine3m(hipStream_t s, long long count, T* a, T* b, const T* w, T* im, double sg, const T* xr = nullptr,
+               const T* xi = nullptr, T* d1 = nullptr, T* d2 = nullptr) {
+  hipLaunchKernelGGL(k_combine3m<T>, dim3((unsigned)((count + AB - 1) / AB)), dim3(AB), 0, s, count, a, b, w, im, sg,
+                     xr, xi, d1, d2);
   FROB_LAUNCH_CHECK();
 }
 
@@ -75,20 +86,15 @@ void adjoint_t(hipStream_t s, int batch, int n, const T* Xr, const T* Xi, const 
   bgemm(s, false, true, n, batch, 1.0, D1, D2, dMr);
   bgemm(s, false, true, n, batch, -1.0, Gr, Xi, dMi);
   bgemm(s, false, true, n, batch, 1.0, Gi, Xr, W);
-  combine3m(s, cnt, dMr, dMi, W, 1.0);
   // dM = -X^H T:  P = Xr^T, Q = -Xi^T, R = Tr, S = Ti
   //   M1 = (Xr + Xi)^T (Tr + Ti),  M2 = Xr^T Ti,  M3 = -Xi^T Tr
-  axpy_flat(s, cnt, Xr, 1.0, Xi, D1);
-  axpy_flat(s, cnt, (const T*)dMr, 1.0, (const T*)dMi, D2);
+  // (T into dMr, dMi and the factors of M1 into D1, D2 in one pass)
+  combine3m(s, cnt, dMr, dMi, W, dMi, 1.0, Xr, Xi, D1, D2);
   bgemm(s, true, false, n, batch, 1.0, Xr, dMi, W);          // M2 (reads Ti before it is overwritten)
   bgemm(s, true, false, n, batch, -1.0, Xi, dMr, dMi);       // M3 -> dMi (Tr still intact)
   bgemm(s, true, false, n, batch, 1.0, D1, D2, dMr);         // M1 -> dMr
-  // (dMr, W, dMi) = (M1, M2, M3): re = -(M1 - M2 + M3), im = -(M2 + M3)
-  combine3m(s, cnt, dMr, W, dMi, -1.0);
-  // combine3m wrote the imaginary part into W; move it into dMi
-  hipLaunchKernelGGL(k_axpy_flat<T>, dim3((unsigned)((cnt + AB - 1) / AB)), dim3(AB), 0, s, cnt, (const T*)W, 0.0,
-                     (const T*)W, dMi);
-  FROB_LAUNCH_CHECK();
+  // (dMr, W, dMi) = (M1, M2, M3): re = -(M1 - M2 + M3) -> dMr, im = -(M2 + M3) -> dMi
+  combine3m(s, cnt, dMr, W, (const T*)dMi, dMi, -1.0);
 }
 
 }  // namespace

@@ -40,6 +40,7 @@ struct GemmF64Params {
   long long sA, sB, sC;      // batch strides of the data pointers
   int rsA, rsB, rsC;         // batch strides of the row-index pointers
   int tilesM, tilesN;
+  int flat;                  // > 0: that many batch entries folded into blockIdx.x (else batch on blockIdx.z)
 };
 
 __device__ __forceinline__ double tri_mask(double v, int tri, int r, int c) {
@@ -70,7 +71,7 @@ constexpr int gemm_min_blocks(int BM, int BN, int BK, bool TA, bool TB) {
 // and index loads); row indices of a row-band operand (A untransposed, B
 // transposed) are looked up once per tile and stay allowed.
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, int BK, bool PLAIN = false>
-__device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, double* __restrict__ smem) {
+__device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, int zb, double* __restrict__ smem) {
   constexpr int KP = BK / 2;       // 16-byte pairs per row of a row-band tile
   constexpr int RP = 256 / KP;     // rows of a row-band tile per pass
   constexpr int FM = BM / WM / 16;
@@ -100,7 +101,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Params& g, int t, dou
   const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
 
-  const long long z = blockIdx.z;
+  const long long z = zb;
   const double* __restrict__ Ap = g.A.p + z * g.sA;
   const double* __restrict__ Bp = g.B.p + z * g.sB;
   double* __restrict__ Cp = g.C.p + z * g.sC;
@@ -378,15 +379,25 @@ __global__ __launch_bounds__(256, gemm_min_blocks(BM, BN, BK, TA, TB)) void k_ge
   // tile-row x of every group instead (all its columns, so its A rows stay
   // in its L2), and the live tiles spread evenly.
   if (!PERSIST) {
+    if (g.flat > 0) {
+      // a batch folded into blockIdx.x: XCD-contiguous ranges of (batch
+      // entry, tile) items, so a batch of small products fills every XCD
+      const int items = tiles * g.flat;
+      const int pi = (items + 7) / 8;
+      const int wi = (bid & 7) * pi + (bid >> 3);
+      if (wi >= items) return;
+      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, wi % tiles, wi / tiles, smem);
+      return;
+    }
     const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
     if (t >= tiles) return;
-    gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, smem);
+    gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, blockIdx.z, smem);
   } else {
     const int step = gridDim.x >> 3;
     for (int li = bid >> 3; li < per; li += step) {
       const int t = g.lowerOnly ? 8 * li + (bid & 7) : (bid & 7) * per + li;
       if (t >= tiles) break;
-      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, smem);
+      gemm_f64_tile<BM, BN, WM, WN, TA, TB, VEC, BK, PLAIN>(g, t, blockIdx.z, smem);
       // a next tile reuses the LDS ring: the tile's last k-step ended with a
       // barrier after its last LDS read, and the epilogue reads no LDS
     }
@@ -398,6 +409,7 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
   GemmF64Params p = p0;
   p.tilesM = ceil_div(p.M, BM);
   p.tilesN = ceil_div(p.N, BN);
+  p.flat = 0;
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
   // capped grids for the untransposed products (the factorizations' updates)
@@ -419,21 +431,22 @@ static void launch_cfg(const GemmF64Params& p0, int batch, hipStream_t s) {
       return;
     }
   }
+  // a batch of more than one entry (not lower-only) is folded into blockIdx.x
+  if (batch > 1 && !p.lowerOnly) p.flat = batch;
+  const dim3 gd = p.flat > 0 ? dim3(8 * ((tiles * batch + 7) / 8), 1, 1) : dim3(grid, 1, batch);
   const bool plain =
       !p.triA && !p.triB && !p.C.rows && !p.C.cols && (TA ? !p.A.rows : true) && (TB ? true : !p.B.rows);
   if constexpr (BM == 128 && BN == 128) {
     if (vec && plain) {
-      hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false, true>), dim3(grid, 1, batch), dim3(256),
-                         0, s, p);
+      hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false, true>), gd, dim3(256), 0, s, p);
       FROB_LAUNCH_CHECK();
       return;
     }
   }
   if (vec)
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, true, BK, false>), gd, dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK, false>), dim3(grid, 1, batch), dim3(256), 0, s,
-                       p);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, false, BK, false>), gd, dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -500,7 +513,12 @@ void gemm_f64_batched(hipStream_t s, bool ta, bool tb, int M, int N, int K, doub
   p.vecB = aligned16(B.p) && (B.ld % 2 == 0) && (sB % 2 == 0) && ((tb ? K : N) % 2 == 0);
   p.sA = sA; p.sB = sB; p.sC = sC;
   p.rsA = rsA; p.rsB = rsB; p.rsC = rsC;
-  const int cfg = gemm_pick_cfg(M, N, need);
+  int cfg = gemm_pick_cfg(M, N, need);
+  // a large batch of small products takes the big tile (its k-loop runs at
+  // the better matrix-core rate) once the batch gives it 1024 tiles
+  if (batch > 1 && !lowerOnly && need == GEMM_NEED_ANY && cfg == GEMM_CFG_64x64 && M >= 128 && N >= 128 &&
+      (long long)ceil_div(M, 128) * ceil_div(N, 128) * batch >= 1024)
+    cfg = GEMM_CFG_128x128;
   if (!ta && !tb) launch_pick<false, false>(p, batch, cfg, s);
   else if (!ta && tb) launch_pick<false, true>(p, batch, cfg, s);
   else if (ta && !tb) launch_pick<true, false>(p, batch, cfg, s);

@@ -38,6 +38,7 @@ struct GemmLpParams {
   long long sA, sB, sC;   // batch strides of the data pointers
   int lowerOnly;
   int tilesM, tilesN;
+  int flat;               // > 0: that many batch entries folded into blockIdx.x (else batch on blockIdx.z)
 };
 
 constexpr int LBK = 32;
@@ -58,12 +59,16 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   __shared__ __attribute__((aligned(16))) __bf16 Bh[HB ? BN * PH : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles = g.tilesM * g.tilesN;
-  const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
-  // XCD-contiguous ranges of tile indices; interleaved for lower-only products
-  // (the idle tiles above the diagonal would otherwise leave whole XCDs idle)
-  const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
-  if (t >= tiles) return;
+  // XCD-contiguous ranges of work items (a tile of a batch entry, the entries
+  // folded in when g.flat > 0, so that every XCD gets its share of a batch of
+  // small products); interleaved tiles for lower-only products (the idle
+  // tiles above the diagonal would otherwise leave whole XCDs idle)
+  const int items = g.flat > 0 ? tiles * g.flat : tiles;
+  const int per = (items + 7) / 8;
+  const int wi = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
+  if (wi >= items) return;
+  const int t = g.flat > 0 ? wi % tiles : wi;
   // tile indices run through groups of eight tile-rows column by column
   const int gsz = 8 * g.tilesN;
   const int grp = t / gsz;
@@ -72,7 +77,7 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64) ? 1 : 2) void k_gemm_lp(Ge
   const int bm0 = (grp * 8 + wt % gh) * BM;
   const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
-  const int z = blockIdx.z;
+  const int z = g.flat > 0 ? wi / tiles : (int)blockIdx.z;
   const TS* Ap = g.A + z * g.sA;
   const TS* Bp = g.B + z * g.sB;
   TS* Cp = g.C + z * g.sC;
@@ -261,12 +266,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lp32(GemmLpParams<TS> g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles = g.tilesM * g.tilesN;
-  const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
-  // XCD-contiguous ranges of tile indices; interleaved for lower-only products
-  // (the idle tiles above the diagonal would otherwise leave whole XCDs idle)
-  const int t = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
-  if (t >= tiles) return;
+  // XCD-contiguous ranges of work items (a tile of a batch entry, the entries
+  // folded in when g.flat > 0, so that every XCD gets its share of a batch of
+  // small products); interleaved tiles for lower-only products (the idle
+  // tiles above the diagonal would otherwise leave whole XCDs idle)
+  const int items = g.flat > 0 ? tiles * g.flat : tiles;
+  const int per = (items + 7) / 8;
+  const int wi = g.lowerOnly ? bid : (bid & 7) * per + (bid >> 3);
+  if (wi >= items) return;
+  const int t = g.flat > 0 ? wi % tiles : wi;
   const int gsz = 8 * g.tilesN;
   const int grp = t / gsz;
   const int gh = min(8, g.tilesM - grp * 8);
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lp32(GemmLpParams<TS> g) {
   const int bm0 = (grp * 8 + wt % gh) * BM;
   const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
-  const int z = blockIdx.z;
+  const int z = g.flat > 0 ? wi / tiles : (int)blockIdx.z;
   const TS* Ap = g.A + z * g.sA;
   const TS* Bp = g.B + z * g.sB;
   TS* Cp = g.C + z * g.sC;
@@ -479,16 +488,24 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lp32(GemmLpParams<TS> g) {
   }
 }
 
+// A batch of more than one entry (not lower-only) is folded into blockIdx.x;
+// returns the grid's z extent.
+template <typename TS>
+int flat_batch(GemmLpParams<TS>& p, int batch) {
+  p.flat = (batch > 1 && !p.lowerOnly) ? batch : 0;
+  return p.flat > 0 ? 1 : batch;
+}
+
 template <typename TS, int BM, int BN, bool TA, bool TB>
 void launch_lp32(GemmLpParams<TS> p, int batch, hipStream_t s, bool vec) {
   p.tilesM = ceil_div(p.M, BM);
   p.tilesN = ceil_div(p.N, BN);
-  const int tiles = p.tilesM * p.tilesN;
-  const int grid = 8 * ((tiles + 7) / 8);
+  const int gz = flat_batch(p, batch);
+  const int grid = 8 * ((p.tilesM * p.tilesN * (p.flat > 0 ? p.flat : 1) + 7) / 8);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, true>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, true>), dim3(grid, 1, gz), dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_lp32<TS, BM, BN, TA, TB, false>), dim3(grid, 1, gz), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -496,9 +513,9 @@ template <typename TS, int MODE, int BM, int BN, bool TA, bool TB>
 void launch_lp(GemmLpParams<TS> p, int batch, hipStream_t s) {
   p.tilesM = ceil_div(p.M, BM);
   p.tilesN = ceil_div(p.N, BN);
-  const int tiles = p.tilesM * p.tilesN;
-  const int grid = 8 * ((tiles + 7) / 8);
-  hipLaunchKernelGGL((k_gemm_lp<TS, MODE, BM, BN, TA, TB>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+  const int gz = flat_batch(p, batch);
+  const int grid = 8 * ((p.tilesM * p.tilesN * (p.flat > 0 ? p.flat : 1) + 7) / 8);
+  hipLaunchKernelGGL((k_gemm_lp<TS, MODE, BM, BN, TA, TB>), dim3(grid, 1, gz), dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
@@ -536,6 +553,7 @@ void gemm_lp_t(hipStream_t s, int mode, bool ta, bool tb, int M, int N, int K, d
   p.sA = sA; p.sB = sB; p.sC = sC;
   p.lowerOnly = lowerOnly ? 1 : 0;
   p.tilesM = p.tilesN = 0;
+  p.flat = 0;
   if (mode == LP_F32) {
     if (!ta && !tb) pick_lp<TS, LP_F32, false, false>(p, batch, s);
     else if (!ta && tb) pick_lp<TS, LP_F32, false, true>(p, batch, s);
