@@ -5,8 +5,9 @@
 // with optional row indirection on A, B and C, an optional column scatter on
 // C, triangular interpretation of op(A)/op(B) (entries outside the triangle
 // read as zero and the k range is clipped to the triangle, a unit diagonal
-// reads as one), a lower-triangle-only output mode, and a batch index on
-// blockIdx.z.  This one kernel serves the trailing updates of the
+// reads as one), a lower-triangle-only output mode, and a batch index
+// (folded into blockIdx.x with the tile index; on blockIdx.z for
+// lower-triangle-only and capped launches).  This one kernel serves the trailing updates of the
 // factorizations (row-indirect NN), the triangular solves and inverses
 // (trmm-like products), the symmetric rank-k updates (lower-only), and the
 // plain products B*Y and -Y*C^{-1}.

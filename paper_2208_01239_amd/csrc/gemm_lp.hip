@@ -7,7 +7,8 @@
 // Storage is FP64 (the mixed-precision factorization: working matrices stay
 // FP64 in HBM, only the MFMA operands are rounded) or FP32 (the batched
 // adjoint).  Row indirection on A, B and C, a lower-triangle-only output mode
-// and a batch index on blockIdx.z follow the FP64 GEMM's conventions.
+// and the batch index (folded into blockIdx.x except for lower-triangle-only
+// products) follow the FP64 GEMM's conventions.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, block tile BM x BN, k-step
 // 32.  A tile is read from HBM with one batch of unconditional loads at

@@ -29,6 +29,7 @@ struct GemmZ64Params {
   long long sA, sB, sC;      // batch strides (both planes)
   int rsA, rsB, rsC;         // batch strides of the row-index pointers
   int tilesM, tilesN;
+  int flat;                  // > 0: that many batch entries folded into blockIdx.x (else batch on blockIdx.z)
 };
 
 __device__ __forceinline__ void ztri_mask(double& re, double& im, int tri, int r, int c) {
@@ -48,7 +49,7 @@ constexpr int zgemm_lds_doubles(int BM, int BN, int BK, bool TA, bool TB) {
 
 // One output tile t (an index in the XCD-contiguous, grouped order).
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC>
-__device__ __forceinline__ void gemm_z64_tile(const GemmZ64Params& g, int t, double* __restrict__ smem) {
+__device__ __forceinline__ void gemm_z64_tile(const GemmZ64Params& g, int t, int zb, double* __restrict__ smem) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
@@ -76,7 +77,7 @@ __device__ __forceinline__ void gemm_z64_tile(const GemmZ64Params& g, int t, dou
   const int bn0 = (wt / gh) * BN;
   if (g.lowerOnly && bn0 > bm0 + BM - 1) return;
 
-  const long long z = blockIdx.z;
+  const long long z = zb;
   const double* __restrict__ Ar = g.A.re + z * g.sA;
   const double* __restrict__ Ai = g.A.im + z * g.sA;
   const double* __restrict__ Br = g.B.re + z * g.sB;
@@ -361,8 +362,9 @@ __device__ __forceinline__ void gemm_z64_tile(const GemmZ64Params& g, int t, dou
 }
 
 // Block b works on XCD b % 8 in that XCD's contiguous range of tile indices,
-// one tile per block; PERSIST: a capped grid (GridCapScope, as in the real
-// GEMM) whose blocks take several tiles.
+// one tile per block (with g.flat > 0, of (batch entry, tile) items, so that
+// a batch of small products fills every XCD); PERSIST: a capped grid
+// (GridCapScope, as in the real GEMM) whose blocks take several tiles.
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool VEC, bool PERSIST>
 __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   __shared__ __attribute__((aligned(16))) double smem[zgemm_lds_doubles(BM, BN, 16, TA, TB)];
@@ -370,15 +372,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_z64(GemmZ64Params g) {
   const int per = (tiles + 7) / 8;
   const int bid = blockIdx.x;
   if (!PERSIST) {
+    if (g.flat > 0) {
+      const int items = tiles * g.flat;
+      const int pi = (items + 7) / 8;
+      const int wi = (bid & 7) * pi + (bid >> 3);
+      if (wi >= items) return;
+      gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, wi % tiles, wi / tiles, smem);
+      return;
+    }
     const int t = (bid & 7) * per + (bid >> 3);
     if (t >= tiles) return;
-    gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, smem);
+    gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, blockIdx.z, smem);
   } else {
     const int step = gridDim.x >> 3;
     for (int li = bid >> 3; li < per; li += step) {
       const int t = (bid & 7) * per + li;
       if (t >= tiles) break;
-      gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, smem);
+      gemm_z64_tile<BM, BN, WM, WN, TA, TB, VEC>(g, t, blockIdx.z, smem);
       // the tile's last k-step ended with a barrier; the epilogue reads no LDS
     }
   }
@@ -389,6 +399,7 @@ static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
   GemmZ64Params p = p0;
   p.tilesM = ceil_div(p.M, BM);
   p.tilesN = ceil_div(p.N, BN);
+  p.flat = 0;
   const int tiles = p.tilesM * p.tilesN;
   const int grid = 8 * ((tiles + 7) / 8);
   const bool vec = p.vecA && p.vecB;
@@ -404,10 +415,13 @@ static void launch_cfg_z(const GemmZ64Params& p0, int batch, hipStream_t s) {
       return;
     }
   }
+  // a batch of more than one entry (not lower-only) is folded into blockIdx.x
+  if (batch > 1 && !p.lowerOnly) p.flat = batch;
+  const dim3 gd = p.flat > 0 ? dim3(8 * ((tiles * batch + 7) / 8), 1, 1) : dim3(grid, 1, batch);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, true, false>), gd, dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false, false>), dim3(grid, 1, batch), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_z64<BM, BN, WM, WN, TA, TB, false, false>), gd, dim3(256), 0, s, p);
   FROB_LAUNCH_CHECK();
 }
 
