@@ -64,6 +64,28 @@ def test_adjoint_fp32_matches_oracle(h, n, batch):
         assert e <= tol
 
 
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_adjoint_large_batch_sampled_entries(h, dtype_name):
+    """A batch large enough for the batched products' big tile: 256 entries of
+    order 200 give 1024 tiles of 128 x 128, ragged in both directions, with
+    the batch folded into the grid's x axis so the entries spread over every
+    XCD.  Sampled entries (the first two, a middle one, the last two) against
+    the oracle, at the tolerances of the tests above."""
+    import torch
+    dtype = getattr(torch, dtype_name)
+    n, batch = 200, 256
+    Xr, Xi, Gr, Gi = _rand(batch, n, 900)
+    if dtype == torch.float32:
+        Xr, Xi, Gr, Gi = [a.astype(np.float32).astype(np.float64) for a in (Xr, Xi, Gr, Gi)]
+    dMr, dMi = _gpu_adjoint(h, Xr, Xi, Gr, Gi, dtype)
+    tol = 1e-12 if dtype == torch.float64 else 8 * n * U32
+    for b in (0, 1, 127, 254, 255):
+        Rr, Ri = oracle.adjoint(Xr[b], Xi[b], Gr[b], Gi[b])
+        e = relF(dMr[b], dMi[b], Rr, Ri)
+        print(f"{dtype_name} b={b}: adjoint relF {e:.2e} (tol {tol:.1e})")
+        assert e <= tol, (b, e)
+
+
 def _loss(h, A, B, Wr, Wi, hpd):
     """L = Re tr(W X) with X = (A + iB)^{-1} from the GPU inversion (FP64)."""
     import torch
